@@ -1,0 +1,151 @@
+/*
+ * micx.h -- C ABI of the MI355X (gfx950) engine for the MINE statistics.
+ *
+ * The engine computes, for pairs of variables, the approximate
+ * characteristic matrix M of the MINE family and the four statistics MIC,
+ * MAS, MEV and MCN derived from it, following Albanese et al. 2012 ("minerva
+ * and minepy: a C engine for the MINE suite", arXiv:1208.4271): its
+ * Appendix A (implementation details, items 1-10), Algorithm 1
+ * (GetClumpsPartition), Algorithm 2 (GetSuperclumpsPartition) and Sec. 2C
+ * (grid bound B(n) = n^alpha).  The paper's engine exposes a dataset
+ * structure, a parameter structure (alpha, c) and a returned score
+ * structure from which four functions compute the statistics (Sec. 2,
+ * "The MINE C engine and its wrappers"); this header keeps that shape and
+ * adds an all-pairs call on an m x n matrix held in device memory.
+ *
+ * Every step of the computation runs in HIP kernels on the GPU.  Host code
+ * only validates arguments, sizes the workspace and launches kernels.
+ *
+ * Conventions
+ *  - Return codes: MICX_OK (0) or a negative MICX_E* code; micx_strerror()
+ *    gives its message.  On error, outputs are left untouched.
+ *  - Grid bound: B = floor(pow(n, alpha)) evaluated in FP64 on the host;
+ *    cells (x, y) obey x, y >= 2 and x*y <= B (Appendix A item 1).  W =
+ *    floor(B/2) - 1 is the side of the dense matrix layout used below.
+ *  - Matrix layout: M[(y-2)*W + (x-2)] = M_{x,y}, the score of grids with x
+ *    bins of the FIRST variable and y bins of the SECOND; entries with
+ *    x*y > B are NaN.
+ *  - Statistics: MIC = max M; MAS = max |M_{x,y} - M_{y,x}|; MEV = max of
+ *    M over x = 2 or y = 2; MCN = min log2(x*y) over cells with
+ *    M >= (1-eps) MIC (Appendix A item 2 sets eps = 0 and log base 2; the
+ *    engine compares with an absolute slack of 1e-12).
+ *  - Sample size: 2 <= n <= MICX_MAX_N.  Values must be finite.
+ *  - Device: every call runs on the device the context was created for.
+ */
+#ifndef MICX_H
+#define MICX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define MICX_OK           0
+#define MICX_EINVAL      -1   /* bad argument: alpha not in (0,1], c <= 0, null pointer, m < 2, n < 2, bad dtype/mode */
+#define MICX_ESMALLN     -2   /* floor(n^alpha) < 4: no grid cell exists */
+#define MICX_ENONFINITE  -3   /* NaN or infinity in the input */
+#define MICX_ENOMEM      -4   /* device or host allocation failed */
+#define MICX_EDEVICE     -5   /* HIP runtime error or device status word set */
+#define MICX_ETOOBIG     -6   /* n > MICX_MAX_N */
+
+/* Largest sample size: ranking sorts one variable inside one workgroup's LDS. */
+#define MICX_MAX_N 8192
+
+/* Element types of input matrices. */
+#define MICX_F32 0
+#define MICX_F64 1
+#define MICX_I32 2
+
+/* Numeric forms of the dynamic program (integer stages are identical). */
+#define MICX_MODE_FP64         0   /* DP in FP64 */
+#define MICX_MODE_FP32_RECHECK 1   /* DP in FP32, chosen grids re-scored in FP64, near ties re-run in FP64 */
+
+/* Opaque context: device, workspace, cached tables. */
+typedef struct micx_ctx micx_ctx;
+
+/* Score of one pair: the characteristic matrix (the paper's score structure). */
+typedef struct {
+    int n;            /* sample size */
+    int B;            /* grid bound floor(n^alpha) */
+    int W;            /* matrix side, floor(B/2) - 1 */
+    double *M;        /* W*W doubles, M[(y-2)*W + (x-2)] = M_{x,y}; NaN where x*y > B */
+    double *Axy;      /* W*W: first variable into l columns (DP), second equipartitioned into r rows: Axy[(r-2)*W + (l-2)] */
+    double *Ayx;      /* W*W: second variable into l columns (DP), first equipartitioned into r rows */
+    double stats[4];  /* MIC, MAS, MEV, MCN (eps = 0), computed on the device */
+} micx_score;
+
+/* Create a context on HIP device `device`.  *ctx receives the handle. */
+int micx_ctx_create(micx_ctx **ctx, int device);
+
+/* Release a context and its workspace.  NULL is ignored. */
+void micx_ctx_destroy(micx_ctx *ctx);
+
+/* Parameter check (the paper's MINE(alpha, c) rejects bad values with a
+ * message).  Returns NULL when 0 < alpha <= 1 and c > 0, else a static
+ * message. */
+const char *micx_check_param(double alpha, double c);
+
+/* Grid bound floor(pow(n, alpha)) in FP64 (Sec. 2C; Appendix A item 1). */
+int micx_grid_bound(int n, double alpha);
+
+/* Score of one pair (the paper's mine_compute_score).
+ * x, y: HOST arrays of n doubles.  mode: MICX_MODE_*.
+ * *out receives a newly allocated score owned by the caller; release it
+ * with micx_free_score().  Synchronous. */
+int micx_compute_score(micx_ctx *ctx, const double *x, const double *y, int n,
+                       double alpha, double c, int mode, micx_score **out);
+
+/* The four statistics of a score (the paper's four statistic functions). */
+double micx_mic(const micx_score *s);
+double micx_mas(const micx_score *s);
+double micx_mev(const micx_score *s);
+double micx_mcn(const micx_score *s, double eps);
+
+/* Free a score returned by micx_compute_score().  NULL is ignored. */
+void micx_free_score(micx_score *s);
+
+/* All pairs of rows of X.
+ * X_dev: DEVICE pointer to an m x n row-major matrix (one variable per row,
+ *        n samples contiguous) of element type dtype (MICX_F32/F64/I32);
+ *        owned by the caller, read only.
+ * out_dev: DEVICE pointer to m(m-1)/2 * 4 doubles owned by the caller; pair
+ *        (i < j) is written at index p = i*m - i*(i+1)/2 + (j-i-1) as
+ *        (MIC, MAS, MEV, MCN), with the first variable i and the second j.
+ * stream: hipStream_t (as void*), or NULL for the null stream.  Kernels are
+ *        queued on it; the call returns after the work completes (it reads
+ *        back the device status word).
+ * mode: MICX_MODE_*. */
+int micx_allpairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n,
+                  double alpha, double c, int mode, double *out_dev, void *stream);
+
+/* Listed pairs of rows of X (the paper's "master variable" and single-pair
+ * modes are lists of this kind).
+ * pairs_host: HOST array of npairs (i, j) int32 index pairs, 0 <= i, j < m,
+ *        i != j; out_dev: DEVICE pointer to npairs * 4 doubles, pair k
+ *        written at 4k as (MIC, MAS, MEV, MCN) with i the first variable. */
+int micx_pairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n,
+               const int32_t *pairs_host, int64_t npairs,
+               double alpha, double c, int mode, double *out_dev, void *stream);
+
+/* Integer stages of one item, read back for bit-exact tests.
+ * x, y: HOST arrays of n doubles.  orient 0: columns from x, rows from y;
+ * orient 1: swapped.  ry: requested row count, 2 <= ry <= floor(B/2).
+ * Outputs (host): *yhat rows produced; row_starts[0..yhat] positions (in
+ * the row variable's sorted order) where each row starts, then n (caller
+ * provides ry+1 ints); *k clumps; *K (super)clumps; ends[0..K-1] number of
+ * points, in the column variable's order, up to and including each
+ * (super)clump (caller provides n ints). */
+int micx_debug_item(micx_ctx *ctx, const double *x, const double *y, int n,
+                    double alpha, double c, int orient, int ry,
+                    int *yhat, int *row_starts, int *k, int *K, int *ends);
+
+/* Message for a return code (static string). */
+const char *micx_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MICX_H */

@@ -170,10 +170,11 @@ int oracle_superclumps(const double *a, const int *q, int n, int khat, int flags
 }
 
 /* Superclump bound for cx columns: khat = floor(c * cx) (Algorithm 2's     */
-/* \hat{k} = cx, App. A items 6-7).                                         */
+/* \hat{k} = cx, App. A items 6-7), at least 1 so that c < 1/2 stays valid. */
 static int khat_of(double c, int cx)
 {
-    return (int) floor(c * (double) cx);
+    int k = (int) floor(c * (double) cx);
+    return k < 1 ? 1 : k;
 }
 
 /* ---------------------------------------------------------------------- */
@@ -460,8 +461,9 @@ int oracle_item(const double *x, const double *y, int n, double alpha, double c,
     *yhat = yh;
     int r = 0;
     row_starts[0] = 0;
-    for (int i = 1; i < n; i++) if (qv[i] != qv[i - 1]) row_starts[++r] = i;
-    row_starts[yh] = n;
+    for (int i = 1; i < n; i++)
+        if (qv[i] != qv[i - 1] && r + 1 <= ry) row_starts[++r] = i;
+    row_starts[yh <= ry ? yh : ry] = n;
     for (int i = 0; i < n; i++) rowpt[ov[i]] = qv[i];
     for (int i = 0; i < n; i++) qu[i] = rowpt[ou[i]];
     int kk = 0;

@@ -1,0 +1,227 @@
+"""Python binding of the micx C ABI (include/micx.h): MINE statistics on MI355X.
+
+Argument marshalling only.  Every step of the computation runs in the HIP
+kernels of ``libmicx.so``; PyTorch supplies device memory and streams.  There
+is no CPU fallback: importing works without the library, but every call
+raises if ``libmicx.so`` has not been built (``python -m
+paper_1208_4271_amd._build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmicx.so")
+
+MICX_OK = 0
+MICX_EINVAL = -1
+MICX_ESMALLN = -2
+MICX_ENONFINITE = -3
+MICX_ENOMEM = -4
+MICX_EDEVICE = -5
+MICX_ETOOBIG = -6
+MAX_N = 8192
+
+F32, F64, I32 = 0, 1, 2
+MODE_FP64 = 0
+MODE_FP32_RECHECK = 1
+
+# Every symbol declared in include/micx.h.
+EXPORTS = (
+    "micx_ctx_create", "micx_ctx_destroy", "micx_check_param", "micx_grid_bound",
+    "micx_compute_score", "micx_mic", "micx_mas", "micx_mev", "micx_mcn", "micx_free_score",
+    "micx_allpairs", "micx_pairs", "micx_debug_item", "micx_strerror",
+)
+
+
+class MicxError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__("%s: %s (code %d)" % (where, strerror(code), code))
+
+
+class _Score(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("B", ctypes.c_int), ("W", ctypes.c_int),
+                ("M", ctypes.POINTER(ctypes.c_double)), ("Axy", ctypes.POINTER(ctypes.c_double)),
+                ("Ayx", ctypes.POINTER(ctypes.c_double)), ("stats", ctypes.c_double * 4)]
+
+
+_lib = None
+_ctxs = {}
+
+
+def load_library():
+    """Load libmicx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libmicx.so is not built: run `python -m paper_1208_4271_amd._build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    dp, ip, vp = P(ctypes.c_double), P(ctypes.c_int), ctypes.c_void_p
+    lib.micx_ctx_create.argtypes = [P(vp), ctypes.c_int]
+    lib.micx_ctx_create.restype = ctypes.c_int
+    lib.micx_ctx_destroy.argtypes = [vp]
+    lib.micx_ctx_destroy.restype = None
+    lib.micx_check_param.argtypes = [ctypes.c_double, ctypes.c_double]
+    lib.micx_check_param.restype = ctypes.c_char_p
+    lib.micx_grid_bound.argtypes = [ctypes.c_int, ctypes.c_double]
+    lib.micx_grid_bound.restype = ctypes.c_int
+    lib.micx_compute_score.argtypes = [vp, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_int, P(P(_Score))]
+    lib.micx_compute_score.restype = ctypes.c_int
+    for f in ("micx_mic", "micx_mas", "micx_mev"):
+        getattr(lib, f).argtypes = [P(_Score)]
+        getattr(lib, f).restype = ctypes.c_double
+    lib.micx_mcn.argtypes = [P(_Score), ctypes.c_double]
+    lib.micx_mcn.restype = ctypes.c_double
+    lib.micx_free_score.argtypes = [P(_Score)]
+    lib.micx_free_score.restype = None
+    lib.micx_allpairs.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_int, vp, vp]
+    lib.micx_allpairs.restype = ctypes.c_int
+    lib.micx_pairs.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_int32),
+                               ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp, vp]
+    lib.micx_pairs.restype = ctypes.c_int
+    lib.micx_debug_item.argtypes = [vp, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_int, ctypes.c_int, ip, ip, ip, ip, ip]
+    lib.micx_debug_item.restype = ctypes.c_int
+    lib.micx_strerror.argtypes = [ctypes.c_int]
+    lib.micx_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load_library().micx_strerror(int(code)).decode()
+
+
+def _check(rc: int, where: str):
+    if rc != MICX_OK:
+        raise MicxError(rc, where)
+
+
+def context(device: int = 0):
+    """The library context of a device (created once per process)."""
+    if device not in _ctxs:
+        h = ctypes.c_void_p()
+        _check(load_library().micx_ctx_create(ctypes.byref(h), int(device)), "micx_ctx_create")
+        _ctxs[device] = h
+    return _ctxs[device]
+
+
+def check_param(alpha: float, c: float):
+    msg = load_library().micx_check_param(float(alpha), float(c))
+    return None if msg is None else msg.decode()
+
+
+def grid_bound(n: int, alpha: float) -> int:
+    return load_library().micx_grid_bound(int(n), float(alpha))
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def compute_score(x, y, alpha: float = 0.6, c: float = 15.0, mode: int = MODE_FP64,
+                  device: int = 0):
+    """Score of one pair (host arrays).  Returns dict: stats (MIC, MAS, MEV,
+    MCN), M, Axy, Ayx (W x W, [rows-2, cols-2], NaN outside the grid bound), B."""
+    lib = load_library()
+    x, y = _f64(x), _f64(y)
+    if len(x) != len(y):
+        raise ValueError("x and y differ in length")
+    out = ctypes.POINTER(_Score)()
+    _check(lib.micx_compute_score(context(device), _dptr(x), _dptr(y), len(x), float(alpha),
+                                  float(c), int(mode), ctypes.byref(out)), "micx_compute_score")
+    try:
+        s = out.contents
+        W = s.W
+        M = np.ctypeslib.as_array(s.M, shape=(W * W,)).reshape(W, W).copy()
+        Axy = np.ctypeslib.as_array(s.Axy, shape=(W * W,)).reshape(W, W).copy()
+        Ayx = np.ctypeslib.as_array(s.Ayx, shape=(W * W,)).reshape(W, W).copy()
+        stats = np.array([lib.micx_mic(out), lib.micx_mas(out), lib.micx_mev(out),
+                          lib.micx_mcn(out, 0.0)])
+        return {"stats": stats, "M": M, "Axy": Axy, "Ayx": Ayx, "B": s.B, "W": W}
+    finally:
+        lib.micx_free_score(out)
+
+
+_DTYPES = {"torch.float32": F32, "torch.float64": F64, "torch.int32": I32}
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def allpairs(X, alpha: float = 0.6, c: float = 15.0, mode: int = MODE_FP64, out=None,
+             stream=None):
+    """All pairs of rows of a CUDA tensor X (m x n, float32/float64/int32).
+
+    Returns a (m(m-1)/2, 4) float64 CUDA tensor of (MIC, MAS, MEV, MCN) in
+    row-major upper-triangle order (0,1), (0,2), ..., (m-2, m-1)."""
+    import torch
+    if not X.is_cuda or X.dim() != 2:
+        raise ValueError("X must be a 2-D CUDA tensor")
+    X = X.contiguous()
+    dt = _DTYPES.get(str(X.dtype))
+    if dt is None:
+        raise ValueError("X dtype must be float32, float64 or int32")
+    m, n = X.shape
+    npairs = m * (m - 1) // 2
+    if out is None:
+        out = torch.empty((npairs, 4), dtype=torch.float64, device=X.device)
+    rc = load_library().micx_allpairs(context(X.device.index or 0), ctypes.c_void_p(X.data_ptr()),
+                                      dt, m, n, float(alpha), float(c), int(mode),
+                                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    _check(rc, "micx_allpairs")
+    return out
+
+
+def pairs(X, pair_list, alpha: float = 0.6, c: float = 15.0, mode: int = MODE_FP64, out=None,
+          stream=None):
+    """Listed pairs (i, j) of rows of a CUDA tensor X.  Returns (npairs, 4)."""
+    import torch
+    if not X.is_cuda or X.dim() != 2:
+        raise ValueError("X must be a 2-D CUDA tensor")
+    X = X.contiguous()
+    dt = _DTYPES.get(str(X.dtype))
+    if dt is None:
+        raise ValueError("X dtype must be float32, float64 or int32")
+    m, n = X.shape
+    pl = np.ascontiguousarray(np.asarray(pair_list, dtype=np.int32).reshape(-1, 2))
+    if out is None:
+        out = torch.empty((len(pl), 4), dtype=torch.float64, device=X.device)
+    rc = load_library().micx_pairs(context(X.device.index or 0), ctypes.c_void_p(X.data_ptr()), dt,
+                                   m, n, pl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(pl),
+                                   float(alpha), float(c), int(mode),
+                                   ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    _check(rc, "micx_pairs")
+    return out
+
+
+def debug_item(x, y, alpha: float, c: float, orient: int, ry: int, device: int = 0):
+    """Integer stages of one item (see micx_debug_item)."""
+    x, y = _f64(x), _f64(y)
+    n = len(x)
+    yhat, k, K = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    rs = np.zeros(ry + 1, dtype=np.int32)
+    ends = np.zeros(n, dtype=np.int32)
+    ip = ctypes.POINTER(ctypes.c_int)
+    _check(load_library().micx_debug_item(context(device), _dptr(x), _dptr(y), n, float(alpha),
+                                          float(c), int(orient), int(ry), ctypes.byref(yhat),
+                                          rs.ctypes.data_as(ip), ctypes.byref(k), ctypes.byref(K),
+                                          ends.ctypes.data_as(ip)), "micx_debug_item")
+    return {"yhat": yhat.value, "row_starts": rs[: yhat.value + 1].copy(), "k": k.value,
+            "K": K.value, "ends": ends[: K.value].copy()}

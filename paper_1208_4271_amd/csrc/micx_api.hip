@@ -1,0 +1,455 @@
+// micx_api.hip -- C ABI of the engine (declared in include/micx.h).
+//
+// Host code here validates arguments, derives the grid geometry (B, the row
+// counts y, x(y) = floor(B/y), khat(y)), sizes the workspace and launches the
+// kernels of micx_kernels.hip in order.  No step of the method runs on the
+// host.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "micx.h"
+#include "micx_internal.h"
+
+using namespace micx;
+
+namespace {
+
+// Grow-only device buffer.
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t bytes) {
+        if (bytes <= cap) return MICX_OK;
+        if (p) hipFree(p);
+        p = nullptr;
+        cap = 0;
+        if (hipMalloc(&p, bytes ? bytes : 1) != hipSuccess) {
+            p = nullptr;
+            return MICX_ENOMEM;
+        }
+        cap = bytes;
+        return MICX_OK;
+    }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    template <class T> T *as() const { return (T *)p; }
+};
+
+}  // namespace
+
+struct micx_ctx {
+    int device = 0;
+    int max_slots = 1024;
+    DevBuf perm, gsize, grank, rowof, yhat, rowstart, xlogx, status;
+    DevBuf geo;        // xcnt | khat | koff | aoff
+    DevBuf cbuf, sbuf, Kb, kb, srcb, A, scratch, pairs, input, out, dense;
+};
+
+#define HIPCHK(expr)                                   \
+    do {                                               \
+        if ((expr) != hipSuccess) return MICX_EDEVICE; \
+    } while (0)
+#define RETCHK(expr)                 \
+    do {                             \
+        int rc_ = (expr);            \
+        if (rc_ != MICX_OK) return rc_; \
+    } while (0)
+
+extern "C" const char *micx_strerror(int code) {
+    switch (code) {
+        case MICX_OK: return "ok";
+        case MICX_EINVAL: return "invalid argument";
+        case MICX_ESMALLN: return "floor(n^alpha) < 4: the grid has no cell";
+        case MICX_ENONFINITE: return "input holds NaN or infinity";
+        case MICX_ENOMEM: return "out of memory";
+        case MICX_EDEVICE: return "HIP runtime error or device status word set";
+        case MICX_ETOOBIG: return "sample size above MICX_MAX_N";
+        default: return "unknown error";
+    }
+}
+
+extern "C" const char *micx_check_param(double alpha, double c) {
+    if (!(alpha > 0.0 && alpha <= 1.0)) return "alpha must be in (0, 1]";
+    if (!(c > 0.0) || !isfinite(c)) return "c must be > 0";
+    return nullptr;
+}
+
+extern "C" int micx_grid_bound(int n, double alpha) {
+    return (int)floor(pow((double)n, alpha));
+}
+
+extern "C" int micx_ctx_create(micx_ctx **ctx, int device) {
+    if (!ctx) return MICX_EINVAL;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return MICX_EDEVICE;
+    micx_ctx *c = new (std::nothrow) micx_ctx();
+    if (!c) return MICX_ENOMEM;
+    c->device = device;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return MICX_EDEVICE;
+    }
+    c->max_slots = dp_max_slots(device);
+    *ctx = c;
+    return MICX_OK;
+}
+
+extern "C" void micx_ctx_destroy(micx_ctx *c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    DevBuf *all[] = {&c->perm, &c->gsize, &c->grank, &c->rowof, &c->yhat, &c->rowstart,
+                     &c->xlogx, &c->status, &c->geo, &c->cbuf, &c->sbuf, &c->Kb, &c->kb,
+                     &c->srcb, &c->A, &c->scratch, &c->pairs, &c->input, &c->out, &c->dense};
+    for (DevBuf *b : all) b->release();
+    delete c;
+}
+
+namespace {
+
+struct HostGeometry {
+    Geometry g;
+    std::vector<int> xcnt, khat, koff, aoff;
+};
+
+// Grid geometry for (n, B, c): row counts y = 2..floor(B/2), x(y) = floor(B/y),
+// khat(y) = max(1, min(floor(c x(y)), n)) (Algorithm 2's bound; it never
+// needs to exceed n, the largest possible clump count).
+void make_geometry(int n, int B, double c, HostGeometry &hg) {
+    Geometry &g = hg.g;
+    g.n = n;
+    g.B = B;
+    g.xmax = B / 2;
+    g.NY = B / 2 - 1;
+    g.W = g.NY;
+    hg.xcnt.resize(g.NY);
+    hg.khat.resize(g.NY);
+    hg.koff.resize(g.NY);
+    hg.aoff.resize(g.NY);
+    int ks = 0, as = 0, kmax = 0, kymax = 0;
+    for (int yi = 0; yi < g.NY; yi++) {
+        const int y = yi + 2, x = B / y;
+        double kd = floor(c * (double)x);
+        int kh = kd >= (double)n ? n : (int)kd;
+        if (kh < 1) kh = 1;
+        hg.xcnt[yi] = x;
+        hg.khat[yi] = kh;
+        hg.koff[yi] = ks;
+        hg.aoff[yi] = as;
+        ks += kh;
+        as += x - 1;
+        kmax = std::max(kmax, kh);
+        kymax = std::max(kymax, (kh + 1) * y);
+    }
+    g.KSUM = ks;
+    g.ASUM = as;
+    g.KMAX = kmax;
+    g.KYMAX = kymax;
+}
+
+int upload_geometry(micx_ctx *ctx, HostGeometry &hg) {
+    const int NY = hg.g.NY;
+    RETCHK(ctx->geo.ensure(sizeof(int) * 4 * (size_t)NY));
+    int *d = ctx->geo.as<int>();
+    std::vector<int> h(4 * (size_t)NY);
+    std::copy(hg.xcnt.begin(), hg.xcnt.end(), h.begin());
+    std::copy(hg.khat.begin(), hg.khat.end(), h.begin() + NY);
+    std::copy(hg.koff.begin(), hg.koff.end(), h.begin() + 2 * NY);
+    std::copy(hg.aoff.begin(), hg.aoff.end(), h.begin() + 3 * NY);
+    HIPCHK(hipMemcpy(d, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice));
+    hg.g.xcnt = d;
+    hg.g.khat = d + NY;
+    hg.g.koff = d + 2 * NY;
+    hg.g.aoff = d + 3 * NY;
+    return MICX_OK;
+}
+
+int check_common(micx_ctx *ctx, int n, double alpha, double c, int mode) {
+    if (!ctx) return MICX_EINVAL;
+    if (micx_check_param(alpha, c)) return MICX_EINVAL;
+    if (mode != MICX_MODE_FP64 && mode != MICX_MODE_FP32_RECHECK) return MICX_EINVAL;
+    if (n < 2) return MICX_EINVAL;
+    if (n > MICX_MAX_N) return MICX_ETOOBIG;
+    if (micx_grid_bound(n, alpha) < 4) return MICX_ESMALLN;
+    return MICX_OK;
+}
+
+// Per-variable stages: ranks and equipartitions.  Returns MICX_ENONFINITE if
+// the rank kernel saw a NaN or infinity.
+int prepare_variables(micx_ctx *ctx, const void *X, int dtype, int m, int n, const Geometry &g,
+                      bool want_rowstart, RankTables &rt, EquipTables &et, hipStream_t s) {
+    const size_t mn = (size_t)m * n;
+    RETCHK(ctx->perm.ensure(mn * sizeof(int)));
+    RETCHK(ctx->gsize.ensure(mn * sizeof(int)));
+    RETCHK(ctx->grank.ensure(mn * sizeof(int)));
+    RETCHK(ctx->rowof.ensure(mn * g.NY * sizeof(uint16_t)));
+    RETCHK(ctx->yhat.ensure((size_t)m * g.NY * sizeof(int)));
+    RETCHK(ctx->xlogx.ensure((size_t)(n + 1) * sizeof(double)));
+    RETCHK(ctx->status.ensure(sizeof(int)));
+    rt.m = m;
+    rt.n = n;
+    rt.perm = ctx->perm.as<int>();
+    rt.gsize = ctx->gsize.as<int>();
+    rt.grank = ctx->grank.as<int>();
+    et.NY = g.NY;
+    et.rowof = ctx->rowof.as<uint16_t>();
+    et.yhat = ctx->yhat.as<int>();
+    et.RS = g.NY + 2;
+    et.rowstart = nullptr;
+    if (want_rowstart) {
+        RETCHK(ctx->rowstart.ensure((size_t)m * g.NY * et.RS * sizeof(int)));
+        et.rowstart = ctx->rowstart.as<int>();
+    }
+    int *status = ctx->status.as<int>();
+    HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
+    HIPCHK(launch_xlogx(n, ctx->xlogx.as<double>(), s));
+    HIPCHK(launch_rank(X, dtype, m, n, rt, status, s));
+    HIPCHK(launch_equip(rt, et, s));
+    int hstatus = 0;
+    HIPCHK(hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hstatus & 1) return MICX_ENONFINITE;
+    if (hstatus) return MICX_EDEVICE;
+    return MICX_OK;
+}
+
+// Pairs per batch: bounded so that the per-item buffers stay near 512 MB.
+int batch_pairs(const Geometry &g, int64_t total) {
+    const size_t per_pair = 2 * (2 * (size_t)g.KSUM * sizeof(int) + 3 * (size_t)g.NY * sizeof(int) +
+                                 (size_t)g.ASUM * sizeof(double));
+    size_t pb = ((size_t)512 << 20) / (per_pair ? per_pair : 1);
+    if (pb < 1) pb = 1;
+    if (pb > (size_t)1 << 20) pb = (size_t)1 << 20;
+    if ((int64_t)pb > total) pb = (size_t)total;
+    return (int)pb;
+}
+
+int ensure_items(micx_ctx *ctx, const Geometry &g, int pb, ItemBuffers &ib) {
+    const size_t npo = 2 * (size_t)pb;
+    RETCHK(ctx->cbuf.ensure(npo * g.KSUM * sizeof(int)));
+    RETCHK(ctx->sbuf.ensure(npo * g.KSUM * sizeof(int)));
+    RETCHK(ctx->Kb.ensure(npo * g.NY * sizeof(int)));
+    RETCHK(ctx->kb.ensure(npo * g.NY * sizeof(int)));
+    RETCHK(ctx->srcb.ensure(npo * g.NY * sizeof(int)));
+    RETCHK(ctx->A.ensure(npo * g.ASUM * sizeof(double)));
+    ib.cbuf = ctx->cbuf.as<int>();
+    ib.sbuf = ctx->sbuf.as<int>();
+    ib.K = ctx->Kb.as<int>();
+    ib.k = ctx->kb.as<int>();
+    ib.src = ctx->srcb.as<int>();
+    ib.A = ctx->A.as<double>();
+    return MICX_OK;
+}
+
+// Runs clumps, DP and statistics for npairs pairs in batches.
+int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const Geometry &g,
+              const int32_t *pairs_dev, int64_t npairs, int m, int mode, double *out_dev,
+              double *M, double *Axy, double *Ayx, hipStream_t s) {
+    const int pb = batch_pairs(g, npairs);
+    ItemBuffers ib;
+    RETCHK(ensure_items(ctx, g, pb, ib));
+    const size_t slot = (size_t)(g.xmax + 1) * (size_t)(g.KMAX + 1);
+    const int64_t items_per_batch = (int64_t)pb * 2 * g.NY;
+    const int nslots = (int)std::min<int64_t>(ctx->max_slots, items_per_batch);
+    RETCHK(ctx->scratch.ensure((size_t)nslots * slot * sizeof(double)));
+    for (int64_t p0 = 0; p0 < npairs; p0 += pb) {
+        const int np = (int)std::min<int64_t>(pb, npairs - p0);
+        PairSource ps;
+        ps.m = m;
+        if (pairs_dev) {
+            ps.pairs = pairs_dev + 2 * p0;
+            ps.p0 = 0;
+        } else {
+            ps.pairs = nullptr;
+            ps.p0 = p0;
+        }
+        HIPCHK(launch_part(rt, et, g, ps, np, ib, s));
+        HIPCHK(launch_dp(rt, et, g, ps, np, ib, ctx->xlogx.as<double>(), ctx->scratch.as<double>(),
+                         nslots, slot, mode, s));
+        HIPCHK(launch_stats(g, np, ib, out_dev + 4 * p0, M, Axy, Ayx, s));
+    }
+    return MICX_OK;
+}
+
+int upload_pair_input(micx_ctx *ctx, const double *x, const double *y, int n, hipStream_t s) {
+    RETCHK(ctx->input.ensure(2 * (size_t)n * sizeof(double)));
+    double *d = ctx->input.as<double>();
+    HIPCHK(hipMemcpyAsync(d, x, (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d + n, y, (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
+    RETCHK(ctx->pairs.ensure(2 * sizeof(int32_t)));
+    const int32_t pr[2] = {0, 1};
+    HIPCHK(hipMemcpyAsync(ctx->pairs.p, pr, sizeof(pr), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MICX_OK;
+}
+
+}  // namespace
+
+extern "C" int micx_allpairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n,
+                             double alpha, double c, int mode, double *out_dev, void *stream) {
+    RETCHK(check_common(ctx, n, alpha, c, mode));
+    if (!X_dev || !out_dev || m < 2) return MICX_EINVAL;
+    if (dtype != MICX_F32 && dtype != MICX_F64 && dtype != MICX_I32) return MICX_EINVAL;
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    HostGeometry hg;
+    make_geometry(n, micx_grid_bound(n, alpha), c, hg);
+    RETCHK(upload_geometry(ctx, hg));
+    RankTables rt;
+    EquipTables et;
+    RETCHK(prepare_variables(ctx, X_dev, dtype, m, n, hg.g, false, rt, et, s));
+    const int64_t npairs = (int64_t)m * (m - 1) / 2;
+    RETCHK(run_pairs(ctx, rt, et, hg.g, nullptr, npairs, m, mode, out_dev, nullptr, nullptr,
+                     nullptr, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MICX_OK;
+}
+
+extern "C" int micx_pairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n,
+                          const int32_t *pairs_host, int64_t npairs, double alpha, double c,
+                          int mode, double *out_dev, void *stream) {
+    RETCHK(check_common(ctx, n, alpha, c, mode));
+    if (!X_dev || !out_dev || !pairs_host || m < 2 || npairs < 1) return MICX_EINVAL;
+    if (dtype != MICX_F32 && dtype != MICX_F64 && dtype != MICX_I32) return MICX_EINVAL;
+    for (int64_t k = 0; k < 2 * npairs; k++)
+        if (pairs_host[k] < 0 || pairs_host[k] >= m) return MICX_EINVAL;
+    for (int64_t k = 0; k < npairs; k++)
+        if (pairs_host[2 * k] == pairs_host[2 * k + 1]) return MICX_EINVAL;
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    HostGeometry hg;
+    make_geometry(n, micx_grid_bound(n, alpha), c, hg);
+    RETCHK(upload_geometry(ctx, hg));
+    RETCHK(ctx->pairs.ensure((size_t)npairs * 2 * sizeof(int32_t)));
+    HIPCHK(hipMemcpyAsync(ctx->pairs.p, pairs_host, (size_t)npairs * 2 * sizeof(int32_t),
+                          hipMemcpyHostToDevice, s));
+    RankTables rt;
+    EquipTables et;
+    RETCHK(prepare_variables(ctx, X_dev, dtype, m, n, hg.g, false, rt, et, s));
+    RETCHK(run_pairs(ctx, rt, et, hg.g, ctx->pairs.as<int32_t>(), npairs, m, mode, out_dev,
+                     nullptr, nullptr, nullptr, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MICX_OK;
+}
+
+extern "C" int micx_compute_score(micx_ctx *ctx, const double *x, const double *y, int n,
+                                  double alpha, double c, int mode, micx_score **out) {
+    RETCHK(check_common(ctx, n, alpha, c, mode));
+    if (!x || !y || !out) return MICX_EINVAL;
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = nullptr;
+    HostGeometry hg;
+    const int B = micx_grid_bound(n, alpha);
+    make_geometry(n, B, c, hg);
+    RETCHK(upload_geometry(ctx, hg));
+    RETCHK(upload_pair_input(ctx, x, y, n, s));
+    RankTables rt;
+    EquipTables et;
+    RETCHK(prepare_variables(ctx, ctx->input.p, MICX_F64, 2, n, hg.g, false, rt, et, s));
+    const int W = hg.g.W;
+    const size_t WW = (size_t)W * W;
+    RETCHK(ctx->dense.ensure((4 + 3 * WW) * sizeof(double)));
+    double *d = ctx->dense.as<double>();
+    RETCHK(run_pairs(ctx, rt, et, hg.g, ctx->pairs.as<int32_t>(), 1, 2, mode, d, d + 4,
+                     d + 4 + WW, d + 4 + 2 * WW, s));
+    std::vector<double> h(4 + 3 * WW);
+    HIPCHK(hipMemcpyAsync(h.data(), d, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    micx_score *sc = (micx_score *)calloc(1, sizeof(micx_score));
+    if (!sc) return MICX_ENOMEM;
+    sc->n = n;
+    sc->B = B;
+    sc->W = W;
+    sc->M = (double *)malloc(WW * sizeof(double));
+    sc->Axy = (double *)malloc(WW * sizeof(double));
+    sc->Ayx = (double *)malloc(WW * sizeof(double));
+    if (!sc->M || !sc->Axy || !sc->Ayx) {
+        micx_free_score(sc);
+        return MICX_ENOMEM;
+    }
+    memcpy(sc->stats, h.data(), 4 * sizeof(double));
+    memcpy(sc->M, h.data() + 4, WW * sizeof(double));
+    memcpy(sc->Axy, h.data() + 4 + WW, WW * sizeof(double));
+    memcpy(sc->Ayx, h.data() + 4 + 2 * WW, WW * sizeof(double));
+    *out = sc;
+    return MICX_OK;
+}
+
+extern "C" void micx_free_score(micx_score *s) {
+    if (!s) return;
+    free(s->M);
+    free(s->Axy);
+    free(s->Ayx);
+    free(s);
+}
+
+extern "C" double micx_mic(const micx_score *s) { return s ? s->stats[0] : NAN; }
+extern "C" double micx_mas(const micx_score *s) { return s ? s->stats[1] : NAN; }
+extern "C" double micx_mev(const micx_score *s) { return s ? s->stats[2] : NAN; }
+
+// MCN(eps): eps = 0 returns the value the device computed with the score.
+// Other eps values scan the returned matrix: min log2(xy) over cells with
+// M >= (1 - eps) MIC (Appendix A item 2).
+extern "C" double micx_mcn(const micx_score *s, double eps) {
+    if (!s) return NAN;
+    if (eps == 0.0) return s->stats[3];
+    const double thr = (1.0 - eps) * s->stats[0] - 1e-12;
+    double best = INFINITY;
+    for (int yy = 2; yy <= s->W + 1; yy++)
+        for (int xx = 2; xx * yy <= s->B; xx++) {
+            const double v = s->M[(size_t)(yy - 2) * s->W + (xx - 2)];
+            if (v >= thr) best = std::min(best, log2((double)(xx * yy)));
+        }
+    return best;
+}
+
+extern "C" int micx_debug_item(micx_ctx *ctx, const double *x, const double *y, int n,
+                               double alpha, double c, int orient, int ry, int *yhat,
+                               int *row_starts, int *k, int *K, int *ends) {
+    RETCHK(check_common(ctx, n, alpha, c, MICX_MODE_FP64));
+    const int B = micx_grid_bound(n, alpha);
+    if (!x || !y || !yhat || !row_starts || !k || !K || !ends) return MICX_EINVAL;
+    if (orient != 0 && orient != 1) return MICX_EINVAL;
+    if (ry < 2 || ry > B / 2) return MICX_EINVAL;
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = nullptr;
+    HostGeometry hg;
+    make_geometry(n, B, c, hg);
+    RETCHK(upload_geometry(ctx, hg));
+    RETCHK(upload_pair_input(ctx, x, y, n, s));
+    RankTables rt;
+    EquipTables et;
+    RETCHK(prepare_variables(ctx, ctx->input.p, MICX_F64, 2, n, hg.g, true, rt, et, s));
+    ItemBuffers ib;
+    RETCHK(ensure_items(ctx, hg.g, 1, ib));
+    PairSource ps;
+    ps.pairs = ctx->pairs.as<int32_t>();
+    ps.m = 2;
+    HIPCHK(launch_part(rt, et, hg.g, ps, 1, ib, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const Geometry &g = hg.g;
+    const int yi = ry - 2;
+    const int V = orient ? 0 : 1;   // row variable
+    const size_t it = (size_t)orient * g.NY + yi;
+    int yh = 0, kk = 0, KK = 0, src = 0;
+    HIPCHK(hipMemcpy(&yh, et.yhat + (size_t)V * g.NY + yi, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&kk, ib.k + it, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&KK, ib.K + it, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&src, ib.src + it, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(row_starts, et.rowstart + ((size_t)V * g.NY + yi) * et.RS,
+                     sizeof(int) * (size_t)(yh + 1), hipMemcpyDeviceToHost));
+    const int *eb = (src ? ib.sbuf : ib.cbuf) + (size_t)orient * g.KSUM + hg.koff[yi];
+    HIPCHK(hipMemcpy(ends, eb, sizeof(int) * (size_t)KK, hipMemcpyDeviceToHost));
+    *yhat = yh;
+    *k = kk;
+    *K = KK;
+    return MICX_OK;
+}

@@ -1,0 +1,72 @@
+// micx_internal.h -- launch interface between the C ABI layer (micx_api.hip)
+// and the device kernels (micx_kernels.hip).  Not installed; not part of the
+// public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace micx {
+
+// Per-dataset ranking tables (one row of n entries per variable).
+struct RankTables {
+    int m = 0, n = 0;
+    int *perm = nullptr;    // [v][i]: sample index at sorted position i
+    int *gsize = nullptr;   // [v][p]: tie-group size at group-start position p, else 0
+    int *grank = nullptr;   // [v][j]: sorted position of the start of sample j's tie group
+};
+
+// Per-(variable, row count) equipartition tables.
+struct EquipTables {
+    int NY = 0;             // number of row counts: y = 2 .. NY+1
+    uint16_t *rowof = nullptr;  // [v][p][y-2]: 0-based row of the tie group starting at position p
+    int *yhat = nullptr;        // [v][y-2]: rows produced
+    int *rowstart = nullptr;    // [v][y-2][r]: start position of row r (r = 0..yhat), may be null
+    int RS = 0;                 // stride of rowstart per (v, y): NY + 2
+};
+
+// Grid geometry of one (n, alpha, c) configuration, computed on the host.
+struct Geometry {
+    int n = 0, B = 0, NY = 0, W = 0;   // NY = floor(B/2) - 1 row counts; W = NY
+    int xmax = 0;                      // largest column count, floor(B/2)
+    // per y-2 (device arrays):
+    int *xcnt = nullptr;   // x(y) = floor(B/y)
+    int *khat = nullptr;   // min(floor(c * x(y)), n)
+    int *koff = nullptr;   // offsets of per-item end buffers inside one (pair, orientation)
+    int *aoff = nullptr;   // offsets of per-item score rows inside one (pair, orientation)
+    int KSUM = 0, ASUM = 0, KMAX = 0, KYMAX = 0;   // sums and maxima over y
+};
+
+// Per-batch item buffers.
+struct ItemBuffers {
+    int *cbuf = nullptr;   // clump ends, capacity khat per item
+    int *sbuf = nullptr;   // superclump ends, capacity khat per item
+    int *K = nullptr;      // (super)clumps used by the DP
+    int *k = nullptr;      // clumps before merging
+    int *src = nullptr;    // 0: DP columns are the clumps (cbuf), 1: the superclumps (sbuf)
+    double *A = nullptr;   // normalised scores, ASUM per (pair, orientation)
+};
+
+// Pair source for a batch: either an explicit list (pairs != null) or the
+// row-major upper triangle starting at global pair index p0.
+struct PairSource {
+    const int32_t *pairs = nullptr;   // device, 2 ints per pair
+    int64_t p0 = 0;
+    int m = 0;
+};
+
+hipError_t launch_rank(const void *X, int dtype, int m, int n, RankTables &rt, int *status,
+                       hipStream_t s);
+hipError_t launch_equip(const RankTables &rt, EquipTables &et, hipStream_t s);
+hipError_t launch_part(const RankTables &rt, const EquipTables &et, const Geometry &g,
+                       PairSource ps, int npairs, ItemBuffers &ib, hipStream_t s);
+hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry &g,
+                     PairSource ps, int npairs, const ItemBuffers &ib, const double *xlogx,
+                     double *scratch, int nslots, size_t slot_doubles, int mode, hipStream_t s);
+hipError_t launch_stats(const Geometry &g, int npairs, const ItemBuffers &ib, double *out,
+                        double *M, double *Axy, double *Ayx, hipStream_t s);
+hipError_t launch_xlogx(int n, double *xlogx, hipStream_t s);
+
+int dp_max_slots(int device);
+
+}  // namespace micx

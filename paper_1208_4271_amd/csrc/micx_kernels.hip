@@ -1,0 +1,568 @@
+// micx_kernels.hip -- gfx950 kernels for the approximate characteristic matrix
+// of the MINE statistics (Albanese et al. 2012, arXiv:1208.4271).
+//
+// Pipeline (one launch each; host orchestration in micx_api.hip):
+//   k_xlogx  table L[j] = j ln j, j = 0..n (FP64) used by every entropy term
+//   k_rank   per variable: sort in LDS, tie groups, dense group ranks
+//   k_equip  per (variable, row count y): EquipartitionYAxis (App. A items 3-4)
+//   k_part   per item (pair, orientation, y), one item per lane:
+//            GetClumpsPartition (Algorithm 1) and GetSuperclumpsPartition
+//            (Algorithm 2) streamed over the points in column order
+//   k_dp     per item, one wavefront: cumulative count table (App. A item
+//            10a), column entropy terms (item 10b) and the OptimizeXAxis
+//            dynamic program over the superclump boundaries
+//   k_stats  per pair: characteristic matrix from both orientations and
+//            MIC, MAS, MEV, MCN (App. A items 1, 2, 4)
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "micx_internal.h"
+
+namespace micx {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ double load_value(const void *X, int dtype, size_t idx) {
+    if (dtype == 0) return (double)((const float *)X)[idx];
+    if (dtype == 1) return ((const double *)X)[idx];
+    return (double)((const int32_t *)X)[idx];
+}
+
+// Order-preserving 64-bit key of a finite double; -0.0 and +0.0 map to the
+// same key because the method compares values with ==.
+__device__ __forceinline__ uint64_t order_key(double d) {
+    if (d == 0.0) d = 0.0;
+    uint64_t b = __double_as_longlong(d);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ int64_t tri_offset(int64_t i, int64_t m) {
+    return i * m - i * (i + 1) / 2;
+}
+
+// Pair (i, j) of batch-local pair index pl.
+__device__ __forceinline__ void pair_of(const PairSource &ps, int pl, int &i, int &j) {
+    if (ps.pairs) {
+        i = ps.pairs[2 * pl];
+        j = ps.pairs[2 * pl + 1];
+        return;
+    }
+    const int64_t P = ps.p0 + pl, m = ps.m;
+    const double mm = 2.0 * (double)m - 1.0;
+    int64_t a = (int64_t)floor((mm - sqrt(mm * mm - 8.0 * (double)P)) * 0.5);
+    if (a < 0) a = 0;
+    if (a > m - 2) a = m - 2;
+    while (a + 1 <= m - 2 && tri_offset(a + 1, m) <= P) a++;
+    while (a > 0 && tri_offset(a, m) > P) a--;
+    i = (int)a;
+    j = (int)(P - tri_offset(a, m) + a + 1);
+}
+
+// ------------------------------------------------------------------ k_xlogx
+
+__global__ void k_xlogx(int n, double *L) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j <= n) L[j] = j > 1 ? (double)j * log((double)j) : 0.0;
+}
+
+// ------------------------------------------------------------------- k_rank
+// One workgroup per variable.  Bitonic sort of (key, sample index) pairs in
+// LDS (N2 = next power of two >= n), then tie-group starts by a max-scan.
+
+__global__ __launch_bounds__(1024) void k_rank(const void *X, int dtype, int m, int n, int N2,
+                                               int *perm, int *gsize, int *grank, int *status) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint64_t *key = (uint64_t *)smem;
+    int *idx = (int *)(key + N2);
+    int *gst = idx + N2;
+    const int v = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const size_t base = (size_t)v * n;
+    for (int i = tid; i < N2; i += nt) {
+        if (i < n) {
+            const double d = load_value(X, dtype, base + i);
+            if (!isfinite(d)) atomicOr(status, 1);
+            key[i] = order_key(d);
+            idx[i] = i;
+        } else {
+            key[i] = ~0ull;
+            idx[i] = 0x7fffffff;
+        }
+    }
+    __syncthreads();
+    for (int k = 2; k <= N2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < N2; i += nt) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const uint64_t ka = key[i], kb = key[ixj];
+                    const int ia = idx[i], ib = idx[ixj];
+                    const bool a_gt_b = (ka > kb) || (ka == kb && ia > ib);
+                    const bool up = (i & k) == 0;
+                    if (a_gt_b == up) {
+                        key[i] = kb; key[ixj] = ka;
+                        idx[i] = ib; idx[ixj] = ia;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // group start of every position: inclusive max-scan of (start ? i : 0)
+    for (int i = tid; i < N2; i += nt)
+        gst[i] = (i < n && (i == 0 || key[i] != key[i - 1])) ? i : 0;
+    __syncthreads();
+    for (int d = 1; d < N2; d <<= 1) {
+        int vals[8];
+        int c = 0;
+        for (int i = tid; i < N2; i += nt, c++) vals[c] = (i >= d) ? max(gst[i], gst[i - d]) : gst[i];
+        __syncthreads();
+        c = 0;
+        for (int i = tid; i < N2; i += nt, c++) gst[i] = vals[c];
+        __syncthreads();
+    }
+    for (int i = tid; i < n; i += nt) {
+        const int s = gst[i];
+        perm[base + i] = idx[i];
+        grank[base + idx[i]] = s;
+        const bool end = (i == n - 1) || key[i + 1] != key[i];
+        if (end) gsize[base + s] = i - s + 1;
+        if (s != i) gsize[base + i] = 0;
+    }
+}
+
+// ------------------------------------------------------------------ k_equip
+// EquipartitionYAxis (App. A items 3-4), one (variable, y) per lane.  The
+// greedy walks the tie groups in order; with a the current row's size, s the
+// next group's size, R the points left when the row opened and L the rows
+// left (including the current one), the paper's real-valued rule
+// |a + s - R/L| >= |a - R/L| (row not empty) is equivalent to the integer
+// test (2a + s) * L >= 2R, used here so that the partition is bit-exact.
+
+__global__ __launch_bounds__(64) void k_equip(int m, int n, int NY, const int *gsize,
+                                              uint16_t *rowof, int *yhat, int *rowstart, int RS) {
+    const int nyb = (NY + 63) / 64;
+    const int v = blockIdx.x / nyb, yb = blockIdx.x % nyb;
+    const int yi = yb * 64 + threadIdx.x;
+    const bool act = yi < NY;
+    const int y = yi + 2;
+    const int *gs = gsize + (size_t)v * n;
+    uint16_t *ro = rowof + (size_t)v * n * NY + yi;
+    int *rs = rowstart ? rowstart + ((size_t)v * NY + yi) * RS : nullptr;
+    int r = 0, a = 0, R = n, L = y;
+    if (act && rs) rs[0] = 0;
+    for (int p = 0; p < n;) {
+        const int s = gs[p];
+        if (a != 0 && (int64_t)(2 * a + s) * L >= 2 * (int64_t)R) {
+            r++;
+            a = 0;
+            R = n - p;
+            L = y - r;
+            if (act && rs) rs[r] = p;
+        }
+        if (act) ro[(size_t)p * NY] = (uint16_t)r;
+        a += s;
+        p += s;
+    }
+    if (act) {
+        yhat[(size_t)v * NY + yi] = r + 1;
+        if (rs) rs[r + 1] = n;
+    }
+}
+
+// ------------------------------------------------------------------- k_part
+// Clumps and superclumps of one item per lane.  A wavefront serves one
+// (pair, orientation) and up to 64 row counts y; the points are visited in
+// the column variable's order, so the per-point reads (tie-group size of the
+// column variable, group rank of the row variable) are the same for every
+// lane and only the row lookup differs.
+//
+// GetClumpsPartition (Algorithm 1, with one fresh label per mixed tie group
+// as Fig. 2 prints it): a column-variable tie group whose points lie in two
+// or more rows is a clump boundary on both sides; otherwise a boundary sits
+// between consecutive groups whose rows differ.
+// GetSuperclumpsPartition (Algorithm 2): when the clumps outnumber
+// khat = floor(c x), EquipartitionYAxis runs over the clump sequence (each
+// clump one tie group) with khat rows.  Both are computed in one pass; the
+// clump list is kept only while it fits in khat entries.
+
+struct PartArgs {
+    int n, NY, KSUM;
+    PairSource ps;
+    const int *perm, *gsize, *grank;
+    const uint16_t *rowof;
+    const int *khat, *koff;
+    int *cbuf, *sbuf, *K, *k, *src;
+};
+
+__global__ __launch_bounds__(64) void k_part(PartArgs a) {
+    const int nyb = (a.NY + 63) / 64;
+    const int w = blockIdx.x;
+    const int yb = w % nyb, po = w / nyb;
+    const int o = po & 1, pl = po >> 1;
+    int pi, pj;
+    pair_of(a.ps, pl, pi, pj);
+    const int U = o ? pj : pi, V = o ? pi : pj;
+    const int lane = threadIdx.x;
+    const int yi = yb * 64 + lane;
+    const bool act = yi < a.NY;
+    const int yic = act ? yi : a.NY - 1;
+    const int n = a.n;
+    const int kh = a.khat[yic];
+    const size_t base = (size_t)po * a.KSUM + a.koff[yic];
+    int *cb = a.cbuf + base;
+    int *sb = a.sbuf + base;
+    const int *permU = a.perm + (size_t)U * n;
+    const int *gsU = a.gsize + (size_t)U * n;
+    const int *grV = a.grank + (size_t)V * n;
+    const uint16_t *rowV = a.rowof + (size_t)V * n * a.NY + yic;
+
+    int first = 0, mixed = 0, gstart = 0;   // current tie group of the column variable
+    int last = -2;                           // label of the previous group: -2 none, -1 mixed
+    int cstart = 0, k = 0;                   // current clump start, clumps emitted
+    int sa = 0, sP0 = 0, sR = n, sL = kh, sr = 0;   // superclump greedy state
+
+    auto emit_clump = [&](int ce) {
+        const int size = ce - cstart;
+        k++;
+        if (act && k <= kh) cb[k - 1] = ce;
+        if (sa != 0 && (int64_t)(2 * sa + size) * sL >= 2 * (int64_t)sR) {
+            if (act) sb[sr] = sP0 + sa;
+            sr++;
+            sP0 += sa;
+            sa = 0;
+            sR = n - sP0;
+            sL = kh - sr;
+        }
+        sa += size;
+        cstart = ce;
+    };
+    auto close_group = [&]() {
+        const int lg = mixed ? -1 : first;
+        if (last != -2 && (lg == -1 || last == -1 || lg != last)) emit_clump(gstart);
+        last = lg;
+    };
+
+    for (int p0 = 0; p0 < n; p0 += 64) {
+        // stage 64 points: column-group size and row-variable group rank
+        const int q = p0 + lane;
+        int gsz = 0, grk = 0;
+        if (q < n) {
+            gsz = gsU[q];
+            grk = grV[permU[q]];
+        }
+        const int cnt = min(64, n - p0);
+        int labs[64];
+#pragma unroll
+        for (int s = 0; s < 64; s++) {
+            const int g = __builtin_amdgcn_readlane(grk, s);
+            labs[s] = (s < cnt) ? (int)rowV[(size_t)g * a.NY] : 0;
+        }
+#pragma unroll
+        for (int s = 0; s < 64; s++) {
+            if (s < cnt) {
+                const int gs = __builtin_amdgcn_readlane(gsz, s);
+                const int lab = labs[s];
+                if (gs > 0) {
+                    if (p0 + s > 0) close_group();
+                    first = lab;
+                    mixed = 0;
+                    gstart = p0 + s;
+                } else {
+                    mixed |= (lab != first);
+                }
+            }
+        }
+    }
+    close_group();
+    emit_clump(n);
+    if (act) sb[sr] = n;
+    if (act) {
+        const size_t it = (size_t)po * a.NY + yi;
+        a.k[it] = k;
+        if (k <= kh) {
+            a.K[it] = k;
+            a.src[it] = 0;
+        } else {
+            a.K[it] = sr + 1;
+            a.src[it] = 1;
+        }
+    }
+}
+
+// --------------------------------------------------------------------- k_dp
+// OptimizeXAxis (App. A item 10) for one item per wavefront.
+//
+// Cumulative counts N[t][r] (points among the first t superclumps that lie in
+// row r) are built in LDS.  The cost of a column spanning superclumps
+// (s, t] is h(s,t) = L[m] - sum_r L[n_r] with m = e_t - e_s and
+// n_r = N[t][r] - N[s][r] -- the column's point count times its row entropy.
+// G_l(t), the least total cost of the first t superclumps in at most l
+// columns, obeys G_1(t) = h(0,t), G_l(t) = min_{0 <= s < t} G_{l-1}(s) + h(s,t)
+// with G_{l-1}(0) = 0; then I_l = H(Q) - G_l(K)/n.
+//
+// Lanes own targets t in chunks of 64; the layers of a pass (up to XB) live
+// in registers.  Sources from earlier chunks are final and are read from the
+// item's G table in global scratch; sources inside the chunk are taken in
+// order, the owning lane publishing its layers through LDS.
+
+struct DpArgs {
+    int n, NY, KSUM, ASUM, KMAX, YH;
+    int64_t nitems;
+    int npairs;
+    PairSource ps;
+    const int *perm, *grank;
+    const uint16_t *rowof;
+    const int *yhat, *xcnt, *koff, *aoff;
+    const int *cbuf, *sbuf, *K, *src;
+    double *A;
+    const double *xlogx;
+    double *scratch;
+    size_t slot;
+};
+
+template <int XB>
+__global__ __launch_bounds__(64) void k_dp64(DpArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = a.n;
+    double *L = (double *)smem;         // n+1
+    double *buf = L + (n + 1);           // XB
+    int *e = (int *)(buf + XB);          // KMAX+1
+    int *N = e + (a.KMAX + 1);           // (KMAX+1) * YH
+    const int lane = threadIdx.x;
+    for (int j = lane; j <= n; j += 64) L[j] = a.xlogx[j];
+    __syncthreads();
+    double *G = a.scratch + (size_t)blockIdx.x * a.slot;
+    const int64_t per_y = 2 * (int64_t)a.npairs;
+
+    for (int64_t item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+        const int yi = (int)(item / per_y);
+        const int po = (int)(item % per_y);
+        const int o = po & 1, pl = po >> 1;
+        int pi, pj;
+        pair_of(a.ps, pl, pi, pj);
+        const int U = o ? pj : pi, V = o ? pi : pj;
+        const int x = a.xcnt[yi];
+        const size_t it = (size_t)po * a.NY + yi;
+        const int K = a.K[it];
+        const int yh = a.yhat[(size_t)V * a.NY + yi];
+        const int *ends = (a.src[it] ? a.sbuf : a.cbuf) + (size_t)po * a.KSUM + a.koff[yi];
+
+        if (lane == 0) e[0] = 0;
+        for (int t = lane; t < K; t += 64) e[t + 1] = ends[t];
+        for (int q = lane; q < (K + 1) * yh; q += 64) N[q] = 0;
+        __syncthreads();
+        const int *permU = a.perm + (size_t)U * n;
+        const int *grV = a.grank + (size_t)V * n;
+        const uint16_t *rowV = a.rowof + (size_t)V * n * a.NY + yi;
+        for (int p = lane; p < n; p += 64) {
+            const int g = grV[permU[p]];
+            const int r = rowV[(size_t)g * a.NY];
+            int lo = 1, hi = K;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (e[mid] > p) hi = mid; else lo = mid + 1;
+            }
+            atomicAdd(&N[lo * yh + r], 1);
+        }
+        __syncthreads();
+        for (int r = lane; r < yh; r += 64) {
+            int run = 0;
+            for (int t = 1; t <= K; t++) {
+                run += N[t * yh + r];
+                N[t * yh + r] = run;
+            }
+        }
+        __syncthreads();
+
+        auto hcost = [&](int s, int t) -> double {
+            double acc = L[e[t] - e[s]];
+            const int *Nt = N + t * yh, *Ns = N + s * yh;
+            for (int r = 0; r < yh; r++) acc -= L[Nt[r] - Ns[r]];
+            return acc;
+        };
+
+        const size_t K1 = (size_t)K + 1;
+        for (int t = lane + 1; t <= K; t += 64) G[K1 + t] = hcost(0, t);
+        __syncthreads();
+        for (int l0 = 2; l0 <= x; l0 += XB) {
+            const int nl = min(XB, x - l0 + 1);
+            for (int c0 = 0; c0 < K; c0 += 64) {
+                const int t = c0 + 1 + lane;
+                const bool act = t <= K;
+                double g[XB];
+                const double h0 = act ? hcost(0, t) : 0.0;
+#pragma unroll
+                for (int jj = 0; jj < XB; jj++) g[jj] = h0;
+                for (int s = 1; s <= c0; s++) {
+                    const double hs = act ? hcost(s, t) : 0.0;
+                    const double *Gs = G + (size_t)(l0 - 1) * K1 + s;
+#pragma unroll
+                    for (int jj = 0; jj < XB; jj++)
+                        if (jj < nl) g[jj] = fmin(g[jj], Gs[(size_t)jj * K1] + hs);
+                }
+                const int cend = min(c0 + 64, K);
+                for (int s = c0 + 1; s < cend; s++) {
+                    if (lane == s - c0 - 1) {
+#pragma unroll
+                        for (int jj = 0; jj + 1 < XB; jj++) buf[jj] = g[jj];
+                    }
+                    __syncthreads();
+                    if (act && t > s) {
+                        const double hs = hcost(s, t);
+                        g[0] = fmin(g[0], G[(size_t)(l0 - 1) * K1 + s] + hs);
+#pragma unroll
+                        for (int jj = 1; jj < XB; jj++)
+                            if (jj < nl) g[jj] = fmin(g[jj], buf[jj - 1] + hs);
+                    }
+                    __syncthreads();
+                }
+                if (act) {
+#pragma unroll
+                    for (int jj = 0; jj < XB; jj++)
+                        if (jj < nl) G[(size_t)(l0 + jj) * K1 + t] = g[jj];
+                }
+                __syncthreads();
+            }
+        }
+        // I_l = (L[n] - sum_r L[q_r] - G_l(K)) / n, normalised by ln min(l, yhat)
+        double sq = 0.0;
+        for (int r = 0; r < yh; r++) sq += L[N[K * yh + r]];
+        double *Aout = a.A + (size_t)po * a.ASUM + a.aoff[yi];
+        for (int l = 2 + lane; l <= x; l += 64) {
+            const double I = (L[n] - sq - G[(size_t)l * K1 + K]) / (double)n;
+            const int norm = min(l, yh);
+            Aout[l - 2] = norm >= 2 ? I / log((double)norm) : 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ k_stats
+// Characteristic matrix and statistics of one pair per thread.
+// M_{x,y} (x bins of the first variable, y of the second) is the larger of
+// the orientation scores for that grid shape: first variable optimised into
+// x columns with the second equipartitioned into y rows, or the second
+// optimised into y columns with the first equipartitioned into x rows.
+
+struct StatsArgs {
+    int npairs, B, NY, W, ASUM;
+    const int *aoff;
+    const double *A;
+    double *out, *M, *Axy, *Ayx;
+};
+
+__global__ void k_stats(StatsArgs a) {
+    const int pl = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pl >= a.npairs) return;
+    const double *A0 = a.A + (size_t)(2 * pl) * a.ASUM;
+    const double *A1 = a.A + (size_t)(2 * pl + 1) * a.ASUM;
+    const int Bh = a.B / 2;
+    auto Mxy = [&](int xx, int yy) -> double {
+        return fmax(A0[a.aoff[yy - 2] + xx - 2], A1[a.aoff[xx - 2] + yy - 2]);
+    };
+    double mic = 0.0;
+    for (int yy = 2; yy <= Bh; yy++)
+        for (int xx = 2; xx * yy <= a.B; xx++) mic = fmax(mic, Mxy(xx, yy));
+    double mas = 0.0, mev = 0.0, mcn = INFINITY;
+    for (int yy = 2; yy <= Bh; yy++)
+        for (int xx = 2; xx * yy <= a.B; xx++) {
+            const double v = Mxy(xx, yy);
+            mas = fmax(mas, fabs(v - Mxy(yy, xx)));
+            if (xx == 2 || yy == 2) mev = fmax(mev, v);
+            if (v >= mic - 1e-12) mcn = fmin(mcn, log2((double)(xx * yy)));
+        }
+    double *o = a.out + (size_t)4 * pl;
+    o[0] = mic; o[1] = mas; o[2] = mev; o[3] = mcn;
+    if (a.M) {
+        const int W = a.W;
+        for (int r = 2; r <= W + 1; r++)
+            for (int cc = 2; cc <= W + 1; cc++) {
+                const size_t q = (size_t)(r - 2) * W + (cc - 2);
+                const bool ok = r * cc <= a.B;
+                a.M[q] = ok ? Mxy(cc, r) : NAN;
+                a.Axy[q] = ok ? A0[a.aoff[r - 2] + cc - 2] : NAN;
+                a.Ayx[q] = ok ? A1[a.aoff[r - 2] + cc - 2] : NAN;
+            }
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_xlogx(int n, double *xlogx, hipStream_t s) {
+    hipLaunchKernelGGL(k_xlogx, dim3((n + 256) / 256), dim3(256), 0, s, n, xlogx);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank(const void *X, int dtype, int m, int n, RankTables &rt, int *status,
+                       hipStream_t s) {
+    int N2 = 1;
+    while (N2 < n) N2 <<= 1;
+    const size_t lds = (size_t)N2 * (8 + 4 + 4);
+    const int threads = N2 >= 1024 ? 1024 : (N2 < 64 ? 64 : N2);
+    hipError_t e = hipFuncSetAttribute((const void *)k_rank,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rank, dim3(m), dim3(threads), lds, s, X, dtype, m, n, N2, rt.perm,
+                       rt.gsize, rt.grank, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_equip(const RankTables &rt, EquipTables &et, hipStream_t s) {
+    const int nyb = (et.NY + 63) / 64;
+    hipLaunchKernelGGL(k_equip, dim3(rt.m * nyb), dim3(64), 0, s, rt.m, rt.n, et.NY, rt.gsize,
+                       et.rowof, et.yhat, et.rowstart, et.RS);
+    return hipGetLastError();
+}
+
+hipError_t launch_part(const RankTables &rt, const EquipTables &et, const Geometry &g,
+                       PairSource ps, int npairs, ItemBuffers &ib, hipStream_t s) {
+    PartArgs a;
+    a.n = rt.n; a.NY = g.NY; a.KSUM = g.KSUM; a.ps = ps;
+    a.perm = rt.perm; a.gsize = rt.gsize; a.grank = rt.grank; a.rowof = et.rowof;
+    a.khat = g.khat; a.koff = g.koff;
+    a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.k = ib.k; a.src = ib.src;
+    const int nyb = (g.NY + 63) / 64;
+    hipLaunchKernelGGL(k_part, dim3((unsigned)(2 * npairs * nyb)), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+static const int kXB = 16;
+
+hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry &g,
+                     PairSource ps, int npairs, const ItemBuffers &ib, const double *xlogx,
+                     double *scratch, int nslots, size_t slot_doubles, int mode, hipStream_t s) {
+    (void)mode;
+    DpArgs a;
+    a.n = rt.n; a.NY = g.NY; a.KSUM = g.KSUM; a.ASUM = g.ASUM; a.KMAX = g.KMAX; a.YH = g.NY + 1;
+    a.nitems = (int64_t)npairs * 2 * g.NY;
+    a.npairs = npairs; a.ps = ps;
+    a.perm = rt.perm; a.grank = rt.grank; a.rowof = et.rowof; a.yhat = et.yhat;
+    a.xcnt = g.xcnt; a.koff = g.koff; a.aoff = g.aoff;
+    a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.src = ib.src; a.A = ib.A;
+    a.xlogx = xlogx; a.scratch = scratch; a.slot = slot_doubles;
+    const size_t lds = (size_t)(rt.n + 1) * 8 + kXB * 8 + (size_t)(g.KMAX + 1) * 4 +
+                       (size_t)g.KYMAX * 4;
+    hipError_t e = hipFuncSetAttribute((const void *)k_dp64<kXB>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int64_t grid = a.nitems < nslots ? a.nitems : nslots;
+    hipLaunchKernelGGL(k_dp64<kXB>, dim3((unsigned)grid), dim3(64), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats(const Geometry &g, int npairs, const ItemBuffers &ib, double *out,
+                        double *M, double *Axy, double *Ayx, hipStream_t s) {
+    StatsArgs a;
+    a.npairs = npairs; a.B = g.B; a.NY = g.NY; a.W = g.W; a.ASUM = g.ASUM;
+    a.aoff = g.aoff; a.A = ib.A; a.out = out; a.M = M; a.Axy = Axy; a.Ayx = Ayx;
+    hipLaunchKernelGGL(k_stats, dim3((npairs + 127) / 128), dim3(128), 0, s, a);
+    return hipGetLastError();
+}
+
+int dp_max_slots(int device) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) return 1024;
+    return p.multiProcessorCount * 8;
+}
+
+}  // namespace micx

@@ -1,0 +1,62 @@
+"""The C-ABI library builds, loads and exports every symbol include/micx.h
+declares.  Host-only entry points (no kernel launch) are exercised here;
+compute calls need a GPU and live in test_gpu_*.py."""
+import os
+import re
+
+import numpy as np
+
+import oracle
+import paper_1208_4271_amd as micx
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "micx.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(micx_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = micx.load_library()
+    declared = _declared_functions()
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(micx.EXPORTS) == declared
+
+
+def test_library_is_built_for_gfx950():
+    data = open(micx.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+
+
+def test_check_param_messages():
+    assert micx.check_param(0.6, 15) is None
+    assert micx.check_param(0.0, 15) is not None
+    assert micx.check_param(1.2, 15) is not None
+    assert micx.check_param(0.6, 0.0) is not None
+    assert micx.check_param(0.6, -1.0) is not None
+    assert micx.check_param(1.0, 1e-3) is None
+
+
+def test_grid_bound_matches_oracle_on_boundary_sizes():
+    for n in (11, 243, 1024, 3125, 7776, 1340, 400, 200):
+        assert micx.grid_bound(n, 0.6) == oracle.grid_bound(n, 0.6)
+    for n in (81, 256, 4096, 8000):
+        assert micx.grid_bound(n, 0.75) == oracle.grid_bound(n, 0.75)
+
+
+def test_strerror_covers_codes():
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert micx.strerror(code)
+    assert micx.strerror(-99) == "unknown error"
+
+
+def test_workloads_shapes():
+    X = workloads.cfg2_matrix()
+    assert X.shape == (64, 400) and X.dtype == np.float32
+    x, y = workloads.cfg1_single_pair()
+    assert len(x) == 200 and x.dtype == np.float64

@@ -1,0 +1,167 @@
+"""GPU path vs the FP64 oracle, through the C ABI.
+
+Integer stages (rows, clumps, superclumps) must match bit for bit; matrix
+entries and MIC/MAS/MEV must agree within 1e-6 absolute (the FP64 form is in
+fact within ~1e-12); MCN must select the same cell.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _cmp_scores(got, want, tol=TOL):
+    gm, wm = got["M"], want["M"]
+    assert gm.shape == wm.shape
+    assert np.array_equal(np.isnan(gm), np.isnan(wm))
+    ok = ~np.isnan(wm)
+    for key in ("M", "Axy", "Ayx"):
+        d = np.abs(got[key][ok] - want[key][ok]).max()
+        assert d <= tol, (key, d)
+    gs, ws = got["stats"], want["stats"]
+    assert np.abs(gs[:3] - ws[:3]).max() <= tol, (gs, ws)
+    assert abs(gs[3] - ws[3]) < 1e-9, (gs, ws)
+
+
+def test_cpp_example(micx):
+    _log("case cpp_example")
+    x, y = workloads.cpp_example()
+    got = micx.compute_score(x, y, 0.6, 15)
+    want = oracle.score(x, y, 0.6, 15)
+    _cmp_scores(got, want)
+    printed = (0.999999, 0.728144, 0.999999, 4.584963)
+    for v, p in zip(got["stats"], printed):
+        assert abs(v - p) <= 5e-7 + 1e-12
+
+
+def test_cfg1_single_pair_full_matrix(micx):
+    _log("case cfg1")
+    x, y = workloads.cfg1_single_pair()
+    _cmp_scores(micx.compute_score(x, y, 0.6, 15), oracle.score(x, y, 0.6, 15), tol=1e-10)
+
+
+@pytest.mark.parametrize("name", [c[0] for c in workloads.boundary_cases()])
+def test_boundary_cases(micx, name):
+    case = [c for c in workloads.boundary_cases() if c[0] == name][0]
+    _, x, y, alpha = case
+    _log("case boundary %s n=%d" % (name, len(x)))
+    _cmp_scores(micx.compute_score(x, y, alpha, 15), oracle.score(x, y, alpha, 15), tol=1e-10)
+
+
+def _integer_stage_cases():
+    rng = np.random.default_rng(11)
+    cases = [("cfg1",) + workloads.cfg1_single_pair() + (0.6, 15.0)]
+    a, b = workloads.fig2_points()
+    cases.append(("fig2", a, b, 1.0, 15.0))
+    n = 500
+    x = np.floor(rng.uniform(0, 40, n))
+    y = np.floor(rng.uniform(0, 25, n))
+    cases.append(("ties", x, y, 0.6, 15.0))
+    cases.append(("ties_c2", x, y, 0.6, 2.0))
+    x = rng.uniform(0, 1, 777)
+    cases.append(("sine_c5", x, np.sin(9 * x) + rng.normal(0, 0.2, 777), 0.7, 5.0))
+    return cases
+
+
+@pytest.mark.parametrize("case", _integer_stage_cases(), ids=lambda c: c[0])
+def test_integer_stages_bit_exact(micx, case):
+    name, x, y, alpha, c = case
+    _log("case integer stages %s" % name)
+    B = oracle.grid_bound(len(x), alpha)
+    for orient in (0, 1):
+        for ry in range(2, B // 2 + 1):
+            g = micx.debug_item(x, y, alpha, c, orient, ry)
+            w = oracle.item(x, y, alpha, c, orient, ry)
+            assert g["yhat"] == w["yhat"], (orient, ry)
+            assert np.array_equal(g["row_starts"], w["row_starts"]), (orient, ry)
+            assert g["k"] == w["k"] and g["K"] == w["K"], (orient, ry, g["k"], w["k"], g["K"], w["K"])
+            assert np.array_equal(g["ends"], w["ends"]), (orient, ry)
+
+
+def test_cfg2_allpairs(micx):
+    import torch
+    _log("case cfg2 allpairs")
+    X = workloads.cfg2_matrix()
+    got = micx.allpairs(torch.from_numpy(X).cuda(), 0.6, 15).cpu().numpy()
+    want = oracle.allpairs(X.astype(np.float64), 0.6, 15)
+    assert got.shape == want.shape
+    assert np.abs(got[:, :3] - want[:, :3]).max() <= TOL
+    assert (np.abs(got[:, 3] - want[:, 3]) < 1e-9).all()
+
+
+def test_cfg3_subset_allpairs(micx):
+    import torch
+    _log("case cfg3 subset")
+    X, planted = workloads.cfg3_matrix()
+    rows = sorted(set([0, 1, 2, 3, 4, 5] + [int(planted[k, 0]) for k in range(6)] +
+                      [int(planted[k, 1]) for k in range(6)]))
+    Xs = X[rows]
+    got = micx.allpairs(torch.from_numpy(Xs).cuda(), 0.6, 15).cpu().numpy()
+    want = oracle.allpairs(Xs, 0.6, 15)
+    assert np.abs(got[:, :3] - want[:, :3]).max() <= TOL
+    assert (np.abs(got[:, 3] - want[:, 3]) < 1e-9).all()
+
+
+def test_cfg4_int32_pairs(micx):
+    import torch
+    _log("case cfg4 int32 subset")
+    C = workloads.cfg4_matrix(m=40)
+    got = micx.allpairs(torch.from_numpy(C).cuda(), 0.6, 15).cpu().numpy()
+    want = oracle.allpairs(C.astype(np.float64), 0.6, 15)
+    assert np.abs(got[:, :3] - want[:, :3]).max() <= TOL
+    assert (np.abs(got[:, 3] - want[:, 3]) < 1e-9).all()
+
+
+def test_pair_list_matches_allpairs(micx):
+    import torch
+    _log("case pair list")
+    X = workloads.cfg2_matrix()[:12]
+    Xd = torch.from_numpy(X).cuda()
+    allp = micx.allpairs(Xd, 0.6, 15).cpu().numpy()
+    m = X.shape[0]
+    lst = [(i, j) for i in range(m) for j in range(i + 1, m)][::-1]
+    got = micx.pairs(Xd, lst, 0.6, 15).cpu().numpy()
+    idx = {p: k for k, p in enumerate([(i, j) for i in range(m) for j in range(i + 1, m)])}
+    for k, p in enumerate(lst):
+        assert np.array_equal(got[k], allp[idx[p]])
+    # swapped order: MIC, MEV, MCN unchanged, MAS unchanged (|M - M^T| is symmetric)
+    got_sw = micx.pairs(Xd, [(j, i) for (i, j) in lst], 0.6, 15).cpu().numpy()
+    assert np.abs(got_sw - got).max() <= 1e-12
+
+
+def test_error_paths(micx):
+    import torch
+    x = np.linspace(0, 1, 100)
+    with pytest.raises(micx.MicxError) as e:
+        micx.compute_score(x, x, 0.0, 15)
+    assert e.value.code == micx.MICX_EINVAL
+    with pytest.raises(micx.MicxError) as e:
+        micx.compute_score(x[:8], x[:8], 0.6, 15)
+    assert e.value.code == micx.MICX_ESMALLN
+    bad = x.copy()
+    bad[17] = np.nan
+    with pytest.raises(micx.MicxError) as e:
+        micx.compute_score(bad, x, 0.6, 15)
+    assert e.value.code == micx.MICX_ENONFINITE
+    big = np.zeros(micx.MAX_N + 1)
+    with pytest.raises(micx.MicxError) as e:
+        micx.compute_score(big, big, 0.6, 15)
+    assert e.value.code == micx.MICX_ETOOBIG
+    Xd = torch.zeros((3, 100), dtype=torch.float64, device="cuda")
+    Xd[1, 5] = float("inf")
+    out = torch.full((3, 4), -7.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(micx.MicxError) as e:
+        micx.allpairs(Xd, 0.6, 15, out=out)
+    assert e.value.code == micx.MICX_ENONFINITE
+    assert (out == -7.0).all(), "outputs must stay untouched on error"

@@ -8,6 +8,7 @@ unmodified source must pass the same battery.
 import math
 import os
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -35,7 +36,7 @@ MUTANTS = {
     # normalised by the requested row count instead of yhat (App. A item 4)
     "norm_by_requested": ("(l < yhat ? l : yhat)", "(l < ry ? l : ry)"),
     # one superclump more than khat (the MINE.jar behaviour of App. A item 7)
-    "khat_plus_one": ("return (int) floor(c * (double) cx);", "return (int) floor(c * (double) cx) + 1;"),
+    "khat_plus_one": ("int k = (int) floor(c * (double) cx);", "int k = (int) floor(c * (double) cx) + 1;"),
 }
 
 
@@ -104,11 +105,28 @@ def test_unmodified_oracle_passes_battery():
     assert _battery()
 
 
+_CHILD = """
+import importlib.util, sys
+sys.path.insert(0, {root!r})
+import oracle
+spec = importlib.util.spec_from_file_location("mut", {here!r})
+mod = importlib.util.module_from_spec(spec)
+spec.loader.exec_module(mod)
+with oracle._use_library({so!r}):
+    ok = mod._battery()
+sys.exit(0 if ok else 3)
+"""
+
+
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_mutant_is_caught(tmp_path, name):
+    # The battery runs in a child process: a mutant may also corrupt memory,
+    # and a crash counts as caught.
     src = open(SRC).read()
     old, new = MUTANTS[name]
     assert src.count(old) == 1
     so = _build_variant(tmp_path, name, src.replace(old, new))
-    with oracle._use_library(so):
-        assert not _battery(), "pins did not catch mutant " + name
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = _CHILD.format(root=root, here=os.path.abspath(__file__), so=so)
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert res.returncode != 0, "pins did not catch mutant " + name
