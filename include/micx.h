@@ -141,6 +141,25 @@ int micx_debug_item(micx_ctx *ctx, const double *x, const double *y, int n,
                     double alpha, double c, int orient, int ry,
                     int *yhat, int *row_starts, int *k, int *K, int *ends);
 
+/* Instrumentation of the pair calls (micx_allpairs, micx_pairs).
+ * With profiling enabled, each call records HIP events on its stream around
+ * every launch of the dynamic-program kernel and counts the algorithmic work
+ * of its items from their actual sizes (K (super)clumps, yhat rows, x
+ * columns): dp_cells = sum (x-1) K(K+1)/2 (one add and one min each),
+ * h_evals = sum K(K+1)/2 column costs, h_terms = sum (yhat+1) K(K+1)/2
+ * table terms.  micx_get_profile() returns the totals of the last call. */
+typedef struct {
+    int64_t items;        /* (pair, orientation, y) items */
+    int64_t dp_cells;     /* DP cell updates */
+    int64_t h_evals;      /* column cost evaluations h(s,t) */
+    int64_t h_terms;      /* x ln x table terms read by those evaluations */
+    double dp_ms;         /* summed duration of the DP kernel launches (HIP events) */
+    int dp_launches;      /* number of DP kernel launches */
+} micx_profile;
+
+int micx_set_profiling(micx_ctx *ctx, int enable);
+int micx_get_profile(micx_ctx *ctx, micx_profile *out);
+
 /* Message for a return code (static string). */
 const char *micx_strerror(int code);
 

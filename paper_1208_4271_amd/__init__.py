@@ -34,6 +34,7 @@ EXPORTS = (
     "micx_ctx_create", "micx_ctx_destroy", "micx_check_param", "micx_grid_bound",
     "micx_compute_score", "micx_mic", "micx_mas", "micx_mev", "micx_mcn", "micx_free_score",
     "micx_allpairs", "micx_pairs", "micx_debug_item", "micx_strerror",
+    "micx_set_profiling", "micx_get_profile",
 )
 
 
@@ -47,6 +48,12 @@ class _Score(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("B", ctypes.c_int), ("W", ctypes.c_int),
                 ("M", ctypes.POINTER(ctypes.c_double)), ("Axy", ctypes.POINTER(ctypes.c_double)),
                 ("Ayx", ctypes.POINTER(ctypes.c_double)), ("stats", ctypes.c_double * 4)]
+
+
+class _Profile(ctypes.Structure):
+    _fields_ = [("items", ctypes.c_int64), ("dp_cells", ctypes.c_int64),
+                ("h_evals", ctypes.c_int64), ("h_terms", ctypes.c_int64),
+                ("dp_ms", ctypes.c_double), ("dp_launches", ctypes.c_int)]
 
 
 _lib = None
@@ -90,6 +97,10 @@ def load_library():
     lib.micx_debug_item.argtypes = [vp, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_int, ctypes.c_int, ip, ip, ip, ip, ip]
     lib.micx_debug_item.restype = ctypes.c_int
+    lib.micx_set_profiling.argtypes = [vp, ctypes.c_int]
+    lib.micx_set_profiling.restype = ctypes.c_int
+    lib.micx_get_profile.argtypes = [vp, P(_Profile)]
+    lib.micx_get_profile.restype = ctypes.c_int
     lib.micx_strerror.argtypes = [ctypes.c_int]
     lib.micx_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -225,3 +236,16 @@ def debug_item(x, y, alpha: float, c: float, orient: int, ry: int, device: int =
                                           ends.ctypes.data_as(ip)), "micx_debug_item")
     return {"yhat": yhat.value, "row_starts": rs[: yhat.value + 1].copy(), "k": k.value,
             "K": K.value, "ends": ends[: K.value].copy()}
+
+
+def set_profiling(enable: bool = True, device: int = 0):
+    """Record DP kernel time (HIP events) and algorithmic work in pair calls."""
+    _check(load_library().micx_set_profiling(context(device), 1 if enable else 0),
+           "micx_set_profiling")
+
+
+def get_profile(device: int = 0) -> dict:
+    """Totals of the last pair call: items, dp_cells, h_evals, h_terms, dp_ms, dp_launches."""
+    p = _Profile()
+    _check(load_library().micx_get_profile(context(device), ctypes.byref(p)), "micx_get_profile")
+    return {k: getattr(p, k) for k, _ in _Profile._fields_}

@@ -52,6 +52,9 @@ struct micx_ctx {
     DevBuf perm, gsize, grank, rowof, yhat, rowstart, xlogx, status;
     DevBuf geo;        // xcnt | khat | koff | aoff
     DevBuf cbuf, sbuf, Kb, kb, srcb, A, scratch, pairs, input, out, dense;
+    DevBuf counters;
+    int profiling = 0;
+    micx_profile prof = {};
 };
 
 #define HIPCHK(expr)                                   \
@@ -108,7 +111,8 @@ extern "C" void micx_ctx_destroy(micx_ctx *c) {
     hipSetDevice(c->device);
     DevBuf *all[] = {&c->perm, &c->gsize, &c->grank, &c->rowof, &c->yhat, &c->rowstart,
                      &c->xlogx, &c->status, &c->geo, &c->cbuf, &c->sbuf, &c->Kb, &c->kb,
-                     &c->srcb, &c->A, &c->scratch, &c->pairs, &c->input, &c->out, &c->dense};
+                     &c->srcb, &c->A, &c->scratch, &c->pairs, &c->input, &c->out, &c->dense,
+                     &c->counters};
     for (DevBuf *b : all) b->release();
     delete c;
 }
@@ -260,6 +264,14 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
     const int64_t items_per_batch = (int64_t)pb * 2 * g.NY;
     const int nslots = (int)std::min<int64_t>(ctx->max_slots, items_per_batch);
     RETCHK(ctx->scratch.ensure((size_t)nslots * slot * sizeof(double)));
+    std::vector<hipEvent_t> ev;
+    unsigned long long *counters = nullptr;
+    ctx->prof = micx_profile{};
+    if (ctx->profiling) {
+        RETCHK(ctx->counters.ensure(4 * sizeof(unsigned long long)));
+        counters = ctx->counters.as<unsigned long long>();
+        HIPCHK(hipMemsetAsync(counters, 0, 4 * sizeof(unsigned long long), s));
+    }
     for (int64_t p0 = 0; p0 < npairs; p0 += pb) {
         const int np = (int)std::min<int64_t>(pb, npairs - p0);
         PairSource ps;
@@ -272,9 +284,37 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
             ps.p0 = p0;
         }
         HIPCHK(launch_part(rt, et, g, ps, np, ib, s));
+        if (counters) HIPCHK(launch_work(et, g, ps, np, ib, counters, s));
+        if (ctx->profiling) {
+            hipEvent_t a, b;
+            HIPCHK(hipEventCreate(&a));
+            HIPCHK(hipEventCreate(&b));
+            ev.push_back(a);
+            ev.push_back(b);
+            HIPCHK(hipEventRecord(a, s));
+        }
         HIPCHK(launch_dp(rt, et, g, ps, np, ib, ctx->xlogx.as<double>(), ctx->scratch.as<double>(),
                          nslots, slot, mode, s));
+        if (ctx->profiling) HIPCHK(hipEventRecord(ev.back(), s));
         HIPCHK(launch_stats(g, np, ib, out_dev + 4 * p0, M, Axy, Ayx, s));
+    }
+    if (ctx->profiling) {
+        HIPCHK(hipStreamSynchronize(s));
+        double ms = 0.0;
+        for (size_t k = 0; k + 1 < ev.size(); k += 2) {
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+            ms += t;
+        }
+        for (hipEvent_t e : ev) hipEventDestroy(e);
+        unsigned long long h[4];
+        HIPCHK(hipMemcpy(h, counters, sizeof(h), hipMemcpyDeviceToHost));
+        ctx->prof.items = (int64_t)h[0];
+        ctx->prof.dp_cells = (int64_t)h[1];
+        ctx->prof.h_evals = (int64_t)h[2];
+        ctx->prof.h_terms = (int64_t)h[3];
+        ctx->prof.dp_ms = ms;
+        ctx->prof.dp_launches = (int)(ev.size() / 2);
     }
     return MICX_OK;
 }
@@ -380,6 +420,18 @@ extern "C" int micx_compute_score(micx_ctx *ctx, const double *x, const double *
     memcpy(sc->Axy, h.data() + 4 + WW, WW * sizeof(double));
     memcpy(sc->Ayx, h.data() + 4 + 2 * WW, WW * sizeof(double));
     *out = sc;
+    return MICX_OK;
+}
+
+extern "C" int micx_set_profiling(micx_ctx *ctx, int enable) {
+    if (!ctx) return MICX_EINVAL;
+    ctx->profiling = enable ? 1 : 0;
+    return MICX_OK;
+}
+
+extern "C" int micx_get_profile(micx_ctx *ctx, micx_profile *out) {
+    if (!ctx || !out) return MICX_EINVAL;
+    *out = ctx->prof;
     return MICX_OK;
 }
 

@@ -486,7 +486,50 @@ __global__ void k_stats(StatsArgs a) {
     }
 }
 
+// ------------------------------------------------------------------- k_work
+// Algorithmic work of a batch (instrumentation): per item, K(K+1)/2 column
+// costs, (x-1) of DP cell updates for each, and yhat+1 table terms each.
+
+__global__ void k_work(int npairs, int NY, PairSource ps, const int *xcnt, const int *yhat,
+                       const int *K, unsigned long long *counters) {
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long c1 = 0, c2 = 0, c3 = 0, c0 = 0;
+    if (it < (int64_t)npairs * 2 * NY) {
+        const int yi = (int)(it % NY);
+        const int po = (int)(it / NY);
+        int pi, pj;
+        pair_of(ps, po >> 1, pi, pj);
+        const int V = (po & 1) ? pi : pj;
+        const unsigned long long k = (unsigned long long)K[it];
+        const unsigned long long pairs = k * (k + 1) / 2;
+        c0 = 1;
+        c1 = (unsigned long long)(xcnt[yi] - 1) * pairs;
+        c2 = pairs;
+        c3 = (unsigned long long)(yhat[(size_t)V * NY + yi] + 1) * pairs;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        c0 += __shfl_down(c0, off);
+        c1 += __shfl_down(c1, off);
+        c2 += __shfl_down(c2, off);
+        c3 += __shfl_down(c3, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&counters[0], c0);
+        atomicAdd(&counters[1], c1);
+        atomicAdd(&counters[2], c2);
+        atomicAdd(&counters[3], c3);
+    }
+}
+
 // ---------------------------------------------------------------- launchers
+
+hipError_t launch_work(const EquipTables &et, const Geometry &g, PairSource ps, int npairs,
+                       const ItemBuffers &ib, unsigned long long *counters, hipStream_t s) {
+    const int64_t items = (int64_t)npairs * 2 * g.NY;
+    hipLaunchKernelGGL(k_work, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, npairs, g.NY,
+                       ps, g.xcnt, et.yhat, ib.K, counters);
+    return hipGetLastError();
+}
 
 hipError_t launch_xlogx(int n, double *xlogx, hipStream_t s) {
     hipLaunchKernelGGL(k_xlogx, dim3((n + 256) / 256), dim3(256), 0, s, n, xlogx);
