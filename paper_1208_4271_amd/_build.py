@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmicx.so")
-SOURCES = ["micx_api.hip", "micx_kernels.hip"]
+SOURCES = ["micx_api.hip", "micx_kernels.hip", "micx_dp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -48,7 +48,7 @@ struct DevBuf {
 
 struct micx_ctx {
     int device = 0;
-    int max_slots = 1024;
+    int cus = 256;
     DevBuf perm, gsize, grank, rowof, yhat, rowstart, xlogx, status;
     DevBuf geo;        // xcnt | khat | koff | aoff
     DevBuf cbuf, sbuf, Kb, kb, srcb, A, scratch, pairs, input, out, dense;
@@ -101,7 +101,7 @@ extern "C" int micx_ctx_create(micx_ctx **ctx, int device) {
         delete c;
         return MICX_EDEVICE;
     }
-    c->max_slots = dp_max_slots(device);
+    c->cus = device_cus(device);
     *ctx = c;
     return MICX_OK;
 }
@@ -157,6 +157,7 @@ void make_geometry(int n, int B, double c, HostGeometry &hg) {
     g.ASUM = as;
     g.KMAX = kmax;
     g.KYMAX = kymax;
+    g.khat_host = hg.khat.data();
 }
 
 int upload_geometry(micx_ctx *ctx, HostGeometry &hg) {
@@ -253,17 +254,23 @@ int ensure_items(micx_ctx *ctx, const Geometry &g, int pb, ItemBuffers &ib) {
     return MICX_OK;
 }
 
-// Runs clumps, DP and statistics for npairs pairs in batches.
+// Runs clumps, DP and statistics for npairs pairs in batches.  The DP runs
+// one launch per row count y, each with its own kernel shape.
 int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const Geometry &g,
               const int32_t *pairs_dev, int64_t npairs, int m, int mode, double *out_dev,
               double *M, double *Axy, double *Ayx, hipStream_t s) {
     const int pb = batch_pairs(g, npairs);
     ItemBuffers ib;
     RETCHK(ensure_items(ctx, g, pb, ib));
-    const size_t slot = (size_t)(g.xmax + 1) * (size_t)(g.KMAX + 1);
-    const int64_t items_per_batch = (int64_t)pb * 2 * g.NY;
-    const int nslots = (int)std::min<int64_t>(ctx->max_slots, items_per_batch);
-    RETCHK(ctx->scratch.ensure((size_t)nslots * slot * sizeof(double)));
+    std::vector<DpPlan> plans(g.NY);
+    size_t scratch = 0;
+    for (int yi = 0; yi < g.NY; yi++) {
+        plans[yi] = dp_plan(g, rt.n, yi, ctx->cus);
+        const size_t waves = (size_t)std::min<int64_t>(plans[yi].max_waves, 2 * (int64_t)pb);
+        const size_t w = ((waves + plans[yi].WPB - 1) / plans[yi].WPB) * plans[yi].WPB;
+        scratch = std::max(scratch, w * plans[yi].slot);
+    }
+    RETCHK(ctx->scratch.ensure(scratch * sizeof(double)));
     std::vector<hipEvent_t> ev;
     unsigned long long *counters = nullptr;
     ctx->prof = micx_profile{};
@@ -285,17 +292,19 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
         }
         HIPCHK(launch_part(rt, et, g, ps, np, ib, s));
         if (counters) HIPCHK(launch_work(et, g, ps, np, ib, counters, s));
-        if (ctx->profiling) {
-            hipEvent_t a, b;
-            HIPCHK(hipEventCreate(&a));
-            HIPCHK(hipEventCreate(&b));
-            ev.push_back(a);
-            ev.push_back(b);
-            HIPCHK(hipEventRecord(a, s));
+        for (int yi = 0; yi < g.NY; yi++) {
+            if (ctx->profiling) {
+                hipEvent_t a, b;
+                HIPCHK(hipEventCreate(&a));
+                HIPCHK(hipEventCreate(&b));
+                ev.push_back(a);
+                ev.push_back(b);
+                HIPCHK(hipEventRecord(a, s));
+            }
+            HIPCHK(launch_dp(rt, et, g, ps, np, ib, ctx->xlogx.as<double>(),
+                             ctx->scratch.as<double>(), yi, plans[yi], mode, s));
+            if (ctx->profiling) HIPCHK(hipEventRecord(ev.back(), s));
         }
-        HIPCHK(launch_dp(rt, et, g, ps, np, ib, ctx->xlogx.as<double>(), ctx->scratch.as<double>(),
-                         nslots, slot, mode, s));
-        if (ctx->profiling) HIPCHK(hipEventRecord(ev.back(), s));
         HIPCHK(launch_stats(g, np, ib, out_dev + 4 * p0, M, Axy, Ayx, s));
     }
     if (ctx->profiling) {

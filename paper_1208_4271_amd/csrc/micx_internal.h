@@ -35,6 +35,17 @@ struct Geometry {
     int *koff = nullptr;   // offsets of per-item end buffers inside one (pair, orientation)
     int *aoff = nullptr;   // offsets of per-item score rows inside one (pair, orientation)
     int KSUM = 0, ASUM = 0, KMAX = 0, KYMAX = 0;   // sums and maxima over y
+    const int *khat_host = nullptr;                // khat per y-2 (host copy)
+};
+
+// Launch shape of the DP for one row count y.
+struct DpPlan {
+    int NL = 0, YR = 0, T = 0;    // kernel template: layers per pass, rows in registers, targets per lane
+    int x = 0, KS = 0, RS = 0;    // columns, G-table row stride, count-record stride
+    int SB = 0, WPB = 0;          // sources staged per block, wavefronts per workgroup
+    int lds = 0, lds_L = 0, lds_stage = 0, lds_pub = 0, lds_wave = 0;
+    int blocks_per_cu = 0, max_waves = 0;
+    size_t slot = 0;              // doubles of G table per wavefront
 };
 
 // Per-batch item buffers.
@@ -60,9 +71,10 @@ hipError_t launch_rank(const void *X, int dtype, int m, int n, RankTables &rt, i
 hipError_t launch_equip(const RankTables &rt, EquipTables &et, hipStream_t s);
 hipError_t launch_part(const RankTables &rt, const EquipTables &et, const Geometry &g,
                        PairSource ps, int npairs, ItemBuffers &ib, hipStream_t s);
+DpPlan dp_plan(const Geometry &g, int n, int yi, int cus);
 hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry &g,
                      PairSource ps, int npairs, const ItemBuffers &ib, const double *xlogx,
-                     double *scratch, int nslots, size_t slot_doubles, int mode, hipStream_t s);
+                     double *scratch, int yi, const DpPlan &p, int mode, hipStream_t s);
 hipError_t launch_stats(const Geometry &g, int npairs, const ItemBuffers &ib, double *out,
                         double *M, double *Axy, double *Ayx, hipStream_t s);
 hipError_t launch_xlogx(int n, double *xlogx, hipStream_t s);
@@ -71,6 +83,6 @@ hipError_t launch_xlogx(int n, double *xlogx, hipStream_t s);
 hipError_t launch_work(const EquipTables &et, const Geometry &g, PairSource ps, int npairs,
                        const ItemBuffers &ib, unsigned long long *counters, hipStream_t s);
 
-int dp_max_slots(int device);
+int device_cus(int device);
 
 }  // namespace micx

@@ -8,15 +8,15 @@
 //   k_part   per item (pair, orientation, y), one item per lane:
 //            GetClumpsPartition (Algorithm 1) and GetSuperclumpsPartition
 //            (Algorithm 2) streamed over the points in column order
-//   k_dp     per item, one wavefront: cumulative count table (App. A item
-//            10a), column entropy terms (item 10b) and the OptimizeXAxis
+//   k_dp64   (micx_dp.hip) per item, one wavefront: cumulative count table
+//            (App. A item 10a), column costs (item 10b) and the OptimizeXAxis
 //            dynamic program over the superclump boundaries
 //   k_stats  per pair: characteristic matrix from both orientations and
 //            MIC, MAS, MEV, MCN (App. A items 1, 2, 4)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "micx_internal.h"
+#include "micx_device.h"
 
 namespace micx {
 
@@ -34,28 +34,6 @@ __device__ __forceinline__ uint64_t order_key(double d) {
     if (d == 0.0) d = 0.0;
     uint64_t b = __double_as_longlong(d);
     return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
-}
-
-__device__ __forceinline__ int64_t tri_offset(int64_t i, int64_t m) {
-    return i * m - i * (i + 1) / 2;
-}
-
-// Pair (i, j) of batch-local pair index pl.
-__device__ __forceinline__ void pair_of(const PairSource &ps, int pl, int &i, int &j) {
-    if (ps.pairs) {
-        i = ps.pairs[2 * pl];
-        j = ps.pairs[2 * pl + 1];
-        return;
-    }
-    const int64_t P = ps.p0 + pl, m = ps.m;
-    const double mm = 2.0 * (double)m - 1.0;
-    int64_t a = (int64_t)floor((mm - sqrt(mm * mm - 8.0 * (double)P)) * 0.5);
-    if (a < 0) a = 0;
-    if (a > m - 2) a = m - 2;
-    while (a + 1 <= m - 2 && tri_offset(a + 1, m) <= P) a++;
-    while (a > 0 && tri_offset(a, m) > P) a--;
-    i = (int)a;
-    j = (int)(P - tri_offset(a, m) + a + 1);
 }
 
 // ------------------------------------------------------------------ k_xlogx
@@ -289,154 +267,6 @@ __global__ __launch_bounds__(64) void k_part(PartArgs a) {
     }
 }
 
-// --------------------------------------------------------------------- k_dp
-// OptimizeXAxis (App. A item 10) for one item per wavefront.
-//
-// Cumulative counts N[t][r] (points among the first t superclumps that lie in
-// row r) are built in LDS.  The cost of a column spanning superclumps
-// (s, t] is h(s,t) = L[m] - sum_r L[n_r] with m = e_t - e_s and
-// n_r = N[t][r] - N[s][r] -- the column's point count times its row entropy.
-// G_l(t), the least total cost of the first t superclumps in at most l
-// columns, obeys G_1(t) = h(0,t), G_l(t) = min_{0 <= s < t} G_{l-1}(s) + h(s,t)
-// with G_{l-1}(0) = 0; then I_l = H(Q) - G_l(K)/n.
-//
-// Lanes own targets t in chunks of 64; the layers of a pass (up to XB) live
-// in registers.  Sources from earlier chunks are final and are read from the
-// item's G table in global scratch; sources inside the chunk are taken in
-// order, the owning lane publishing its layers through LDS.
-
-struct DpArgs {
-    int n, NY, KSUM, ASUM, KMAX, YH;
-    int64_t nitems;
-    int npairs;
-    PairSource ps;
-    const int *perm, *grank;
-    const uint16_t *rowof;
-    const int *yhat, *xcnt, *koff, *aoff;
-    const int *cbuf, *sbuf, *K, *src;
-    double *A;
-    const double *xlogx;
-    double *scratch;
-    size_t slot;
-};
-
-template <int XB>
-__global__ __launch_bounds__(64) void k_dp64(DpArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int n = a.n;
-    double *L = (double *)smem;         // n+1
-    double *buf = L + (n + 1);           // XB
-    int *e = (int *)(buf + XB);          // KMAX+1
-    int *N = e + (a.KMAX + 1);           // (KMAX+1) * YH
-    const int lane = threadIdx.x;
-    for (int j = lane; j <= n; j += 64) L[j] = a.xlogx[j];
-    __syncthreads();
-    double *G = a.scratch + (size_t)blockIdx.x * a.slot;
-    const int64_t per_y = 2 * (int64_t)a.npairs;
-
-    for (int64_t item = blockIdx.x; item < a.nitems; item += gridDim.x) {
-        const int yi = (int)(item / per_y);
-        const int po = (int)(item % per_y);
-        const int o = po & 1, pl = po >> 1;
-        int pi, pj;
-        pair_of(a.ps, pl, pi, pj);
-        const int U = o ? pj : pi, V = o ? pi : pj;
-        const int x = a.xcnt[yi];
-        const size_t it = (size_t)po * a.NY + yi;
-        const int K = a.K[it];
-        const int yh = a.yhat[(size_t)V * a.NY + yi];
-        const int *ends = (a.src[it] ? a.sbuf : a.cbuf) + (size_t)po * a.KSUM + a.koff[yi];
-
-        if (lane == 0) e[0] = 0;
-        for (int t = lane; t < K; t += 64) e[t + 1] = ends[t];
-        for (int q = lane; q < (K + 1) * yh; q += 64) N[q] = 0;
-        __syncthreads();
-        const int *permU = a.perm + (size_t)U * n;
-        const int *grV = a.grank + (size_t)V * n;
-        const uint16_t *rowV = a.rowof + (size_t)V * n * a.NY + yi;
-        for (int p = lane; p < n; p += 64) {
-            const int g = grV[permU[p]];
-            const int r = rowV[(size_t)g * a.NY];
-            int lo = 1, hi = K;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (e[mid] > p) hi = mid; else lo = mid + 1;
-            }
-            atomicAdd(&N[lo * yh + r], 1);
-        }
-        __syncthreads();
-        for (int r = lane; r < yh; r += 64) {
-            int run = 0;
-            for (int t = 1; t <= K; t++) {
-                run += N[t * yh + r];
-                N[t * yh + r] = run;
-            }
-        }
-        __syncthreads();
-
-        auto hcost = [&](int s, int t) -> double {
-            double acc = L[e[t] - e[s]];
-            const int *Nt = N + t * yh, *Ns = N + s * yh;
-            for (int r = 0; r < yh; r++) acc -= L[Nt[r] - Ns[r]];
-            return acc;
-        };
-
-        const size_t K1 = (size_t)K + 1;
-        for (int t = lane + 1; t <= K; t += 64) G[K1 + t] = hcost(0, t);
-        __syncthreads();
-        for (int l0 = 2; l0 <= x; l0 += XB) {
-            const int nl = min(XB, x - l0 + 1);
-            for (int c0 = 0; c0 < K; c0 += 64) {
-                const int t = c0 + 1 + lane;
-                const bool act = t <= K;
-                double g[XB];
-                const double h0 = act ? hcost(0, t) : 0.0;
-#pragma unroll
-                for (int jj = 0; jj < XB; jj++) g[jj] = h0;
-                for (int s = 1; s <= c0; s++) {
-                    const double hs = act ? hcost(s, t) : 0.0;
-                    const double *Gs = G + (size_t)(l0 - 1) * K1 + s;
-#pragma unroll
-                    for (int jj = 0; jj < XB; jj++)
-                        if (jj < nl) g[jj] = fmin(g[jj], Gs[(size_t)jj * K1] + hs);
-                }
-                const int cend = min(c0 + 64, K);
-                for (int s = c0 + 1; s < cend; s++) {
-                    if (lane == s - c0 - 1) {
-#pragma unroll
-                        for (int jj = 0; jj + 1 < XB; jj++) buf[jj] = g[jj];
-                    }
-                    __syncthreads();
-                    if (act && t > s) {
-                        const double hs = hcost(s, t);
-                        g[0] = fmin(g[0], G[(size_t)(l0 - 1) * K1 + s] + hs);
-#pragma unroll
-                        for (int jj = 1; jj < XB; jj++)
-                            if (jj < nl) g[jj] = fmin(g[jj], buf[jj - 1] + hs);
-                    }
-                    __syncthreads();
-                }
-                if (act) {
-#pragma unroll
-                    for (int jj = 0; jj < XB; jj++)
-                        if (jj < nl) G[(size_t)(l0 + jj) * K1 + t] = g[jj];
-                }
-                __syncthreads();
-            }
-        }
-        // I_l = (L[n] - sum_r L[q_r] - G_l(K)) / n, normalised by ln min(l, yhat)
-        double sq = 0.0;
-        for (int r = 0; r < yh; r++) sq += L[N[K * yh + r]];
-        double *Aout = a.A + (size_t)po * a.ASUM + a.aoff[yi];
-        for (int l = 2 + lane; l <= x; l += 64) {
-            const double I = (L[n] - sq - G[(size_t)l * K1 + K]) / (double)n;
-            const int norm = min(l, yh);
-            Aout[l - 2] = norm >= 2 ? I / log((double)norm) : 0.0;
-        }
-        __syncthreads();
-    }
-}
-
 // ------------------------------------------------------------------ k_stats
 // Characteristic matrix and statistics of one pair per thread.
 // M_{x,y} (x bins of the first variable, y of the second) is the larger of
@@ -569,30 +399,6 @@ hipError_t launch_part(const RankTables &rt, const EquipTables &et, const Geomet
     return hipGetLastError();
 }
 
-static const int kXB = 16;
-
-hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry &g,
-                     PairSource ps, int npairs, const ItemBuffers &ib, const double *xlogx,
-                     double *scratch, int nslots, size_t slot_doubles, int mode, hipStream_t s) {
-    (void)mode;
-    DpArgs a;
-    a.n = rt.n; a.NY = g.NY; a.KSUM = g.KSUM; a.ASUM = g.ASUM; a.KMAX = g.KMAX; a.YH = g.NY + 1;
-    a.nitems = (int64_t)npairs * 2 * g.NY;
-    a.npairs = npairs; a.ps = ps;
-    a.perm = rt.perm; a.grank = rt.grank; a.rowof = et.rowof; a.yhat = et.yhat;
-    a.xcnt = g.xcnt; a.koff = g.koff; a.aoff = g.aoff;
-    a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.src = ib.src; a.A = ib.A;
-    a.xlogx = xlogx; a.scratch = scratch; a.slot = slot_doubles;
-    const size_t lds = (size_t)(rt.n + 1) * 8 + kXB * 8 + (size_t)(g.KMAX + 1) * 4 +
-                       (size_t)g.KYMAX * 4;
-    hipError_t e = hipFuncSetAttribute((const void *)k_dp64<kXB>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    int64_t grid = a.nitems < nslots ? a.nitems : nslots;
-    hipLaunchKernelGGL(k_dp64<kXB>, dim3((unsigned)grid), dim3(64), lds, s, a);
-    return hipGetLastError();
-}
-
 hipError_t launch_stats(const Geometry &g, int npairs, const ItemBuffers &ib, double *out,
                         double *M, double *Axy, double *Ayx, hipStream_t s) {
     StatsArgs a;
@@ -602,10 +408,10 @@ hipError_t launch_stats(const Geometry &g, int npairs, const ItemBuffers &ib, do
     return hipGetLastError();
 }
 
-int dp_max_slots(int device) {
+int device_cus(int device) {
     hipDeviceProp_t p;
-    if (hipGetDeviceProperties(&p, device) != hipSuccess) return 1024;
-    return p.multiProcessorCount * 8;
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) return 256;
+    return p.multiProcessorCount;
 }
 
 }  // namespace micx
