@@ -145,9 +145,11 @@ int micx_debug_item(micx_ctx *ctx, const double *x, const double *y, int n,
  * With profiling enabled, each call records HIP events on its stream around
  * every launch of the dynamic-program kernel and counts the algorithmic work
  * of its items from their actual sizes (K (super)clumps, yhat rows, x
- * columns): dp_cells = sum (x-1) K(K+1)/2 (one add and one min each),
- * h_evals = sum K(K+1)/2 column costs, h_terms = sum (yhat+1) K(K+1)/2
- * table terms.  micx_get_profile() returns the totals of the last call. */
+ * columns).  Layers 2..x-1 are needed at every target and layer x only at
+ * the last one, so dp_cells = sum (x-2) K(K+1)/2 + K (one add and one min
+ * each); h_evals = sum of the column costs needed (K(K+1)/2 when x >= 3,
+ * else 2K-1); h_terms = sum (yhat+1) h_evals table terms.
+ * micx_get_profile() returns the totals of the last call. */
 typedef struct {
     int64_t items;        /* (pair, orientation, y) items */
     int64_t dp_cells;     /* DP cell updates */

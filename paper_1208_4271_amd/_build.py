@@ -9,7 +9,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmicx.so")
-SOURCES = ["micx_api.hip", "micx_kernels.hip", "micx_dp.hip"]
+SOURCES = ["micx_api.hip", "micx_kernels.hip", "micx_dp.hip", "micx_dp_i0.hip", "micx_dp_i1.hip",
+           "micx_dp_i2.hip", "micx_dp_i3.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -25,18 +26,43 @@ def flags():
     ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into paper_1208_4271_amd/libmicx.so."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + flags() + ["-o", tmp] + srcs
+# Extra flags per source.  The DP takes minima of finite values only, so it is
+# compiled without NaN semantics (v_min_f64 needs no operand canonicalisation).
+EXTRA = {s: ["-fno-honor-nans"] for s in SOURCES if s.startswith("micx_dp")}
+
+
+def _compile(src, obj, verbose, defines=()):
+    cmd = [HIPCC] + flags() + EXTRA.get(src, []) + list(defines) + ["-c", "-o", obj,
+                                                                     os.path.join(CSRC, src)]
+    cmd = [c for c in cmd if c != "-shared"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+        raise RuntimeError("hipcc failed on %s:\n%s%s" % (src, res.stdout, res.stderr))
+    return obj
+
+
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile every HIP source (in parallel) and link paper_1208_4271_amd/libmicx.so
+    (or `out`; `defines` are extra -D flags for the build-time tuning knobs)."""
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(os.path.dirname(os.path.abspath(out)), "_build",
+                          os.path.basename(out).replace(".so", ""))
+    os.makedirs(objdir, exist_ok=True)
+    objs = [os.path.join(objdir, s.replace(".hip", ".o")) for s in SOURCES]
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        list(ex.map(lambda so: _compile(so[0], so[1], verbose, defines), zip(SOURCES, objs)))
+    LIBOUT = out
+    tmp = LIBOUT + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("link failed:\n" + res.stdout + res.stderr)
+    os.replace(tmp, LIBOUT)
+    return LIBOUT
 
 
 if __name__ == "__main__":

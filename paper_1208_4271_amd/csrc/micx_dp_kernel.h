@@ -1,0 +1,311 @@
+// micx_dp_kernel.h -- the OptimizeXAxis dynamic program (Albanese et al. 2012,
+// Appendix A item 10) for every (pair, orientation) item of one row count y.
+//
+// Per item (one wavefront):
+//  * item 10a: cumulative counts N[t][r] -- points among the first t
+//    (super)clumps that lie in row r -- built in LDS from the superclump ends
+//    and the row labels (a flag scan gives each point's superclump, LDS
+//    atomics count, a wavefront scan accumulates over t);
+//  * item 10b: the column cost h(s,t) = L[m] - sum_r L[n_r], m = e_t - e_s,
+//    n_r = N[t][r] - N[s][r], L[j] = j ln j: the span's point count times its
+//    row entropy, computed once per (s,t) and used for every layer;
+//  * the DP: G_1(t) = h(0,t), G_l(t) = min_{0 <= s < t} G_{l-1}(s) + h(s,t)
+//    with G_{l-1}(0) = 0.  G_l(K) is the least sum of column costs over
+//    partitions into at most l columns, and I_l = H(Q) - G_l(K)/n.
+//
+// Layout.  Lanes own targets t, T per lane (a chunk of 64T targets).  The
+// layers of a pass (up to NL) live in registers, as do the target's
+// cumulative counts (up to YR rows).  Sources from earlier chunks are final:
+// their layer values are staged from the item's G table (global, layer-major)
+// into LDS, SB sources at a time, and read back as wavefront-uniform
+// broadcasts.  Sources inside the chunk are taken in order; the lane that
+// owns a source publishes its layer values through LDS.
+#pragma once
+
+#include <stdlib.h>
+
+#include <algorithm>
+
+#include "micx_device.h"
+
+namespace micx {
+
+struct DpArgs {
+    int n, NY, KSUM, ASUM;
+    int yi, x, RS, KS;           // class: row count y = yi+2, x(y), rec stride y+1, G row stride
+    int nitems, npairs, SB;      // items of the class = 2 * npairs
+    PairSource ps;
+    const int *perm, *grank;
+    const uint16_t *rowof;
+    const int *yhat, *koff, *aoff;
+    const int *cbuf, *sbuf, *K, *src;
+    double *A;
+    const double *xlogx;
+    double *scratch;
+    size_t slot;                 // doubles of G table per wavefront
+    int lds_L, lds_stage, lds_pub, lds_wave;
+};
+
+// Wavefronts per SIMD the compiler must fit: the layer registers (2 VGPRs per
+// double, T targets) set the budget, and more resident wavefronts hide the
+// LDS latency of the broadcasts and table gathers.
+// Build-time tuning knobs: MICX_DP_MINWAVES_EXTRA (registers assumed beyond
+// the layer array when choosing the occupancy target; 0 disables the target)
+// and MICX_DP_GROUP (layers per scheduling group).
+#ifndef MICX_DP_MINWAVES_EXTRA
+#define MICX_DP_MINWAVES_EXTRA 80
+#endif
+#ifndef MICX_DP_GROUP
+#define MICX_DP_GROUP 8
+#endif
+
+template <int NL, int T>
+constexpr int dp_min_waves() {
+    constexpr int need = T * ((NL + 1) & ~1) * 2 + MICX_DP_MINWAVES_EXTRA;
+    return MICX_DP_MINWAVES_EXTRA == 0 ? 1 : (need <= 128 ? 4 : (need <= 168 ? 3 : (need <= 256 ? 2 : 1)));
+}
+
+// Layers per scheduling group: the broadcasts of one group are loaded, then
+// its cells update, so only one group's operands are live at a time.
+constexpr int DP_GROUP = MICX_DP_GROUP;
+
+template <int NL, int YR, int T>
+__global__ __launch_bounds__(256, (dp_min_waves<NL, T>())) void k_dp64(DpArgs a) {
+    constexpr int NLP = (NL + 1) & ~1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = a.n, NY = a.NY, RS = a.RS, KS = a.KS, x = a.x, yi = a.yi, SB = a.SB;
+    const int sbs = __builtin_ctz(SB);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double *L = (double *)smem;
+    for (int j = threadIdx.x; j <= n; j += blockDim.x) L[j] = a.xlogx[j];
+    __syncthreads();
+    unsigned char *wb = smem + a.lds_L + (size_t)wv * a.lds_wave;
+    double *stage = (double *)wb;                              // SB x NLP, or n flag bytes
+    double *pub = (double *)(wb + a.lds_stage);                // NLP
+    int *rec = (int *)(wb + a.lds_stage + a.lds_pub);          // (K+1) x RS: e_t, N_t[0..RS-2]
+    const int wpb = blockDim.x >> 6;
+    const int gw = blockIdx.x * wpb + wv, nw = gridDim.x * wpb;
+    double *G = a.scratch + (size_t)gw * a.slot;
+
+    for (int po = gw; po < a.nitems; po += nw) {
+        const int o = po & 1, pl = po >> 1;
+        int pi, pj;
+        pair_of(a.ps, pl, pi, pj);
+        const int U = o ? pj : pi, V = o ? pi : pj;
+        const size_t it = (size_t)po * NY + yi;
+        const int K = a.K[it];
+        const int yh = a.yhat[(size_t)V * NY + yi];
+        const int *ends = (a.src[it] ? a.sbuf : a.cbuf) + (size_t)po * a.KSUM + a.koff[yi];
+
+        // ---- cumulative counts (item 10a); rows beyond yhat stay 0 ----
+        unsigned char *F = (unsigned char *)stage;
+        for (int k = lane; k < (K + 1) * RS; k += 64) rec[k] = 0;
+        for (int p = lane; p < n; p += 64) F[p] = 0;
+        wave_sync();
+        for (int t = lane; t < K; t += 64) {
+            const int et = ends[t];
+            rec[(t + 1) * RS] = et;
+            if (t + 1 < K) F[et] = 1;
+        }
+        wave_sync();
+        {
+            const int *permU = a.perm + (size_t)U * n;
+            const int *grV = a.grank + (size_t)V * n;
+            const uint16_t *rowV = a.rowof + (size_t)V * n * NY + yi;
+            int carry = 0;
+            for (int p0 = 0; p0 < n; p0 += 64) {
+                const int p = p0 + lane;
+                const bool f = p < n && F[p] != 0;
+                const uint64_t bal = __ballot(f);
+                const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                      __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+                if (p < n) {
+                    const int g = grV[permU[p]];
+                    const int r = rowV[(size_t)g * NY];
+                    atomicAdd(&rec[(carry + below + (f ? 1 : 0) + 1) * RS + 1 + r], 1);
+                }
+                carry += __popcll(bal);
+            }
+        }
+        wave_sync();
+        if (yh >= 8) {
+            for (int r = lane; r < yh; r += 64) {
+                int run = 0;
+                for (int t = 1; t <= K; t++) {
+                    run += rec[t * RS + 1 + r];
+                    rec[t * RS + 1 + r] = run;
+                }
+            }
+        } else {
+            for (int r = 0; r < yh; r++) {
+                int c2 = 0;
+                for (int t0 = 1; t0 <= K; t0 += 64) {
+                    const int t = t0 + lane;
+                    const int v = t <= K ? rec[t * RS + 1 + r] : 0;
+                    const int incl = wave_incl_scan(v, lane) + c2;
+                    if (t <= K) rec[t * RS + 1 + r] = incl;
+                    c2 = __shfl(incl, 63, 64);
+                }
+            }
+        }
+        wave_sync();
+
+        // column cost h(s,t) with both records read from LDS (any row count)
+        auto hcost = [&](int s, int t) -> double {
+            const int *rs = rec + s * RS, *rt = rec + t * RS;
+            double acc = L[rt[0] - rs[0]];
+            for (int r = 0; r < yh; r++) acc -= L[rt[1 + r] - rs[1 + r]];
+            return acc;
+        };
+
+        // ---- full layers l = 2..x-1 for every target (item 10b costs, OptimizeXAxis) ----
+        for (int l0 = 2; l0 <= x - 1; l0 += NL) {
+            const int nl = min(NL, x - l0);
+            const int nlp = (nl + 1) & ~1;
+            for (int c0 = 0; c0 < K; c0 += 64 * T) {
+                int tt[T], et[T];
+                int Nt[T][YR > 0 ? YR : 1];
+                double g[T][NLP], gprev[T];
+#pragma unroll
+                for (int j = 0; j < T; j++) {
+                    tt[j] = c0 + 64 * j + lane + 1;
+                    const int tc = tt[j] <= K ? tt[j] : K;
+                    const int *rt = rec + tc * RS;
+                    et[j] = rt[0];
+                    double h0 = L[et[j]];
+                    if constexpr (YR > 0) {
+#pragma unroll
+                        for (int r = 0; r < YR; r++) {
+                            Nt[j][r] = rt[1 + r];
+                            h0 -= L[Nt[j][r]];
+                        }
+                    } else {
+                        for (int r = 0; r < yh; r++) h0 -= L[rt[1 + r]];
+                    }
+                    gprev[j] = l0 == 2 ? h0 : G[(size_t)(l0 - 1) * KS + tc];
+#pragma unroll
+                    for (int q = 0; q < NLP; q++) g[j][q] = h0;
+                }
+                // h(s, t_j) for this lane's targets (count rows from registers or LDS)
+                auto hsrc = [&](int s, double (&out)[T]) {
+                    const int *rs = rec + s * RS;
+                    const int es = rs[0];
+#pragma unroll
+                    for (int j = 0; j < T; j++) out[j] = L[et[j] - es];
+                    if constexpr (YR > 0) {
+#pragma unroll
+                        for (int r = 0; r < YR; r++) {
+                            const int nsr = rs[1 + r];
+#pragma unroll
+                            for (int j = 0; j < T; j++) out[j] -= L[Nt[j][r] - nsr];
+                        }
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < T; j++) out[j] = hcost(s, tt[j] <= K ? tt[j] : K);
+                    }
+                };
+                // sources of earlier chunks, SB at a time through LDS; the next
+                // source's costs are gathered while this source's cells update
+                constexpr int UNR = (NL >= 16 || YR >= 16) ? 1 : 2;
+                for (int sb = 1; sb <= c0; sb += SB) {
+                    const int ns = min(SB, c0 - sb + 1);
+                    for (int k = lane; k < nlp * SB; k += 64) {
+                        const int q = k >> sbs, sl = k & (SB - 1);
+                        stage[sl * NLP + q] =
+                            (sl < ns && q < nl) ? G[(size_t)(l0 - 1 + q) * KS + sb + sl] : 0.0;
+                    }
+                    wave_sync();
+                    double hc[T], hn[T];
+                    hsrc(sb, hc);
+#pragma unroll UNR
+                    for (int sl = 0; sl < ns; sl++) {
+                        hsrc(sb + min(sl + 1, ns - 1), hn);
+                        const double *gs = stage + sl * NLP;
+#pragma unroll
+                        for (int q = 0; q < NLP; q += 2) {
+                            const double2 v = *(const double2 *)(gs + q);
+#pragma unroll
+                            for (int j = 0; j < T; j++) {
+                                g[j][q] = fmin(g[j][q], v.x + hc[j]);
+                                g[j][q + 1] = fmin(g[j][q + 1], v.y + hc[j]);
+                            }
+                            if ((q + 2) % DP_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
+                        }
+#pragma unroll
+                        for (int j = 0; j < T; j++) hc[j] = hn[j];
+                    }
+                    wave_sync();
+                }
+                // sources inside the chunk, in order: the owning lane publishes
+                // the source's layers; the costs are gathered before the wait
+#pragma unroll
+                for (int jo = 0; jo < T; jo++) {
+                    const int sbeg = c0 + 64 * jo + 1;
+                    // the chunk's last target is no source for any target of this chunk
+                    const int send = min(c0 + 64 * jo + 64, min(c0 + 64 * T, K) - 1);
+                    for (int s = sbeg; s <= send; s++) {
+                        const int ln = s - sbeg;
+                        double hs[T];
+                        hsrc(s, hs);
+                        if (lane == ln) {
+                            double2 *pv = (double2 *)pub;
+                            pv[0] = make_double2(gprev[jo], g[jo][0]);
+#pragma unroll
+                            for (int q = 2; q < NLP; q += 2) pv[q >> 1] = make_double2(g[jo][q - 1], g[jo][q]);
+                        }
+                        wave_sync();
+#pragma unroll
+                        for (int j = jo; j < T; j++) {
+                            if (j == jo && lane <= ln) continue;
+#pragma unroll
+                            for (int q = 0; q < NLP; q += 2) {
+                                const double2 v = *(const double2 *)(pub + q);
+                                g[j][q] = fmin(g[j][q], v.x + hs[j]);
+                                g[j][q + 1] = fmin(g[j][q + 1], v.y + hs[j]);
+                                if ((q + 2) % DP_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
+                            }
+                        }
+                        wave_sync();
+                    }
+                }
+                // the chunk's layers become sources for later chunks
+#pragma unroll
+                for (int j = 0; j < T; j++) {
+                    if (tt[j] <= K) {
+                        if (l0 == 2) G[(size_t)KS + tt[j]] = gprev[j];
+#pragma unroll
+                        for (int q = 0; q < NLP; q++)
+                            if (q < nl) G[(size_t)(l0 + q) * KS + tt[j]] = g[j][q];
+                    }
+                }
+                global_sync();
+            }
+        }
+
+        // ---- last layer only at t = K: G_x(K) = min_{0 <= s < K} G_{x-1}(s) + h(s,K) ----
+        double best = INFINITY;
+        for (int s = lane; s < K; s += 64) {
+            double gs = 0.0;   // G_{x-1}(0) = 0
+            if (s > 0) gs = (x == 2) ? hcost(0, s) : G[(size_t)(x - 1) * KS + s];
+            best = fmin(best, gs + hcost(s, K));
+        }
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) best = fmin(best, __shfl_xor(best, d, 64));
+
+        // ---- I_l = (L[n] - sum_r L[q_r] - G_l(K)) / n, normalised by ln min(l, yhat) ----
+        double sq = 0.0;
+        for (int r = 0; r < yh; r++) sq += L[rec[K * RS + 1 + r]];
+        double *Aout = a.A + (size_t)po * a.ASUM + a.aoff[yi];
+        for (int l = 2 + lane; l <= x; l += 64) {
+            const double Gl = (l == x) ? best : G[(size_t)l * KS + K];
+            const double I = (L[n] - sq - Gl) / (double)n;
+            const int norm = min(l, yh);
+            Aout[l - 2] = norm >= 2 ? I / log((double)norm) : 0.0;
+        }
+        wave_sync();
+    }
+}
+
+typedef void (*dp_kernel_t)(DpArgs);
+
+}  // namespace micx

@@ -1,0 +1,13 @@
+// micx_dp_shapes.h -- the DP kernel shapes compiled into the library:
+// NL (full layers per pass) x YR (count rows held in registers; 0 = read from
+// LDS) x T (targets per lane).  Each micx_dp_i*.hip instantiates a slice.
+#pragma once
+
+#define MICX_NL_LIST(X, YR) X(1, YR) X(2, YR) X(3, YR) X(4, YR) X(5, YR) X(6, YR) X(7, YR) X(8, YR) \
+    X(10, YR) X(12, YR) X(14, YR) X(16, YR) X(20, YR) X(24, YR) X(28, YR) X(32, YR) X(36, YR)
+#define MICX_NL_SMALL(X, YR) X(1, YR) X(2, YR) X(3, YR) X(4, YR) X(5, YR) X(6, YR) X(8, YR)
+#define MICX_NL_TINY(X, YR) X(1, YR) X(2, YR) X(3, YR) X(4, YR)
+#define MICX_CASE(NLv, YRv) \
+    if (NL == NLv && YR == YRv) return T == 1 ? k_dp64<NLv, YRv, 1> : k_dp64<NLv, YRv, 2>;
+#define MICX_CASE1(NLv, YRv) \
+    if (NL == NLv && YR == YRv) return T == 1 ? k_dp64<NLv, YRv, 1> : nullptr;

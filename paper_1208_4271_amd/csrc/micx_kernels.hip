@@ -317,8 +317,12 @@ __global__ void k_stats(StatsArgs a) {
 }
 
 // ------------------------------------------------------------------- k_work
-// Algorithmic work of a batch (instrumentation): per item, K(K+1)/2 column
-// costs, (x-1) of DP cell updates for each, and yhat+1 table terms each.
+// Algorithmic work of a batch (instrumentation).  Per item with K columns, x
+// layers and yhat rows: layers 2..x-1 are needed at every target t (t
+// candidate sources each) and layer x only at t = K, so the DP has
+// (x-2) K(K+1)/2 + K cell updates; the column costs needed are all
+// K(K+1)/2 spans when x >= 3, else the 2K-1 spans starting at 0 or ending
+// at K; each cost reads yhat+1 table terms.
 
 __global__ void k_work(int npairs, int NY, PairSource ps, const int *xcnt, const int *yhat,
                        const int *K, unsigned long long *counters) {
@@ -331,11 +335,12 @@ __global__ void k_work(int npairs, int NY, PairSource ps, const int *xcnt, const
         pair_of(ps, po >> 1, pi, pj);
         const int V = (po & 1) ? pi : pj;
         const unsigned long long k = (unsigned long long)K[it];
-        const unsigned long long pairs = k * (k + 1) / 2;
+        const unsigned long long x = (unsigned long long)xcnt[yi];
+        const unsigned long long spans = k * (k + 1) / 2;
         c0 = 1;
-        c1 = (unsigned long long)(xcnt[yi] - 1) * pairs;
-        c2 = pairs;
-        c3 = (unsigned long long)(yhat[(size_t)V * NY + yi] + 1) * pairs;
+        c1 = (x - 2) * spans + k;
+        c2 = x >= 3 ? spans : 2 * k - 1;
+        c3 = (unsigned long long)(yhat[(size_t)V * NY + yi] + 1) * c2;
     }
     for (int off = 32; off > 0; off >>= 1) {
         c0 += __shfl_down(c0, off);
