@@ -8,9 +8,13 @@ micx_allpairs call over the whole matrix (input resident in HBM), which runs
 every stage: ranking, equipartition, clumps/superclumps, the OptimizeXAxis DP
 and the four statistics.
 
+Two numeric forms are timed: the 32-bit fixed-point DP (MICX_MODE_DP32,
+reported as `value` by default) and the plain FP64 DP (MICX_MODE_FP64).
 Prints one JSON line.  Besides the contract fields it carries:
-  roofline      the DP kernel against the FP64 VALU peak (HIP events on the
-                library's stream, algorithmic work counted from the items)
+  roofline      the DP kernel of the reported form against the VALU peak (HIP
+                events on the library's stream, algorithmic work counted from
+                the items)
+  forms         pairs/s, roofline fraction, error bound and parity per form
   cpu_baseline  the FP64 oracle timed on the host cores on a bounded sample
   parity        max |dMIC|, |dMAS|, |dMEV| and MCN mismatches on that sample
 """
@@ -30,7 +34,8 @@ sys.path.insert(0, ROOT)
 METRIC = "MIC pairs/s at n=1340, α=0.6, c=15 (FP32+FP64 vs FP64 GPU) + max |ΔMIC|"
 
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz -- one non-packed VALU operation per lane
-# per clock (FP64 add/min issue at this rate; FP64 FMA peak 78.6 TFLOP/s counts 2).
+# per clock (FP64 add/min and 32-bit integer add/min issue at this rate; the FP64
+# FMA peak of 78.6 TFLOP/s counts an FMA as 2).
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
@@ -39,7 +44,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", choices=("fp64", "fp32"), default="fp64")
+    ap.add_argument("--mode", choices=("fp64", "dp32"), default="dp32",
+                    help="form reported as `value`; the other form is timed beside it")
+    ap.add_argument("--only", action="store_true", help="time the --mode form only")
     ap.add_argument("--m", type=int, default=1000, help="variables (1000 = the full workload)")
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="pairs timed on the CPU oracle (0 disables the baseline)")
@@ -49,6 +56,50 @@ def parse():
 
 def pair_index(i, j, m):
     return i * m - i * (i + 1) // 2 + (j - i - 1)
+
+
+def run_form(micx, Xd, out, stream, mode, alpha, c, steps, warmup, label):
+    """Time `steps` micx_allpairs calls of one numeric form, then one
+    instrumented call.  Returns (ms_per_step, profile, host copy of the output)."""
+    import torch
+    for w in range(warmup):
+        micx.allpairs(Xd, alpha, c, mode, out=out, stream=stream)
+        print("bench: %s warmup %d done" % (label, w), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        micx.allpairs(Xd, alpha, c, mode, out=out, stream=stream)
+        print("bench: %s step %d done" % (label, s), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / max(steps, 1)
+    # one more call with the library's instrumentation on: DP kernel time from
+    # HIP events recorded on the launch stream, algorithmic work from the items
+    micx.set_profiling(True)
+    micx.allpairs(Xd, alpha, c, mode, out=out, stream=stream)
+    prof = micx.get_profile()
+    micx.set_profiling(False)
+    return ms_per_step, prof, out.cpu().numpy()
+
+
+def roofline_of(prof, kernel):
+    alg_ops = 2.0 * prof["dp_cells"] + 2.0 * prof["h_terms"]
+    dp_s = prof["dp_ms"] / 1e3
+    achieved = alg_ops / dp_s / 1e12 if dp_s > 0 else 0.0
+    return {
+        "bound": "alu", "achieved": round(achieved, 4), "peak": round(VALU_PEAK_TOPS, 4),
+        "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 5), "traffic": None,
+        "kernel": kernel, "launches": prof["dp_launches"],
+        "avg_launch_ms": round(prof["dp_ms"] / max(prof["dp_launches"], 1), 3),
+        "alg_ops": alg_ops, "dp_cells": prof["dp_cells"], "h_evals": prof["h_evals"],
+        "h_terms": prof["h_terms"], "items": prof["items"],
+    }
+
+
+def parity_of(got, ref):
+    d = np.abs(got - ref)
+    return {"pairs": int(len(ref)), "max_dMIC": float(d[:, 0].max()), "max_dMAS": float(d[:, 1].max()),
+            "max_dMEV": float(d[:, 2].max()), "mcn_mismatch": int((d[:, 3] > 1e-9).sum())}
 
 
 def main():
@@ -62,7 +113,6 @@ def main():
     import workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    mode = micx.MODE_FP64 if args.mode == "fp64" else micx.MODE_FP32_RECHECK
     alpha, c = 0.6, 15.0
     X, planted = workloads.cfg3_matrix()
     X = X[: args.m]
@@ -71,51 +121,37 @@ def main():
     Xd = torch.from_numpy(X).cuda()
     out = torch.empty((npairs, 4), dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
+    print("bench: m=%d n=%d pairs=%d warmup=%d steps=%d" %
+          (m, n, npairs, args.warmup, args.steps), file=sys.stderr, flush=True)
 
-    print("bench: m=%d n=%d pairs=%d mode=%s warmup=%d steps=%d" %
-          (m, n, npairs, args.mode, args.warmup, args.steps), file=sys.stderr, flush=True)
-    for w in range(args.warmup):
-        micx.allpairs(Xd, alpha, c, mode, out=out, stream=stream)
-        print("bench: warmup %d done" % w, file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        micx.allpairs(Xd, alpha, c, mode, out=out, stream=stream)
-        print("bench: step %d done" % s, file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / max(args.steps, 1)
-    value = npairs / (ms_per_step / 1e3)
+    forms = {}
+    order = ["dp32", "fp64"] if args.mode == "dp32" else ["fp64", "dp32"]
+    if args.only:
+        order = order[:1]
+    results = {}
+    for form in order:
+        mode = micx.MODE_DP32 if form == "dp32" else micx.MODE_FP64
+        ms, prof, host = run_form(micx, Xd, out, stream, mode, alpha, c, args.steps, args.warmup, form)
+        results[form] = (ms, prof, host)
+        forms[form] = {"value": round(npairs / (ms / 1e3), 2), "ms_per_step": round(ms, 3),
+                       "roofline_frac": roofline_of(prof, "k_dp")["frac"],
+                       "dp32_classes": prof["dp32_classes"], "fp64_classes": prof["fp64_classes"],
+                       "dp32_bound": prof["dp32_bound"]}
 
-    # One more call with the library's instrumentation on: DP kernel time from
-    # HIP events recorded on the launch stream, algorithmic work from the items.
-    micx.set_profiling(True)
-    micx.allpairs(Xd, alpha, c, mode, out=out, stream=stream)
-    prof = micx.get_profile()
-    micx.set_profiling(False)
-    gpu = out.cpu().numpy()
-    alg_ops = 2.0 * prof["dp_cells"] + 2.0 * prof["h_terms"]
-    dp_s = prof["dp_ms"] / 1e3
-    achieved = alg_ops / dp_s / 1e12 if dp_s > 0 else 0.0
-    roofline = {
-        "bound": "alu", "achieved": round(achieved, 4), "peak": round(VALU_PEAK_TOPS, 4),
-        "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 5), "traffic": None,
-        "kernel": "k_dp64", "launches": prof["dp_launches"],
-        "avg_launch_ms": round(prof["dp_ms"] / max(prof["dp_launches"], 1), 3),
-        "alg_ops": alg_ops, "dp_cells": prof["dp_cells"], "h_evals": prof["h_evals"],
-        "h_terms": prof["h_terms"], "items": prof["items"],
-    }
-
+    main_form = order[0]
+    ms, prof, host = results[main_form]
+    value = npairs / (ms / 1e3)
     result = {
         "metric": METRIC, "value": round(value, 2), "unit": "pairs/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.mode == "fp64" else "f32+f64", "data": "synthetic",
+        "dtype": "f64" if main_form == "fp64" else "u32+f64", "data": "synthetic",
         "config": {"workload": "microarray-shaped all-pairs: m=%d x n=%d float64 log-normal "
                                "rounded to 2 decimals, 50 planted pairs" % (m, n),
                    "m": m, "n": n, "pairs": npairs, "alpha": alpha, "c": c,
-                   "mode": args.mode, "parallelism": "single GPU"},
-        "roofline": roofline,
+                   "form": main_form, "parallelism": "single GPU"},
+        "roofline": roofline_of(prof, "k_dp<%s>" % ("double" if main_form == "fp64" else "uint32_t")),
+        "forms": forms,
     }
 
     if args.cpu_sample > 0:
@@ -132,18 +168,16 @@ def main():
         t0 = time.perf_counter()
         ref = oracle.allpairs(X, alpha, c, pairs=np.array(sample), nthreads=threads)
         cpu_s = time.perf_counter() - t0
-        got = gpu[[pair_index(a, b, m) for a, b in sample]]
-        d = np.abs(got - ref)
+        idx = [pair_index(a, b, m) for a, b in sample]
         result["cpu_baseline"] = {
             "value": round(len(sample) / cpu_s, 3), "unit": "pairs/s", "cores": threads,
             "kind": "oracle",
             "sample": "%d pairs of this workload (all planted pairs + seeded random pairs), "
                       "FP64 oracle, %.1f s" % (len(sample), cpu_s),
         }
-        result["parity"] = {
-            "pairs": len(sample), "max_dMIC": float(d[:, 0].max()), "max_dMAS": float(d[:, 1].max()),
-            "max_dMEV": float(d[:, 2].max()), "mcn_mismatch": int((d[:, 3] > 1e-9).sum()),
-        }
+        result["parity"] = parity_of(results[main_form][2][idx], ref)
+        for form in results:
+            forms[form]["parity"] = parity_of(results[form][2][idx], ref)
     print(json.dumps(result), flush=True)
 
 

@@ -58,9 +58,16 @@ extern "C" {
 #define MICX_F64 1
 #define MICX_I32 2
 
-/* Numeric forms of the dynamic program (integer stages are identical). */
-#define MICX_MODE_FP64         0   /* DP in FP64 */
-#define MICX_MODE_FP32_RECHECK 1   /* DP in FP32, chosen grids re-scored in FP64, near ties re-run in FP64 */
+/* Numeric forms of the dynamic program (integer stages are identical).
+ * MICX_MODE_DP32 runs the DP in 32-bit fixed point: column costs are scaled
+ * by S and rounded through a table (T[j] = round(S j ln j)), sums are exact
+ * integer arithmetic, and every matrix entry is then within a bound that the
+ * library computes per row count y, (y+1) x / (2 S n ln 2) with
+ * S ~ 2^32 / (n ln y).  Row counts whose bound exceeds the tolerance (see
+ * micx_set_dp32_tolerance, default 1e-7) run in FP64.  Scores, the
+ * H(Q) term and all statistics are computed in FP64 in both forms. */
+#define MICX_MODE_FP64  0   /* DP in FP64 */
+#define MICX_MODE_DP32  1   /* DP in 32-bit fixed point with a per-class error bound, FP64 elsewhere */
 
 /* Opaque context: device, workspace, cached tables. */
 typedef struct micx_ctx micx_ctx;
@@ -157,10 +164,18 @@ typedef struct {
     int64_t h_terms;      /* x ln x table terms read by those evaluations */
     double dp_ms;         /* summed duration of the DP kernel launches (HIP events) */
     int dp_launches;      /* number of DP kernel launches */
+    int dp32_classes;     /* row counts run in 32-bit fixed point (MICX_MODE_DP32) */
+    int fp64_classes;     /* row counts run in FP64 */
+    double dp32_bound;    /* largest |dM| bound among the fixed-point row counts */
 } micx_profile;
 
 int micx_set_profiling(micx_ctx *ctx, int enable);
 int micx_get_profile(micx_ctx *ctx, micx_profile *out);
+
+/* Tolerance on |dM| for MICX_MODE_DP32 (default 1e-7): a row count whose
+ * fixed-point bound exceeds it runs in FP64.  Returns MICX_EINVAL unless
+ * tol > 0. */
+int micx_set_dp32_tolerance(micx_ctx *ctx, double tol);
 
 /* Message for a return code (static string). */
 const char *micx_strerror(int code);

@@ -27,14 +27,14 @@ MAX_N = 8192
 
 F32, F64, I32 = 0, 1, 2
 MODE_FP64 = 0
-MODE_FP32_RECHECK = 1
+MODE_DP32 = 1
 
 # Every symbol declared in include/micx.h.
 EXPORTS = (
     "micx_ctx_create", "micx_ctx_destroy", "micx_check_param", "micx_grid_bound",
     "micx_compute_score", "micx_mic", "micx_mas", "micx_mev", "micx_mcn", "micx_free_score",
     "micx_allpairs", "micx_pairs", "micx_debug_item", "micx_strerror",
-    "micx_set_profiling", "micx_get_profile",
+    "micx_set_profiling", "micx_get_profile", "micx_set_dp32_tolerance",
 )
 
 
@@ -53,7 +53,9 @@ class _Score(ctypes.Structure):
 class _Profile(ctypes.Structure):
     _fields_ = [("items", ctypes.c_int64), ("dp_cells", ctypes.c_int64),
                 ("h_evals", ctypes.c_int64), ("h_terms", ctypes.c_int64),
-                ("dp_ms", ctypes.c_double), ("dp_launches", ctypes.c_int)]
+                ("dp_ms", ctypes.c_double), ("dp_launches", ctypes.c_int),
+                ("dp32_classes", ctypes.c_int), ("fp64_classes", ctypes.c_int),
+                ("dp32_bound", ctypes.c_double)]
 
 
 _lib = None
@@ -101,6 +103,8 @@ def load_library():
     lib.micx_set_profiling.restype = ctypes.c_int
     lib.micx_get_profile.argtypes = [vp, P(_Profile)]
     lib.micx_get_profile.restype = ctypes.c_int
+    lib.micx_set_dp32_tolerance.argtypes = [vp, ctypes.c_double]
+    lib.micx_set_dp32_tolerance.restype = ctypes.c_int
     lib.micx_strerror.argtypes = [ctypes.c_int]
     lib.micx_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -249,3 +253,9 @@ def get_profile(device: int = 0) -> dict:
     p = _Profile()
     _check(load_library().micx_get_profile(context(device), ctypes.byref(p)), "micx_get_profile")
     return {k: getattr(p, k) for k, _ in _Profile._fields_}
+
+
+def set_dp32_tolerance(tol: float, device: int = 0):
+    """Largest |dM| allowed for a row count to run the DP in 32-bit fixed point."""
+    _check(load_library().micx_set_dp32_tolerance(context(device), float(tol)),
+           "micx_set_dp32_tolerance")

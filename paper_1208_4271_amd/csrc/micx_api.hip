@@ -52,7 +52,8 @@ struct micx_ctx {
     DevBuf perm, gsize, grank, rowof, yhat, rowstart, xlogx, status;
     DevBuf geo;        // xcnt | khat | koff | aoff
     DevBuf cbuf, sbuf, Kb, kb, srcb, A, scratch, pairs, input, out, dense;
-    DevBuf counters;
+    DevBuf counters, fxtab;
+    double dp32_tol = 1e-7;
     int profiling = 0;
     micx_profile prof = {};
 };
@@ -112,7 +113,7 @@ extern "C" void micx_ctx_destroy(micx_ctx *c) {
     DevBuf *all[] = {&c->perm, &c->gsize, &c->grank, &c->rowof, &c->yhat, &c->rowstart,
                      &c->xlogx, &c->status, &c->geo, &c->cbuf, &c->sbuf, &c->Kb, &c->kb,
                      &c->srcb, &c->A, &c->scratch, &c->pairs, &c->input, &c->out, &c->dense,
-                     &c->counters};
+                     &c->counters, &c->fxtab};
     for (DevBuf *b : all) b->release();
     delete c;
 }
@@ -180,7 +181,7 @@ int upload_geometry(micx_ctx *ctx, HostGeometry &hg) {
 int check_common(micx_ctx *ctx, int n, double alpha, double c, int mode) {
     if (!ctx) return MICX_EINVAL;
     if (micx_check_param(alpha, c)) return MICX_EINVAL;
-    if (mode != MICX_MODE_FP64 && mode != MICX_MODE_FP32_RECHECK) return MICX_EINVAL;
+    if (mode != MICX_MODE_FP64 && mode != MICX_MODE_DP32) return MICX_EINVAL;
     if (n < 2) return MICX_EINVAL;
     if (n > MICX_MAX_N) return MICX_ETOOBIG;
     if (micx_grid_bound(n, alpha) < 4) return MICX_ESMALLN;
@@ -264,13 +265,24 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
     RETCHK(ensure_items(ctx, g, pb, ib));
     std::vector<DpPlan> plans(g.NY);
     size_t scratch = 0;
+    int nfx = 0;
     for (int yi = 0; yi < g.NY; yi++) {
-        plans[yi] = dp_plan(g, rt.n, yi, ctx->cus);
+        plans[yi] = dp_plan(g, rt.n, yi, ctx->cus, mode, ctx->dp32_tol);
         const size_t waves = (size_t)std::min<int64_t>(plans[yi].max_waves, 2 * (int64_t)pb);
         const size_t w = ((waves + plans[yi].WPB - 1) / plans[yi].WPB) * plans[yi].WPB;
-        scratch = std::max(scratch, w * plans[yi].slot);
+        scratch = std::max(scratch, w * plans[yi].slot_bytes);
+        nfx += plans[yi].fx ? 1 : 0;
     }
-    RETCHK(ctx->scratch.ensure(scratch * sizeof(double)));
+    RETCHK(ctx->scratch.ensure(scratch));
+    // fixed-point cost tables, one per row count that runs in 32 bits
+    const size_t tabn = (size_t)rt.n + 1;
+    if (nfx) {
+        RETCHK(ctx->fxtab.ensure((size_t)g.NY * tabn * sizeof(uint32_t)));
+        for (int yi = 0; yi < g.NY; yi++)
+            if (plans[yi].fx)
+                HIPCHK(launch_fxtable(rt.n, plans[yi], ctx->xlogx.as<double>(),
+                                      ctx->fxtab.as<uint32_t>() + yi * tabn, s));
+    }
     std::vector<hipEvent_t> ev;
     unsigned long long *counters = nullptr;
     ctx->prof = micx_profile{};
@@ -301,8 +313,9 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
                 ev.push_back(b);
                 HIPCHK(hipEventRecord(a, s));
             }
-            HIPCHK(launch_dp(rt, et, g, ps, np, ib, ctx->xlogx.as<double>(),
-                             ctx->scratch.as<double>(), yi, plans[yi], mode, s));
+            const uint32_t *tab = plans[yi].fx ? ctx->fxtab.as<uint32_t>() + yi * tabn : nullptr;
+            HIPCHK(launch_dp(rt, et, g, ps, np, ib, ctx->xlogx.as<double>(), tab,
+                             ctx->scratch.p, yi, plans[yi], s));
             if (ctx->profiling) HIPCHK(hipEventRecord(ev.back(), s));
         }
         HIPCHK(launch_stats(g, np, ib, out_dev + 4 * p0, M, Axy, Ayx, s));
@@ -324,6 +337,14 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
         ctx->prof.h_terms = (int64_t)h[3];
         ctx->prof.dp_ms = ms;
         ctx->prof.dp_launches = (int)(ev.size() / 2);
+    }
+    for (const DpPlan &p : plans) {
+        if (p.fx) {
+            ctx->prof.dp32_classes++;
+            ctx->prof.dp32_bound = std::max(ctx->prof.dp32_bound, p.bound);
+        } else {
+            ctx->prof.fp64_classes++;
+        }
     }
     return MICX_OK;
 }
@@ -435,6 +456,12 @@ extern "C" int micx_compute_score(micx_ctx *ctx, const double *x, const double *
 extern "C" int micx_set_profiling(micx_ctx *ctx, int enable) {
     if (!ctx) return MICX_EINVAL;
     ctx->profiling = enable ? 1 : 0;
+    return MICX_OK;
+}
+
+extern "C" int micx_set_dp32_tolerance(micx_ctx *ctx, double tol) {
+    if (!ctx || !(tol > 0.0)) return MICX_EINVAL;
+    ctx->dp32_tol = tol;
     return MICX_OK;
 }
 

@@ -1,28 +1,40 @@
 // micx_dp.hip -- launch planning and dispatch of the OptimizeXAxis DP kernel
-// (micx_dp_kernel.h) for one row count y at a time.
+// (micx_dp_kernel.h) for one row count y at a time, and the fixed-point cost
+// tables of the 32-bit form.
+#include <math.h>
+
 #include "micx_dp_kernel.h"
 
 namespace micx {
 
-dp_kernel_t dp_pick_0(int NL, int YR, int T);
-dp_kernel_t dp_pick_1(int NL, int YR, int T);
-dp_kernel_t dp_pick_2(int NL, int YR, int T);
-dp_kernel_t dp_pick_3(int NL, int YR, int T);
-
-// ------------------------------------------------------------------ dispatch
+dp_kernel_t dp_pick_f64_0(int NL, int YR, int T);
+dp_kernel_t dp_pick_f64_1(int NL, int YR, int T);
+dp_kernel_t dp_pick_f64_2(int NL, int YR, int T);
+dp_kernel_t dp_pick_f64_3(int NL, int YR, int T);
+dp_kernel_t dp_pick_u32_0(int NL, int YR, int T);
+dp_kernel_t dp_pick_u32_1(int NL, int YR, int T);
+dp_kernel_t dp_pick_u32_2(int NL, int YR, int T);
+dp_kernel_t dp_pick_u32_3(int NL, int YR, int T);
 
 namespace {
 
-
-dp_kernel_t pick(int NL, int YR, int T) {
-    dp_kernel_t k = dp_pick_0(NL, YR, T);
-    if (!k) k = dp_pick_1(NL, YR, T);
-    if (!k) k = dp_pick_2(NL, YR, T);
-    if (!k) k = dp_pick_3(NL, YR, T);
+dp_kernel_t pick(bool fx, int NL, int YR, int T) {
+    dp_kernel_t k;
+    if (fx) {
+        k = dp_pick_u32_0(NL, YR, T);
+        if (!k) k = dp_pick_u32_1(NL, YR, T);
+        if (!k) k = dp_pick_u32_2(NL, YR, T);
+        if (!k) k = dp_pick_u32_3(NL, YR, T);
+    } else {
+        k = dp_pick_f64_0(NL, YR, T);
+        if (!k) k = dp_pick_f64_1(NL, YR, T);
+        if (!k) k = dp_pick_f64_2(NL, YR, T);
+        if (!k) k = dp_pick_f64_3(NL, YR, T);
+    }
     return k;
 }
 
-bool have_shape(int NL, int YR) { return pick(NL, YR, 1) != nullptr; }
+bool have_shape(int NL, int YR) { return pick(false, NL, YR, 1) != nullptr; }
 
 int env_int(const char *name, int dflt) {
     const char *v = getenv(name);
@@ -37,15 +49,34 @@ int round_up_in(int v, const int *set, int count, int otherwise) {
 
 inline int align16(size_t b) { return (int)((b + 15) & ~(size_t)15); }
 
+// T[j] = round(S * j ln j) mod 2^32 for one row-count class.
+__global__ void k_fxtable(int n, double scale, const double *xlogx, uint32_t *tab) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j <= n) tab[j] = (uint32_t)(unsigned long long)__double2ll_rn(scale * xlogx[j]);
+}
+
 }  // namespace
 
 // Shape of the DP launch for row count y (class yi).
-DpPlan dp_plan(const Geometry &g, int n, int yi, int cus) {
+//
+// Fixed-point form (mode MICX_MODE_DP32): every candidate G_{l-1}(s) + h(s,t)
+// is at most e_t ln(yhat) <= n ln y in exact arithmetic, so the scale
+// S = floor(2^32 / (1.02 n ln max(y,2))) keeps the rounded sums below 2^32
+// with a 2% margin.  Each column cost is off by at most (yhat+1)/2 units and
+// a partition into at most l <= x columns by l(yhat+1)/2, so an entry M of
+// the class is off by at most (y+1) x / (2 S n ln 2).  Classes whose bound
+// exceeds the tolerance run in FP64.
+DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol) {
     static const int NLS[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32, 36};
     static const int YRS[] = {2, 3, 4, 5, 6, 7, 8, 10, 12, 16, 20, 24, 32, 40};
     DpPlan p;
     const int y = yi + 2, x = g.B / y;
     const int kh = g.khat_host[yi];
+    p.scale = floor(4294967296.0 / (1.02 * (double)n * log((double)std::max(y, 2))));
+    p.bound = 0.5 * (double)(y + 1) * (double)x / (p.scale * (double)n * log(2.0));
+    p.fx = mode == MICX_MODE_DP32 && p.bound <= tol && p.scale >= 1.0;
+    const int vb = p.fx ? 4 : 8;                       // bytes per DP value
+    const int PK = 16 / vb;
     const int nf = std::max(x - 2, 1);                 // full layers (at least one shape)
     // tuning overrides: MICX_DP_NLCAP caps the layers per pass, MICX_DP_T
     // forces the targets per lane (1 or 2)
@@ -56,18 +87,18 @@ DpPlan dp_plan(const Geometry &g, int n, int yi, int cus) {
     p.T = (p.NL >= 5 && p.YR > 0 && p.YR <= 12) ? 2 : 1;
     const int tforce = env_int("MICX_DP_T", 0);
     if (tforce == 1 || (tforce == 2 && p.NL >= 5 && p.YR > 0 && p.YR <= 12)) p.T = tforce;
-    const int NLP = (p.NL + 1) & ~1;
+    const int NLP = (p.NL + PK - 1) / PK * PK;
     p.KS = kh + 1;
     p.RS = (p.YR > 0 ? p.YR : y) + 1;
     p.x = x;
-    p.slot = (size_t)x * (size_t)p.KS;                 // layers 0..x-1 (0 unused)
-    const int lds_L = align16((size_t)(n + 1) * 8);
+    p.slot_bytes = (size_t)x * (size_t)p.KS * vb;      // layers 0..x-1 (0 unused)
+    const int lds_L = align16((size_t)(n + 1) * vb);
     const int lds_rec = align16((size_t)(kh + 1) * p.RS * 4);
-    const int lds_pub = align16((size_t)NLP * 8);
+    const int lds_pub = align16((size_t)NLP * vb);
     const int budget = 160 * 1024;
     p.WPB = 4;
     for (p.SB = 64; p.SB >= 8; p.SB >>= 1) {
-        const int lds_stage = align16(std::max((size_t)p.SB * NLP * 8, (size_t)n));
+        const int lds_stage = align16(std::max((size_t)p.SB * NLP * vb, (size_t)n));
         const int wave = align16((size_t)lds_stage + lds_pub + lds_rec);
         p.lds_L = lds_L;
         p.lds_stage = lds_stage;
@@ -85,10 +116,16 @@ DpPlan dp_plan(const Geometry &g, int n, int yi, int cus) {
     return p;
 }
 
+hipError_t launch_fxtable(int n, const DpPlan &p, const double *xlogx, uint32_t *tab,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_fxtable, dim3((n + 256) / 256), dim3(256), 0, s, n, p.scale, xlogx, tab);
+    return hipGetLastError();
+}
+
 hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry &g,
                      PairSource ps, int npairs, const ItemBuffers &ib, const double *xlogx,
-                     double *scratch, int yi, const DpPlan &p, int mode, hipStream_t s) {
-    (void)mode;
+                     const uint32_t *fxtab, void *scratch, int yi, const DpPlan &p,
+                     hipStream_t s) {
     DpArgs a;
     a.n = rt.n; a.NY = g.NY; a.KSUM = g.KSUM; a.ASUM = g.ASUM;
     a.yi = yi; a.x = p.x; a.RS = p.RS; a.KS = p.KS;
@@ -96,9 +133,10 @@ hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry
     a.perm = rt.perm; a.grank = rt.grank; a.rowof = et.rowof; a.yhat = et.yhat;
     a.koff = g.koff; a.aoff = g.aoff;
     a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.src = ib.src; a.A = ib.A;
-    a.xlogx = xlogx; a.scratch = scratch; a.slot = p.slot;
+    a.xlogx = xlogx; a.fxtab = fxtab; a.inv_scale = 1.0 / p.scale;
+    a.scratch = scratch; a.slot_bytes = p.slot_bytes;
     a.lds_L = p.lds_L; a.lds_stage = p.lds_stage; a.lds_pub = p.lds_pub; a.lds_wave = p.lds_wave;
-    dp_kernel_t k = pick(p.NL, p.YR, p.T);
+    dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T);
     if (!k) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        p.lds);

@@ -1,10 +1,12 @@
-// micx_dp_i3.hip -- DP kernel instances for count-row classes YR=10, YR=12, YR=16, YR=20, YR=24, YR=32, YR=40, YR=0.
+// micx_dp_f64_i3.hip -- DP kernel instances (double values) for count-row classes YR=10, YR=12, YR=16, YR=20, YR=24, YR=32, YR=40, YR=0.
 #include "micx_dp_kernel.h"
+
+#define MICX_V double
 #include "micx_dp_shapes.h"
 
 namespace micx {
 
-dp_kernel_t dp_pick_3(int NL, int YR, int T) {
+dp_kernel_t dp_pick_f64_3(int NL, int YR, int T) {
     MICX_NL_SMALL(MICX_CASE, 10)
     MICX_NL_SMALL(MICX_CASE, 12)
     MICX_NL_SMALL(MICX_CASE1, 16)

@@ -11,7 +11,17 @@
 //    row entropy, computed once per (s,t) and used for every layer;
 //  * the DP: G_1(t) = h(0,t), G_l(t) = min_{0 <= s < t} G_{l-1}(s) + h(s,t)
 //    with G_{l-1}(0) = 0.  G_l(K) is the least sum of column costs over
-//    partitions into at most l columns, and I_l = H(Q) - G_l(K)/n.
+//    partitions into at most l columns, and I_l = H(Q) - G_l(K)/n.  Layers
+//    2..x-1 are needed at every target; layer x only at t = K.
+//
+// Value types.  V = double runs the DP in FP64.  V = uint32_t runs it in
+// 32-bit fixed point: the table holds T[j] = round(S * j ln j) mod 2^32 for a
+// per-row-count scale S chosen so that every candidate G_{l-1}(s) + h(s,t)
+// (at most e_t ln(yhat) in exact arithmetic) stays below 2^32.  Integer sums
+// are exact, so the DP finds the exact optimum of the rounded costs; each
+// cost is off by at most (yhat+1)/2 units, so G_l(K)/S is within
+// l (yhat+1) / (2S) of the true optimum.  The host uses this form only where
+// that bound, in units of M, is below the requested tolerance.
 //
 // Layout.  Lanes own targets t, T per lane (a chunk of 64T targets).  The
 // layers of a pass (up to NL) live in registers, as do the target's
@@ -25,6 +35,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "micx_device.h"
 
@@ -32,7 +43,7 @@ namespace micx {
 
 struct DpArgs {
     int n, NY, KSUM, ASUM;
-    int yi, x, RS, KS;           // class: row count y = yi+2, x(y), rec stride y+1, G row stride
+    int yi, x, RS, KS;           // class: row count y = yi+2, x(y), count-record stride, G row stride
     int nitems, npairs, SB;      // items of the class = 2 * npairs
     PairSource ps;
     const int *perm, *grank;
@@ -40,61 +51,87 @@ struct DpArgs {
     const int *yhat, *koff, *aoff;
     const int *cbuf, *sbuf, *K, *src;
     double *A;
-    const double *xlogx;
-    double *scratch;
-    size_t slot;                 // doubles of G table per wavefront
+    const double *xlogx;         // FP64 table j ln j
+    const uint32_t *fxtab;       // fixed-point table of the class (uint32 form)
+    double inv_scale;            // 1 / S (uint32 form)
+    void *scratch;
+    size_t slot_bytes;           // G table bytes per wavefront
     int lds_L, lds_stage, lds_pub, lds_wave;
 };
 
-// Wavefronts per SIMD the compiler must fit: the layer registers (2 VGPRs per
-// double, T targets) set the budget, and more resident wavefronts hide the
-// LDS latency of the broadcasts and table gathers.
+template <class V> struct DpVal;
+
+template <> struct DpVal<double> {
+    static constexpr int PK = 2;    // values per 16-byte LDS access
+    static constexpr int SP = 1;    // sources merged per minimum
+    __device__ static double mn(double a, double b) { return fmin(a, b); }
+    __device__ static double big() { return INFINITY; }
+    __device__ static double real(double g, double) { return g; }
+};
+
+template <> struct DpVal<uint32_t> {
+    static constexpr int PK = 4;
+    static constexpr int SP = 2;    // two sources per v_min3_u32
+    __device__ static uint32_t mn(uint32_t a, uint32_t b) { return a < b ? a : b; }
+    __device__ static uint32_t big() { return 0xffffffffu; }
+    __device__ static double real(uint32_t g, double inv_scale) { return (double)g * inv_scale; }
+};
+
 // Build-time tuning knobs: MICX_DP_MINWAVES_EXTRA (registers assumed beyond
 // the layer array when choosing the occupancy target; 0 disables the target)
-// and MICX_DP_GROUP (layers per scheduling group).
+// and MICX_DP_GROUP (16-byte layer packs per scheduling group).
 #ifndef MICX_DP_MINWAVES_EXTRA
 #define MICX_DP_MINWAVES_EXTRA 80
 #endif
 #ifndef MICX_DP_GROUP
-#define MICX_DP_GROUP 8
+#define MICX_DP_GROUP 4
 #endif
 
-template <int NL, int T>
+template <class V, int NL, int T>
 constexpr int dp_min_waves() {
-    constexpr int need = T * ((NL + 1) & ~1) * 2 + MICX_DP_MINWAVES_EXTRA;
-    return MICX_DP_MINWAVES_EXTRA == 0 ? 1 : (need <= 128 ? 4 : (need <= 168 ? 3 : (need <= 256 ? 2 : 1)));
+    constexpr int PK = DpVal<V>::PK;
+    constexpr int need = T * ((NL + PK - 1) / PK * PK) * (int)(sizeof(V) / 4) + MICX_DP_MINWAVES_EXTRA;
+    return MICX_DP_MINWAVES_EXTRA == 0 ? 1
+                                       : (need <= 128 ? 4 : (need <= 168 ? 3 : (need <= 256 ? 2 : 1)));
 }
 
-// Layers per scheduling group: the broadcasts of one group are loaded, then
-// its cells update, so only one group's operands are live at a time.
-constexpr int DP_GROUP = MICX_DP_GROUP;
+template <class V>
+struct alignas(16) Pack {
+    V v[DpVal<V>::PK];
+};
 
-template <int NL, int YR, int T>
-__global__ __launch_bounds__(256, (dp_min_waves<NL, T>())) void k_dp64(DpArgs a) {
-    constexpr int NLP = (NL + 1) & ~1;
+template <class V, int NL, int YR, int T>
+__global__ __launch_bounds__(256, (dp_min_waves<V, NL, T>())) void k_dp(DpArgs a) {
+    using DV = DpVal<V>;
+    constexpr int PK = DV::PK;
+    constexpr int NLP = (NL + PK - 1) / PK * PK;
+    constexpr bool FX = std::is_same<V, uint32_t>::value;
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = a.n, NY = a.NY, RS = a.RS, KS = a.KS, x = a.x, yi = a.yi, SB = a.SB;
     const int sbs = __builtin_ctz(SB);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    double *L = (double *)smem;
-    for (int j = threadIdx.x; j <= n; j += blockDim.x) L[j] = a.xlogx[j];
+    V *L = (V *)smem;
+    for (int j = threadIdx.x; j <= n; j += blockDim.x) {
+        if constexpr (FX) L[j] = a.fxtab[j];
+        else L[j] = a.xlogx[j];
+    }
     __syncthreads();
     unsigned char *wb = smem + a.lds_L + (size_t)wv * a.lds_wave;
-    double *stage = (double *)wb;                              // SB x NLP, or n flag bytes
-    double *pub = (double *)(wb + a.lds_stage);                // NLP
+    V *stage = (V *)wb;                                        // SB x NLP, or n flag bytes
+    V *pub = (V *)(wb + a.lds_stage);                          // NLP
     int *rec = (int *)(wb + a.lds_stage + a.lds_pub);          // (K+1) x RS: e_t, N_t[0..RS-2]
     const int wpb = blockDim.x >> 6;
     const int gw = blockIdx.x * wpb + wv, nw = gridDim.x * wpb;
-    double *G = a.scratch + (size_t)gw * a.slot;
+    V *G = (V *)((unsigned char *)a.scratch + (size_t)gw * a.slot_bytes);
 
     for (int po = gw; po < a.nitems; po += nw) {
         const int o = po & 1, pl = po >> 1;
         int pi, pj;
         pair_of(a.ps, pl, pi, pj);
-        const int U = o ? pj : pi, V = o ? pi : pj;
+        const int U = o ? pj : pi, Vv = o ? pi : pj;
         const size_t it = (size_t)po * NY + yi;
         const int K = a.K[it];
-        const int yh = a.yhat[(size_t)V * NY + yi];
+        const int yh = a.yhat[(size_t)Vv * NY + yi];
         const int *ends = (a.src[it] ? a.sbuf : a.cbuf) + (size_t)po * a.KSUM + a.koff[yi];
 
         // ---- cumulative counts (item 10a); rows beyond yhat stay 0 ----
@@ -110,8 +147,8 @@ __global__ __launch_bounds__(256, (dp_min_waves<NL, T>())) void k_dp64(DpArgs a)
         wave_sync();
         {
             const int *permU = a.perm + (size_t)U * n;
-            const int *grV = a.grank + (size_t)V * n;
-            const uint16_t *rowV = a.rowof + (size_t)V * n * NY + yi;
+            const int *grV = a.grank + (size_t)Vv * n;
+            const uint16_t *rowV = a.rowof + (size_t)Vv * n * NY + yi;
             int carry = 0;
             for (int p0 = 0; p0 < n; p0 += 64) {
                 const int p = p0 + lane;
@@ -151,9 +188,9 @@ __global__ __launch_bounds__(256, (dp_min_waves<NL, T>())) void k_dp64(DpArgs a)
         wave_sync();
 
         // column cost h(s,t) with both records read from LDS (any row count)
-        auto hcost = [&](int s, int t) -> double {
+        auto hcost = [&](int s, int t) -> V {
             const int *rs = rec + s * RS, *rt = rec + t * RS;
-            double acc = L[rt[0] - rs[0]];
+            V acc = L[rt[0] - rs[0]];
             for (int r = 0; r < yh; r++) acc -= L[rt[1 + r] - rs[1 + r]];
             return acc;
         };
@@ -161,18 +198,18 @@ __global__ __launch_bounds__(256, (dp_min_waves<NL, T>())) void k_dp64(DpArgs a)
         // ---- full layers l = 2..x-1 for every target (item 10b costs, OptimizeXAxis) ----
         for (int l0 = 2; l0 <= x - 1; l0 += NL) {
             const int nl = min(NL, x - l0);
-            const int nlp = (nl + 1) & ~1;
+            const int nlp = (nl + PK - 1) / PK * PK;
             for (int c0 = 0; c0 < K; c0 += 64 * T) {
                 int tt[T], et[T];
                 int Nt[T][YR > 0 ? YR : 1];
-                double g[T][NLP], gprev[T];
+                V g[T][NLP], gprev[T];
 #pragma unroll
                 for (int j = 0; j < T; j++) {
                     tt[j] = c0 + 64 * j + lane + 1;
                     const int tc = tt[j] <= K ? tt[j] : K;
                     const int *rt = rec + tc * RS;
                     et[j] = rt[0];
-                    double h0 = L[et[j]];
+                    V h0 = L[et[j]];
                     if constexpr (YR > 0) {
 #pragma unroll
                         for (int r = 0; r < YR; r++) {
@@ -187,7 +224,7 @@ __global__ __launch_bounds__(256, (dp_min_waves<NL, T>())) void k_dp64(DpArgs a)
                     for (int q = 0; q < NLP; q++) g[j][q] = h0;
                 }
                 // h(s, t_j) for this lane's targets (count rows from registers or LDS)
-                auto hsrc = [&](int s, double (&out)[T]) {
+                auto hsrc = [&](int s, V (&out)[T]) {
                     const int *rs = rec + s * RS;
                     const int es = rs[0];
 #pragma unroll
@@ -204,35 +241,59 @@ __global__ __launch_bounds__(256, (dp_min_waves<NL, T>())) void k_dp64(DpArgs a)
                         for (int j = 0; j < T; j++) out[j] = hcost(s, tt[j] <= K ? tt[j] : K);
                     }
                 };
-                // sources of earlier chunks, SB at a time through LDS; the next
-                // source's costs are gathered while this source's cells update
-                constexpr int UNR = (NL >= 16 || YR >= 16) ? 1 : 2;
+                // sources of earlier chunks, SB at a time through LDS.  The
+                // next sources' costs are gathered while this step's cells
+                // update; the fixed-point form merges two sources per min3
+                // (a missing partner carries the largest value and cost 0).
+                constexpr int SP = DV::SP;
                 for (int sb = 1; sb <= c0; sb += SB) {
                     const int ns = min(SB, c0 - sb + 1);
                     for (int k = lane; k < nlp * SB; k += 64) {
                         const int q = k >> sbs, sl = k & (SB - 1);
-                        stage[sl * NLP + q] =
-                            (sl < ns && q < nl) ? G[(size_t)(l0 - 1 + q) * KS + sb + sl] : 0.0;
+                        stage[sl * NLP + q] = (sl < ns && q < nl)
+                                                  ? G[(size_t)(l0 - 1 + q) * KS + sb + sl]
+                                                  : DV::big();
                     }
                     wave_sync();
-                    double hc[T], hn[T];
-                    hsrc(sb, hc);
-#pragma unroll UNR
-                    for (int sl = 0; sl < ns; sl++) {
-                        hsrc(sb + min(sl + 1, ns - 1), hn);
-                        const double *gs = stage + sl * NLP;
+                    V hc[SP][T], hn[SP][T];
 #pragma unroll
-                        for (int q = 0; q < NLP; q += 2) {
-                            const double2 v = *(const double2 *)(gs + q);
+                    for (int u = 0; u < SP; u++) {
+                        if (u < ns) hsrc(sb + u, hc[u]);
+                        else {
 #pragma unroll
-                            for (int j = 0; j < T; j++) {
-                                g[j][q] = fmin(g[j][q], v.x + hc[j]);
-                                g[j][q + 1] = fmin(g[j][q + 1], v.y + hc[j]);
+                            for (int j = 0; j < T; j++) hc[u][j] = 0;
+                        }
+                    }
+                    for (int sl = 0; sl < ns; sl += SP) {
+#pragma unroll
+                        for (int u = 0; u < SP; u++) {
+                            const int nx = sl + SP + u;
+                            if (nx < ns) hsrc(sb + nx, hn[u]);
+                            else {
+#pragma unroll
+                                for (int j = 0; j < T; j++) hn[u][j] = 0;
                             }
-                            if ((q + 2) % DP_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
                         }
 #pragma unroll
-                        for (int j = 0; j < T; j++) hc[j] = hn[j];
+                        for (int q = 0; q < NLP; q += PK) {
+                            Pack<V> v[SP];
+#pragma unroll
+                            for (int u = 0; u < SP; u++) v[u] = *(const Pack<V> *)(stage + (sl + u) * NLP + q);
+#pragma unroll
+                            for (int j = 0; j < T; j++)
+#pragma unroll
+                                for (int e = 0; e < PK; e++) {
+                                    V m = g[j][q + e];
+#pragma unroll
+                                    for (int u = 0; u < SP; u++) m = DV::mn(m, v[u].v[e] + hc[u][j]);
+                                    g[j][q + e] = m;
+                                }
+                            if ((q / PK + 1) % MICX_DP_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
+                        }
+#pragma unroll
+                        for (int u = 0; u < SP; u++)
+#pragma unroll
+                            for (int j = 0; j < T; j++) hc[u][j] = hn[u][j];
                     }
                     wave_sync();
                 }
@@ -245,24 +306,28 @@ __global__ __launch_bounds__(256, (dp_min_waves<NL, T>())) void k_dp64(DpArgs a)
                     const int send = min(c0 + 64 * jo + 64, min(c0 + 64 * T, K) - 1);
                     for (int s = sbeg; s <= send; s++) {
                         const int ln = s - sbeg;
-                        double hs[T];
+                        V hs[T];
                         hsrc(s, hs);
                         if (lane == ln) {
-                            double2 *pv = (double2 *)pub;
-                            pv[0] = make_double2(gprev[jo], g[jo][0]);
 #pragma unroll
-                            for (int q = 2; q < NLP; q += 2) pv[q >> 1] = make_double2(g[jo][q - 1], g[jo][q]);
+                            for (int q = 0; q < NLP; q += PK) {
+                                Pack<V> w;
+#pragma unroll
+                                for (int e = 0; e < PK; e++)
+                                    w.v[e] = (q + e == 0) ? gprev[jo] : g[jo][q + e - 1];
+                                *(Pack<V> *)(pub + q) = w;
+                            }
                         }
                         wave_sync();
 #pragma unroll
                         for (int j = jo; j < T; j++) {
                             if (j == jo && lane <= ln) continue;
 #pragma unroll
-                            for (int q = 0; q < NLP; q += 2) {
-                                const double2 v = *(const double2 *)(pub + q);
-                                g[j][q] = fmin(g[j][q], v.x + hs[j]);
-                                g[j][q + 1] = fmin(g[j][q + 1], v.y + hs[j]);
-                                if ((q + 2) % DP_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
+                            for (int q = 0; q < NLP; q += PK) {
+                                const Pack<V> v = *(const Pack<V> *)(pub + q);
+#pragma unroll
+                                for (int e = 0; e < PK; e++) g[j][q + e] = DV::mn(g[j][q + e], v.v[e] + hs[j]);
+                                if ((q / PK + 1) % MICX_DP_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
                             }
                         }
                         wave_sync();
@@ -283,22 +348,23 @@ __global__ __launch_bounds__(256, (dp_min_waves<NL, T>())) void k_dp64(DpArgs a)
         }
 
         // ---- last layer only at t = K: G_x(K) = min_{0 <= s < K} G_{x-1}(s) + h(s,K) ----
-        double best = INFINITY;
+        V best = DV::big();
         for (int s = lane; s < K; s += 64) {
-            double gs = 0.0;   // G_{x-1}(0) = 0
+            V gs = 0;   // G_{x-1}(0) = 0
             if (s > 0) gs = (x == 2) ? hcost(0, s) : G[(size_t)(x - 1) * KS + s];
-            best = fmin(best, gs + hcost(s, K));
+            best = DV::mn(best, gs + hcost(s, K));
         }
 #pragma unroll
-        for (int d = 32; d > 0; d >>= 1) best = fmin(best, __shfl_xor(best, d, 64));
+        for (int d = 32; d > 0; d >>= 1) best = DV::mn(best, (V)__shfl_xor(best, d, 64));
 
-        // ---- I_l = (L[n] - sum_r L[q_r] - G_l(K)) / n, normalised by ln min(l, yhat) ----
+        // ---- I_l = (L[n] - sum_r L[q_r] - G_l(K)) / n in FP64, normalised by ln min(l, yhat) ----
         double sq = 0.0;
-        for (int r = 0; r < yh; r++) sq += L[rec[K * RS + 1 + r]];
+        for (int r = 0; r < yh; r++) sq += a.xlogx[rec[K * RS + 1 + r]];
+        const double Ln = a.xlogx[n];
         double *Aout = a.A + (size_t)po * a.ASUM + a.aoff[yi];
         for (int l = 2 + lane; l <= x; l += 64) {
-            const double Gl = (l == x) ? best : G[(size_t)l * KS + K];
-            const double I = (L[n] - sq - Gl) / (double)n;
+            const V Gl = (l == x) ? best : G[(size_t)l * KS + K];
+            const double I = (Ln - sq - DV::real(Gl, a.inv_scale)) / (double)n;
             const int norm = min(l, yh);
             Aout[l - 2] = norm >= 2 ? I / log((double)norm) : 0.0;
         }

@@ -1,10 +1,12 @@
-// micx_dp_i0.hip -- DP kernel instances for count-row classes YR=2, YR=3.
+// micx_dp_u32_i0.hip -- DP kernel instances (uint32_t values) for count-row classes YR=2, YR=3.
 #include "micx_dp_kernel.h"
+
+#define MICX_V uint32_t
 #include "micx_dp_shapes.h"
 
 namespace micx {
 
-dp_kernel_t dp_pick_0(int NL, int YR, int T) {
+dp_kernel_t dp_pick_u32_0(int NL, int YR, int T) {
     MICX_NL_LIST(MICX_CASE, 2)
     MICX_NL_LIST(MICX_CASE, 3)
     return nullptr;

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "micx.h"
+
 namespace micx {
 
 // Per-dataset ranking tables (one row of n entries per variable).
@@ -40,12 +42,15 @@ struct Geometry {
 
 // Launch shape of the DP for one row count y.
 struct DpPlan {
+    bool fx = false;              // 32-bit fixed-point DP (else FP64)
+    double scale = 0.0;           // fixed-point scale S
+    double bound = 0.0;           // bound on |dM| of the fixed-point form for this class
     int NL = 0, YR = 0, T = 0;    // kernel template: layers per pass, rows in registers, targets per lane
     int x = 0, KS = 0, RS = 0;    // columns, G-table row stride, count-record stride
     int SB = 0, WPB = 0;          // sources staged per block, wavefronts per workgroup
     int lds = 0, lds_L = 0, lds_stage = 0, lds_pub = 0, lds_wave = 0;
     int blocks_per_cu = 0, max_waves = 0;
-    size_t slot = 0;              // doubles of G table per wavefront
+    size_t slot_bytes = 0;        // G table bytes per wavefront
 };
 
 // Per-batch item buffers.
@@ -71,10 +76,13 @@ hipError_t launch_rank(const void *X, int dtype, int m, int n, RankTables &rt, i
 hipError_t launch_equip(const RankTables &rt, EquipTables &et, hipStream_t s);
 hipError_t launch_part(const RankTables &rt, const EquipTables &et, const Geometry &g,
                        PairSource ps, int npairs, ItemBuffers &ib, hipStream_t s);
-DpPlan dp_plan(const Geometry &g, int n, int yi, int cus);
+DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol);
+hipError_t launch_fxtable(int n, const DpPlan &p, const double *xlogx, uint32_t *tab,
+                          hipStream_t s);
 hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry &g,
                      PairSource ps, int npairs, const ItemBuffers &ib, const double *xlogx,
-                     double *scratch, int yi, const DpPlan &p, int mode, hipStream_t s);
+                     const uint32_t *fxtab, void *scratch, int yi, const DpPlan &p,
+                     hipStream_t s);
 hipError_t launch_stats(const Geometry &g, int npairs, const ItemBuffers &ib, double *out,
                         double *M, double *Axy, double *Ayx, hipStream_t s);
 hipError_t launch_xlogx(int n, double *xlogx, hipStream_t s);

@@ -141,6 +141,7 @@ def test_pair_list_matches_allpairs(micx):
 
 
 def test_error_paths(micx):
+    _log("case error paths")
     import torch
     x = np.linspace(0, 1, 100)
     with pytest.raises(micx.MicxError) as e:
@@ -165,3 +166,62 @@ def test_error_paths(micx):
         micx.allpairs(Xd, 0.6, 15, out=out)
     assert e.value.code == micx.MICX_ENONFINITE
     assert (out == -7.0).all(), "outputs must stay untouched on error"
+
+
+# ------------------------------------------------------------------ DP32 form
+def _bound(micx):
+    p = micx.get_profile()
+    return p["dp32_bound"], p["dp32_classes"], p["fp64_classes"]
+
+
+def test_dp32_cpp_example(micx):
+    _log("case dp32 cpp_example")
+    x, y = workloads.cpp_example()
+    got = micx.compute_score(x, y, 0.6, 15, mode=micx.MODE_DP32)
+    bound, nfx, _ = _bound(micx)
+    assert nfx > 0 and bound <= 1e-7
+    want = oracle.score(x, y, 0.6, 15)
+    _cmp_scores(got, want, tol=bound + 1e-12)
+    for v, p in zip(got["stats"], (0.999999, 0.728144, 0.999999, 4.584963)):
+        assert abs(v - p) <= 5e-7 + bound
+
+
+def test_dp32_cfg1_matrix_within_bound(micx):
+    _log("case dp32 cfg1")
+    x, y = workloads.cfg1_single_pair()
+    got = micx.compute_score(x, y, 0.6, 15, mode=micx.MODE_DP32)
+    bound, nfx, _ = _bound(micx)
+    assert nfx > 0
+    _cmp_scores(got, oracle.score(x, y, 0.6, 15), tol=bound + 1e-12)
+
+
+def test_dp32_cfg2_allpairs(micx):
+    import torch
+    _log("case dp32 cfg2 allpairs")
+    X = workloads.cfg2_matrix()
+    got = micx.allpairs(torch.from_numpy(X).cuda(), 0.6, 15, mode=micx.MODE_DP32).cpu().numpy()
+    bound, nfx, nf64 = _bound(micx)
+    assert nfx > 0
+    want = oracle.allpairs(X.astype(np.float64), 0.6, 15)
+    d = np.abs(got[:, :3] - want[:, :3]).max()
+    assert d <= min(TOL, bound + 1e-12), (d, bound)
+    mism = int((np.abs(got[:, 3] - want[:, 3]) > 1e-9).sum())
+    _log("dp32 cfg2: max|d|=%.3g bound=%.3g mcn mismatches=%d of %d" % (d, bound, mism, len(got)))
+    assert mism <= len(got) // 200
+
+
+def test_dp32_tolerance_falls_back_to_fp64(micx):
+    # With a tolerance below every class bound the whole DP runs in FP64 and
+    # matches the FP64 form bit for bit.
+    import torch
+    _log("case dp32 tolerance fallback")
+    X = torch.from_numpy(workloads.cfg2_matrix()[:10]).cuda()
+    micx.set_dp32_tolerance(1e-30)
+    try:
+        a = micx.allpairs(X, 0.6, 15, mode=micx.MODE_DP32).cpu().numpy()
+        _, nfx, nf64 = _bound(micx)
+    finally:
+        micx.set_dp32_tolerance(1e-7)
+    b = micx.allpairs(X, 0.6, 15, mode=micx.MODE_FP64).cpu().numpy()
+    assert nfx == 0 and nf64 > 0
+    assert np.array_equal(a, b)
