@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import os
+import re
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -31,16 +32,48 @@ def flags():
 EXTRA = {s: ["-fno-honor-nans"] for s in SOURCES if s.startswith("micx_dp")}
 
 
-def _compile(src, obj, verbose, defines=()):
-    cmd = [HIPCC] + flags() + EXTRA.get(src, []) + list(defines) + ["-c", "-o", obj,
-                                                                     os.path.join(CSRC, src)]
+# The DP kernels must not spill: their resource usage is read back from the
+# compiler and the build fails if any of them uses private (scratch) memory.
+USAGE_FLAG = "-Rpass-analysis=kernel-resource-usage"
+_DP_NAME = re.compile(r"k_dpI([dj])Li(\d+)ELi(\d+)ELi(\d+)E")
+
+
+def dp_resource_usage(text):
+    """Parse the compiler's kernel-resource-usage remarks: {(fx, NL, YR, T):
+    {"VGPRs": .., "AGPRs": .., "ScratchSize": .., ...}} for the DP kernels."""
+    out, cur = {}, None
+    for line in text.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            k = _DP_NAME.search(m.group(1))
+            cur = (int(k.group(1) == "j"), int(k.group(2)), int(k.group(3)), int(k.group(4))) if k else None
+            if cur is not None:
+                out[cur] = {}
+            continue
+        m = re.search(r"remark:\s+([A-Za-z ]+?)(?: \[bytes/lane\])?: (\d+)", line)
+        if m and cur is not None:
+            out[cur][m.group(1).strip()] = int(m.group(2))
+    return out
+
+
+def _compile(src, obj, verbose, defines=(), check_spills=True, device_only=False):
+    dp = src.startswith("micx_dp_")
+    cmd = [HIPCC] + flags() + EXTRA.get(src, []) + list(defines) + ([USAGE_FLAG] if dp else [])
+    cmd += (["--cuda-device-only"] if device_only else []) + ["-c", "-o", obj, os.path.join(CSRC, src)]
     cmd = [c for c in cmd if c != "-shared"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed on %s:\n%s%s" % (src, res.stdout, res.stderr))
-    return obj
+    usage = dp_resource_usage(res.stderr) if dp else {}
+    if check_spills:
+        bad = sorted(k for k, u in usage.items() if u.get("ScratchSize", 0) or u.get("VGPRs Spill", 0))
+        if bad:
+            raise RuntimeError("DP kernels of %s spill registers (fx, NL, YR, T): %s; regenerate the "
+                               "occupancy table (python -m paper_1208_4271_amd.gen_dp_occupancy)"
+                               % (src, bad))
+    return usage
 
 
 def build(verbose: bool = False, out: str = LIB, defines=()) -> str:

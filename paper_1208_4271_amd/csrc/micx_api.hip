@@ -52,7 +52,7 @@ struct micx_ctx {
     DevBuf perm, gsize, grank, rowof, yhat, rowstart, xlogx, status;
     DevBuf geo;        // xcnt | khat | koff | aoff
     DevBuf cbuf, sbuf, Kb, kb, srcb, A, scratch, pairs, input, out, dense;
-    DevBuf counters, fxtab;
+    DevBuf counters, fxtab, gbuf;
     double dp32_tol = 1e-7;
     int profiling = 0;
     micx_profile prof = {};
@@ -113,7 +113,7 @@ extern "C" void micx_ctx_destroy(micx_ctx *c) {
     DevBuf *all[] = {&c->perm, &c->gsize, &c->grank, &c->rowof, &c->yhat, &c->rowstart,
                      &c->xlogx, &c->status, &c->geo, &c->cbuf, &c->sbuf, &c->Kb, &c->kb,
                      &c->srcb, &c->A, &c->scratch, &c->pairs, &c->input, &c->out, &c->dense,
-                     &c->counters, &c->fxtab};
+                     &c->counters, &c->fxtab, &c->gbuf};
     for (DevBuf *b : all) b->release();
     delete c;
 }
@@ -230,7 +230,7 @@ int prepare_variables(micx_ctx *ctx, const void *X, int dtype, int m, int n, con
 // Pairs per batch: bounded so that the per-item buffers stay near 512 MB.
 int batch_pairs(const Geometry &g, int64_t total) {
     const size_t per_pair = 2 * (2 * (size_t)g.KSUM * sizeof(int) + 3 * (size_t)g.NY * sizeof(int) +
-                                 (size_t)g.ASUM * sizeof(double));
+                                 (size_t)g.ASUM * sizeof(double) + (size_t)g.n * sizeof(int));
     size_t pb = ((size_t)512 << 20) / (per_pair ? per_pair : 1);
     if (pb < 1) pb = 1;
     if (pb > (size_t)1 << 20) pb = (size_t)1 << 20;
@@ -246,6 +246,8 @@ int ensure_items(micx_ctx *ctx, const Geometry &g, int pb, ItemBuffers &ib) {
     RETCHK(ctx->kb.ensure(npo * g.NY * sizeof(int)));
     RETCHK(ctx->srcb.ensure(npo * g.NY * sizeof(int)));
     RETCHK(ctx->A.ensure(npo * g.ASUM * sizeof(double)));
+    RETCHK(ctx->gbuf.ensure(npo * (size_t)g.n * sizeof(int)));
+    ib.gbuf = ctx->gbuf.as<int>();
     ib.cbuf = ctx->cbuf.as<int>();
     ib.sbuf = ctx->sbuf.as<int>();
     ib.K = ctx->Kb.as<int>();

@@ -87,6 +87,11 @@ DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol) 
     p.T = (p.NL >= 5 && p.YR > 0 && p.YR <= 12) ? 2 : 1;
     const int tforce = env_int("MICX_DP_T", 0);
     if (tforce == 1 || (tforce == 2 && p.NL >= 5 && p.YR > 0 && p.YR <= 12)) p.T = tforce;
+    if (x == 2) {                                      // no full layer: the lean shape
+        p.NL = 0;
+        p.YR = 0;
+        p.T = 1;
+    }
     const int NLP = (p.NL + PK - 1) / PK * PK;
     p.KS = kh + 1;
     p.RS = (p.YR > 0 ? p.YR : y) + 1;
@@ -98,7 +103,7 @@ DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol) 
     const int budget = 160 * 1024;
     p.WPB = 4;
     for (p.SB = 64; p.SB >= 8; p.SB >>= 1) {
-        const int lds_stage = align16(std::max((size_t)p.SB * NLP * vb, (size_t)n));
+        const int lds_stage = align16(std::max((size_t)p.SB * NLP * vb, (size_t)3 * n));
         const int wave = align16((size_t)lds_stage + lds_pub + lds_rec);
         p.lds_L = lds_L;
         p.lds_stage = lds_stage;
@@ -111,7 +116,17 @@ DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol) 
         p.WPB--;
         p.lds = p.lds_L + p.WPB * p.lds_wave;
     }
+    // resident workgroups per CU: the runtime's figure for this kernel (its
+    // registers and LDS), capped by the LDS budget
     p.blocks_per_cu = std::max(1, budget / std::max(p.lds, 1));
+    dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T);
+    int occ = 0;
+    if (k && hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds) ==
+                 hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k, 64 * p.WPB, p.lds) ==
+                 hipSuccess &&
+        occ > 0)
+        p.blocks_per_cu = std::min(p.blocks_per_cu, occ);
     p.max_waves = cus * p.blocks_per_cu * p.WPB;
     return p;
 }
@@ -132,7 +147,7 @@ hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry
     a.nitems = 2 * npairs; a.npairs = npairs; a.SB = p.SB; a.ps = ps;
     a.perm = rt.perm; a.grank = rt.grank; a.rowof = et.rowof; a.yhat = et.yhat;
     a.koff = g.koff; a.aoff = g.aoff;
-    a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.src = ib.src; a.A = ib.A;
+    a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.src = ib.src; a.gbuf = ib.gbuf; a.A = ib.A;
     a.xlogx = xlogx; a.fxtab = fxtab; a.inv_scale = 1.0 / p.scale;
     a.scratch = scratch; a.slot_bytes = p.slot_bytes;
     a.lds_L = p.lds_L; a.lds_stage = p.lds_stage; a.lds_pub = p.lds_pub; a.lds_wave = p.lds_wave;

@@ -15,6 +15,7 @@ dp_kernel_t dp_pick_f64_3(int NL, int YR, int T) {
     MICX_NL_TINY(MICX_CASE1, 32)
     MICX_NL_TINY(MICX_CASE1, 40)
     MICX_NL_LIST(MICX_CASE1, 0)
+    MICX_CASE1(0, 0)
     return nullptr;
 }
 

@@ -38,6 +38,7 @@
 #include <type_traits>
 
 #include "micx_device.h"
+#include "micx_dp_occupancy.h"
 
 namespace micx {
 
@@ -49,7 +50,7 @@ struct DpArgs {
     const int *perm, *grank;
     const uint16_t *rowof;
     const int *yhat, *koff, *aoff;
-    const int *cbuf, *sbuf, *K, *src;
+    const int *cbuf, *sbuf, *K, *src, *gbuf;
     double *A;
     const double *xlogx;         // FP64 table j ln j
     const uint32_t *fxtab;       // fixed-point table of the class (uint32 form)
@@ -77,22 +78,28 @@ template <> struct DpVal<uint32_t> {
     __device__ static double real(uint32_t g, double inv_scale) { return (double)g * inv_scale; }
 };
 
-// Build-time tuning knobs: MICX_DP_MINWAVES_EXTRA (registers assumed beyond
-// the layer array when choosing the occupancy target; 0 disables the target)
-// and MICX_DP_GROUP (16-byte layer packs per scheduling group).
-#ifndef MICX_DP_MINWAVES_EXTRA
-#define MICX_DP_MINWAVES_EXTRA 80
-#endif
+// Build-time tuning knob: MICX_DP_GROUP (16-byte layer packs per scheduling
+// group).  MICX_DP_OCC_FORCE sets one occupancy target for every shape (used
+// only when the occupancy table is regenerated).
 #ifndef MICX_DP_GROUP
 #define MICX_DP_GROUP 4
 #endif
 
-template <class V, int NL, int T>
+// Occupancy target (waves per SIMD) of a kernel shape: the largest target at
+// which the shape compiles without spilling registers, from the generated
+// table; shapes not in it get no target.  A spill-free DP is required: spill
+// code placed inside a divergent region leaves the slots of inactive lanes
+// unwritten, and the build rejects any DP kernel that spills.
+template <class V, int NL, int YR, int T>
 constexpr int dp_min_waves() {
-    constexpr int PK = DpVal<V>::PK;
-    constexpr int need = T * ((NL + PK - 1) / PK * PK) * (int)(sizeof(V) / 4) + MICX_DP_MINWAVES_EXTRA;
-    return MICX_DP_MINWAVES_EXTRA == 0 ? 1
-                                       : (need <= 128 ? 4 : (need <= 168 ? 3 : (need <= 256 ? 2 : 1)));
+#ifdef MICX_DP_OCC_FORCE
+    return MICX_DP_OCC_FORCE;
+#else
+    constexpr int fx = std::is_same<V, uint32_t>::value ? 1 : 0;
+    for (const DpOcc &e : kDpOcc)
+        if (e.fx == fx && e.nl == NL && e.yr == YR && e.t == T) return e.waves;
+    return 1;
+#endif
 }
 
 template <class V>
@@ -101,7 +108,7 @@ struct alignas(16) Pack {
 };
 
 template <class V, int NL, int YR, int T>
-__global__ __launch_bounds__(256, (dp_min_waves<V, NL, T>())) void k_dp(DpArgs a) {
+__global__ __launch_bounds__(256, (dp_min_waves<V, NL, YR, T>())) void k_dp(DpArgs a) {
     using DV = DpVal<V>;
     constexpr int PK = DV::PK;
     constexpr int NLP = (NL + PK - 1) / PK * PK;
@@ -109,7 +116,9 @@ __global__ __launch_bounds__(256, (dp_min_waves<V, NL, T>())) void k_dp(DpArgs a
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = a.n, NY = a.NY, RS = a.RS, KS = a.KS, x = a.x, yi = a.yi, SB = a.SB;
     const int sbs = __builtin_ctz(SB);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // the wavefront index is uniform across the wave; saying so keeps the item
+    // index, its sizes and pointers in scalar registers and its branches scalar
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     V *L = (V *)smem;
     for (int j = threadIdx.x; j <= n; j += blockDim.x) {
         if constexpr (FX) L[j] = a.fxtab[j];
@@ -117,7 +126,7 @@ __global__ __launch_bounds__(256, (dp_min_waves<V, NL, T>())) void k_dp(DpArgs a
     }
     __syncthreads();
     unsigned char *wb = smem + a.lds_L + (size_t)wv * a.lds_wave;
-    V *stage = (V *)wb;                                        // SB x NLP, or n flag bytes
+    V *stage = (V *)wb;                                        // SB x NLP, or labels and flags
     V *pub = (V *)(wb + a.lds_stage);                          // NLP
     int *rec = (int *)(wb + a.lds_stage + a.lds_pub);          // (K+1) x RS: e_t, N_t[0..RS-2]
     const int wpb = blockDim.x >> 6;
@@ -130,12 +139,22 @@ __global__ __launch_bounds__(256, (dp_min_waves<V, NL, T>())) void k_dp(DpArgs a
         pair_of(a.ps, pl, pi, pj);
         const int U = o ? pj : pi, Vv = o ? pi : pj;
         const size_t it = (size_t)po * NY + yi;
-        const int K = a.K[it];
-        const int yh = a.yhat[(size_t)Vv * NY + yi];
+        const int K = __builtin_amdgcn_readfirstlane(a.K[it]);
+        const int yh = __builtin_amdgcn_readfirstlane(a.yhat[(size_t)Vv * NY + yi]);
         const int *ends = (a.src[it] ? a.sbuf : a.cbuf) + (size_t)po * a.KSUM + a.koff[yi];
 
         // ---- cumulative counts (item 10a); rows beyond yhat stay 0 ----
-        unsigned char *F = (unsigned char *)stage;
+        // Row labels of the points in column order are gathered first (all
+        // loads independent); a flag per superclump start then gives each
+        // point its superclump through a ballot scan, and LDS atomics count.
+        uint16_t *lab = (uint16_t *)stage;
+        unsigned char *F = (unsigned char *)stage + 2 * (size_t)n;
+        {
+            const int *gb = a.gbuf + (size_t)po * n;
+            const uint16_t *rowV = a.rowof + (size_t)Vv * n * NY + yi;
+#pragma unroll 4
+            for (int p = lane; p < n; p += 64) lab[p] = rowV[(size_t)gb[p] * NY];
+        }
         for (int k = lane; k < (K + 1) * RS; k += 64) rec[k] = 0;
         for (int p = lane; p < n; p += 64) F[p] = 0;
         wave_sync();
@@ -146,9 +165,6 @@ __global__ __launch_bounds__(256, (dp_min_waves<V, NL, T>())) void k_dp(DpArgs a
         }
         wave_sync();
         {
-            const int *permU = a.perm + (size_t)U * n;
-            const int *grV = a.grank + (size_t)Vv * n;
-            const uint16_t *rowV = a.rowof + (size_t)Vv * n * NY + yi;
             int carry = 0;
             for (int p0 = 0; p0 < n; p0 += 64) {
                 const int p = p0 + lane;
@@ -156,11 +172,7 @@ __global__ __launch_bounds__(256, (dp_min_waves<V, NL, T>())) void k_dp(DpArgs a
                 const uint64_t bal = __ballot(f);
                 const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
                                       __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-                if (p < n) {
-                    const int g = grV[permU[p]];
-                    const int r = rowV[(size_t)g * NY];
-                    atomicAdd(&rec[(carry + below + (f ? 1 : 0) + 1) * RS + 1 + r], 1);
-                }
+                if (p < n) atomicAdd(&rec[(carry + below + (f ? 1 : 0) + 1) * RS + 1 + lab[p]], 1);
                 carry += __popcll(bal);
             }
         }
@@ -196,6 +208,8 @@ __global__ __launch_bounds__(256, (dp_min_waves<V, NL, T>())) void k_dp(DpArgs a
         };
 
         // ---- full layers l = 2..x-1 for every target (item 10b costs, OptimizeXAxis) ----
+        // (NL = 0 is the shape for x = 2, where no layer is needed at every target)
+        if constexpr (NL > 0)
         for (int l0 = 2; l0 <= x - 1; l0 += NL) {
             const int nl = min(NL, x - l0);
             const int nlp = (nl + PK - 1) / PK * PK;
@@ -366,7 +380,8 @@ __global__ __launch_bounds__(256, (dp_min_waves<V, NL, T>())) void k_dp(DpArgs a
             const V Gl = (l == x) ? best : G[(size_t)l * KS + K];
             const double I = (Ln - sq - DV::real(Gl, a.inv_scale)) / (double)n;
             const int norm = min(l, yh);
-            Aout[l - 2] = norm >= 2 ? I / log((double)norm) : 0.0;
+            // ln(norm) = (norm ln norm) / norm from the j ln j table
+            Aout[l - 2] = norm >= 2 ? I * (double)norm / a.xlogx[norm] : 0.0;
         }
         wave_sync();
     }

@@ -60,6 +60,7 @@ struct ItemBuffers {
     int *K = nullptr;      // (super)clumps used by the DP
     int *k = nullptr;      // clumps before merging
     int *src = nullptr;    // 0: DP columns are the clumps (cbuf), 1: the superclumps (sbuf)
+    int *gbuf = nullptr;   // per (pair, orientation): group rank of the row variable, column order
     double *A = nullptr;   // normalised scores, ASUM per (pair, orientation)
 };
 

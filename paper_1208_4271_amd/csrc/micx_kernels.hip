@@ -169,7 +169,7 @@ struct PartArgs {
     const int *perm, *gsize, *grank;
     const uint16_t *rowof;
     const int *khat, *koff;
-    int *cbuf, *sbuf, *K, *k, *src;
+    int *cbuf, *sbuf, *K, *k, *src, *gbuf;
 };
 
 __global__ __launch_bounds__(64) void k_part(PartArgs a) {
@@ -227,6 +227,7 @@ __global__ __launch_bounds__(64) void k_part(PartArgs a) {
         if (q < n) {
             gsz = gsU[q];
             grk = grV[permU[q]];
+            if (yb == 0) a.gbuf[(size_t)po * n + q] = grk;   // reused by the DP's count table
         }
         const int cnt = min(64, n - p0);
         int labs[64];
@@ -398,7 +399,7 @@ hipError_t launch_part(const RankTables &rt, const EquipTables &et, const Geomet
     a.n = rt.n; a.NY = g.NY; a.KSUM = g.KSUM; a.ps = ps;
     a.perm = rt.perm; a.gsize = rt.gsize; a.grank = rt.grank; a.rowof = et.rowof;
     a.khat = g.khat; a.koff = g.koff;
-    a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.k = ib.k; a.src = ib.src;
+    a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.k = ib.k; a.src = ib.src; a.gbuf = ib.gbuf;
     const int nyb = (g.NY + 63) / 64;
     hipLaunchKernelGGL(k_part, dim3((unsigned)(2 * npairs * nyb)), dim3(64), 0, s, a);
     return hipGetLastError();

@@ -225,3 +225,19 @@ def test_dp32_tolerance_falls_back_to_fp64(micx):
     b = micx.allpairs(X, 0.6, 15, mode=micx.MODE_FP64).cpu().numpy()
     assert nfx == 0 and nf64 > 0
     assert np.array_equal(a, b)
+
+
+def test_alternating_forms_full_matrices(micx):
+    # Calls that alternate the two forms and the sample count reuse every
+    # device buffer; each call must depend on its own inputs only.  Row
+    # counts 3 and 5 with norm ln 3, ln 5 are the entries to watch.
+    _log("case alternating forms")
+    rng = np.random.default_rng(7)
+    for n in (1000, 1023, 1024):
+        x = rng.uniform(0, 1, n)
+        y = np.sin(3 * x) + rng.normal(0, 0.2, n)
+        want = oracle.score(x, y, 0.6, 15)
+        for mode in (micx.MODE_DP32, micx.MODE_FP64, micx.MODE_DP32):
+            got = micx.compute_score(x, y, 0.6, 15, mode=mode)
+            tol = 1e-10 if mode == micx.MODE_FP64 else _bound(micx)[0] + 1e-12
+            _cmp_scores(got, want, tol=tol)
