@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="pairs timed on the CPU oracle (0 disables the baseline)")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="end with one plain device copy of MIB MiB, the reference "
+                         "for scaling hardware byte counters")
     return ap.parse_args()
 
 
@@ -178,6 +181,14 @@ def main():
         result["parity"] = parity_of(results[main_form][2][idx], ref)
         for form in results:
             forms[form]["parity"] = parity_of(results[form][2][idx], ref)
+    if args.copy_calibration > 0:
+        nb = args.copy_calibration << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = nb
     print(json.dumps(result), flush=True)
 
 

@@ -52,7 +52,7 @@ struct micx_ctx {
     DevBuf perm, gsize, grank, rowof, yhat, rowstart, xlogx, status;
     DevBuf geo;        // xcnt | khat | koff | aoff
     DevBuf cbuf, sbuf, Kb, kb, srcb, A, scratch, pairs, input, out, dense;
-    DevBuf counters, fxtab, gbuf;
+    DevBuf counters, fxtab, lab;
     double dp32_tol = 1e-7;
     int profiling = 0;
     micx_profile prof = {};
@@ -113,7 +113,7 @@ extern "C" void micx_ctx_destroy(micx_ctx *c) {
     DevBuf *all[] = {&c->perm, &c->gsize, &c->grank, &c->rowof, &c->yhat, &c->rowstart,
                      &c->xlogx, &c->status, &c->geo, &c->cbuf, &c->sbuf, &c->Kb, &c->kb,
                      &c->srcb, &c->A, &c->scratch, &c->pairs, &c->input, &c->out, &c->dense,
-                     &c->counters, &c->fxtab, &c->gbuf};
+                     &c->counters, &c->fxtab, &c->lab};
     for (DevBuf *b : all) b->release();
     delete c;
 }
@@ -227,11 +227,16 @@ int prepare_variables(micx_ctx *ctx, const void *X, int dtype, int m, int n, con
     return MICX_OK;
 }
 
-// Pairs per batch: bounded so that the per-item buffers stay near 512 MB.
+// Row labels take one byte when every label fits (labels < yhat <= NY + 1),
+// else two; a row of labels is padded to whole 64-point blocks.
+int lab_bytes(const Geometry &g) { return g.NY + 1 <= 256 ? 1 : 2; }
+size_t lab_row_bytes(const Geometry &g) { return (size_t)((g.n + 63) / 64 * 64) * lab_bytes(g); }
+
+// Pairs per batch: bounded so that the per-item buffers stay near 2 GB.
 int batch_pairs(const Geometry &g, int64_t total) {
     const size_t per_pair = 2 * (2 * (size_t)g.KSUM * sizeof(int) + 3 * (size_t)g.NY * sizeof(int) +
-                                 (size_t)g.ASUM * sizeof(double) + (size_t)g.n * sizeof(int));
-    size_t pb = ((size_t)512 << 20) / (per_pair ? per_pair : 1);
+                                 (size_t)g.ASUM * sizeof(double) + (size_t)g.NY * lab_row_bytes(g));
+    size_t pb = ((size_t)2048 << 20) / (per_pair ? per_pair : 1);
     if (pb < 1) pb = 1;
     if (pb > (size_t)1 << 20) pb = (size_t)1 << 20;
     if ((int64_t)pb > total) pb = (size_t)total;
@@ -246,8 +251,10 @@ int ensure_items(micx_ctx *ctx, const Geometry &g, int pb, ItemBuffers &ib) {
     RETCHK(ctx->kb.ensure(npo * g.NY * sizeof(int)));
     RETCHK(ctx->srcb.ensure(npo * g.NY * sizeof(int)));
     RETCHK(ctx->A.ensure(npo * g.ASUM * sizeof(double)));
-    RETCHK(ctx->gbuf.ensure(npo * (size_t)g.n * sizeof(int)));
-    ib.gbuf = ctx->gbuf.as<int>();
+    ib.lab16 = lab_bytes(g) == 2;
+    ib.lab_row = lab_row_bytes(g);
+    RETCHK(ctx->lab.ensure(npo * g.NY * ib.lab_row));
+    ib.lab = ctx->lab.as<unsigned char>();
     ib.cbuf = ctx->cbuf.as<int>();
     ib.sbuf = ctx->sbuf.as<int>();
     ib.K = ctx->Kb.as<int>();

@@ -103,7 +103,7 @@ DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol) 
     const int budget = 160 * 1024;
     p.WPB = 4;
     for (p.SB = 64; p.SB >= 8; p.SB >>= 1) {
-        const int lds_stage = align16(std::max((size_t)p.SB * NLP * vb, (size_t)3 * n));
+        const int lds_stage = align16(std::max((size_t)p.SB * NLP * vb, (size_t)n));
         const int wave = align16((size_t)lds_stage + lds_pub + lds_rec);
         p.lds_L = lds_L;
         p.lds_stage = lds_stage;
@@ -145,9 +145,10 @@ hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry
     a.n = rt.n; a.NY = g.NY; a.KSUM = g.KSUM; a.ASUM = g.ASUM;
     a.yi = yi; a.x = p.x; a.RS = p.RS; a.KS = p.KS;
     a.nitems = 2 * npairs; a.npairs = npairs; a.SB = p.SB; a.ps = ps;
-    a.perm = rt.perm; a.grank = rt.grank; a.rowof = et.rowof; a.yhat = et.yhat;
+    a.yhat = et.yhat;
     a.koff = g.koff; a.aoff = g.aoff;
-    a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.src = ib.src; a.gbuf = ib.gbuf; a.A = ib.A;
+    a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.src = ib.src; a.A = ib.A;
+    a.lab = ib.lab; a.lab_row = ib.lab_row; a.lab16 = ib.lab16;
     a.xlogx = xlogx; a.fxtab = fxtab; a.inv_scale = 1.0 / p.scale;
     a.scratch = scratch; a.slot_bytes = p.slot_bytes;
     a.lds_L = p.lds_L; a.lds_stage = p.lds_stage; a.lds_pub = p.lds_pub; a.lds_wave = p.lds_wave;

@@ -47,10 +47,11 @@ struct DpArgs {
     int yi, x, RS, KS;           // class: row count y = yi+2, x(y), count-record stride, G row stride
     int nitems, npairs, SB;      // items of the class = 2 * npairs
     PairSource ps;
-    const int *perm, *grank;
-    const uint16_t *rowof;
     const int *yhat, *koff, *aoff;
-    const int *cbuf, *sbuf, *K, *src, *gbuf;
+    const int *cbuf, *sbuf, *K, *src;
+    const unsigned char *lab;    // row labels in column order, [item][y-2][p]
+    size_t lab_row;
+    int lab16;
     double *A;
     const double *xlogx;         // FP64 table j ln j
     const uint32_t *fxtab;       // fixed-point table of the class (uint32 form)
@@ -144,17 +145,13 @@ __global__ __launch_bounds__(256, (dp_min_waves<V, NL, YR, T>())) void k_dp(DpAr
         const int *ends = (a.src[it] ? a.sbuf : a.cbuf) + (size_t)po * a.KSUM + a.koff[yi];
 
         // ---- cumulative counts (item 10a); rows beyond yhat stay 0 ----
-        // Row labels of the points in column order are gathered first (all
-        // loads independent); a flag per superclump start then gives each
-        // point its superclump through a ballot scan, and LDS atomics count.
-        uint16_t *lab = (uint16_t *)stage;
-        unsigned char *F = (unsigned char *)stage + 2 * (size_t)n;
-        {
-            const int *gb = a.gbuf + (size_t)po * n;
-            const uint16_t *rowV = a.rowof + (size_t)Vv * n * NY + yi;
-#pragma unroll 4
-            for (int p = lane; p < n; p += 64) lab[p] = rowV[(size_t)gb[p] * NY];
-        }
+        // A flag per superclump start gives each point its superclump through
+        // a ballot scan; the point's row label (stored in column order by the
+        // partition kernel) selects the count, and LDS atomics count.
+        unsigned char *F = (unsigned char *)stage;
+        const unsigned char *lb8 = a.lab + ((size_t)po * NY + yi) * a.lab_row;
+        const uint16_t *lb16 = (const uint16_t *)lb8;
+        const bool l16 = a.lab16 != 0;
         for (int k = lane; k < (K + 1) * RS; k += 64) rec[k] = 0;
         for (int p = lane; p < n; p += 64) F[p] = 0;
         wave_sync();
@@ -166,23 +163,37 @@ __global__ __launch_bounds__(256, (dp_min_waves<V, NL, YR, T>())) void k_dp(DpAr
         wave_sync();
         {
             int carry = 0;
+#pragma unroll 4
             for (int p0 = 0; p0 < n; p0 += 64) {
                 const int p = p0 + lane;
+                const int lab = p < n ? (l16 ? (int)lb16[p] : (int)lb8[p]) : 0;
                 const bool f = p < n && F[p] != 0;
                 const uint64_t bal = __ballot(f);
                 const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
                                       __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-                if (p < n) atomicAdd(&rec[(carry + below + (f ? 1 : 0) + 1) * RS + 1 + lab[p]], 1);
+                if (p < n) atomicAdd(&rec[(carry + below + (f ? 1 : 0) + 1) * RS + 1 + lab], 1);
                 carry += __popcll(bal);
             }
         }
         wave_sync();
         if (yh >= 8) {
+            // one row per lane, eight superclumps per step (loads issued together)
             for (int r = lane; r < yh; r += 64) {
-                int run = 0;
-                for (int t = 1; t <= K; t++) {
-                    run += rec[t * RS + 1 + r];
-                    rec[t * RS + 1 + r] = run;
+                int *col = rec + 1 + r;
+                int run = 0, t = 1;
+                for (; t + 7 <= K; t += 8) {
+                    int v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; u++) v[u] = col[(t + u) * RS];
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        run += v[u];
+                        col[(t + u) * RS] = run;
+                    }
+                }
+                for (; t <= K; t++) {
+                    run += col[t * RS];
+                    col[t * RS] = run;
                 }
             }
         } else {

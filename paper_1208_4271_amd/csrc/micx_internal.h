@@ -60,7 +60,12 @@ struct ItemBuffers {
     int *K = nullptr;      // (super)clumps used by the DP
     int *k = nullptr;      // clumps before merging
     int *src = nullptr;    // 0: DP columns are the clumps (cbuf), 1: the superclumps (sbuf)
-    int *gbuf = nullptr;   // per (pair, orientation): group rank of the row variable, column order
+    // Row labels of every point in column order, per (pair, orientation) and
+    // row count: [item][y-2][p], lab_row bytes per row (n rounded up to 64
+    // entries), one byte per label, two when some row count exceeds 255.
+    unsigned char *lab = nullptr;
+    size_t lab_row = 0;
+    int lab16 = 0;
     double *A = nullptr;   // normalised scores, ASUM per (pair, orientation)
 };
 

@@ -169,7 +169,10 @@ struct PartArgs {
     const int *perm, *gsize, *grank;
     const uint16_t *rowof;
     const int *khat, *koff;
-    int *cbuf, *sbuf, *K, *k, *src, *gbuf;
+    int *cbuf, *sbuf, *K, *k, *src;
+    unsigned char *lab;          // row labels in column order, [item][y-2][p]
+    size_t lab_row;
+    int lab16;
 };
 
 __global__ __launch_bounds__(64) void k_part(PartArgs a) {
@@ -227,7 +230,6 @@ __global__ __launch_bounds__(64) void k_part(PartArgs a) {
         if (q < n) {
             gsz = gsU[q];
             grk = grV[permU[q]];
-            if (yb == 0) a.gbuf[(size_t)po * n + q] = grk;   // reused by the DP's count table
         }
         const int cnt = min(64, n - p0);
         int labs[64];
@@ -235,6 +237,27 @@ __global__ __launch_bounds__(64) void k_part(PartArgs a) {
         for (int s = 0; s < 64; s++) {
             const int g = __builtin_amdgcn_readlane(grk, s);
             labs[s] = (s < cnt) ? (int)rowV[(size_t)g * a.NY] : 0;
+        }
+        // this lane's row labels of the 64 points, for the DP's count table
+        // (the row is padded to whole 64-point blocks; padding holds 0)
+        if (act) {
+            uint4 *dst = (uint4 *)(a.lab + ((size_t)po * a.NY + yi) * a.lab_row) + (p0 >> (a.lab16 ? 3 : 4));
+            if (a.lab16) {
+#pragma unroll
+                for (int v = 0; v < 8; v++) {
+                    const int *l = labs + 8 * v;
+                    dst[v] = make_uint4(l[0] | l[1] << 16, l[2] | l[3] << 16, l[4] | l[5] << 16, l[6] | l[7] << 16);
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int *l = labs + 16 * v;
+                    dst[v] = make_uint4(l[0] | l[1] << 8 | l[2] << 16 | l[3] << 24,
+                                        l[4] | l[5] << 8 | l[6] << 16 | l[7] << 24,
+                                        l[8] | l[9] << 8 | l[10] << 16 | l[11] << 24,
+                                        l[12] | l[13] << 8 | l[14] << 16 | l[15] << 24);
+                }
+            }
         }
 #pragma unroll
         for (int s = 0; s < 64; s++) {
@@ -399,7 +422,8 @@ hipError_t launch_part(const RankTables &rt, const EquipTables &et, const Geomet
     a.n = rt.n; a.NY = g.NY; a.KSUM = g.KSUM; a.ps = ps;
     a.perm = rt.perm; a.gsize = rt.gsize; a.grank = rt.grank; a.rowof = et.rowof;
     a.khat = g.khat; a.koff = g.koff;
-    a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.k = ib.k; a.src = ib.src; a.gbuf = ib.gbuf;
+    a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.k = ib.k; a.src = ib.src;
+    a.lab = ib.lab; a.lab_row = ib.lab_row; a.lab16 = ib.lab16;
     const int nyb = (g.NY + 63) / 64;
     hipLaunchKernelGGL(k_part, dim3((unsigned)(2 * npairs * nyb)), dim3(64), 0, s, a);
     return hipGetLastError();
