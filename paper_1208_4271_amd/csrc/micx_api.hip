@@ -196,7 +196,8 @@ int prepare_variables(micx_ctx *ctx, const void *X, int dtype, int m, int n, con
     RETCHK(ctx->perm.ensure(mn * sizeof(int)));
     RETCHK(ctx->gsize.ensure(mn * sizeof(int)));
     RETCHK(ctx->grank.ensure(mn * sizeof(int)));
-    RETCHK(ctx->rowof.ensure(mn * g.NY * sizeof(uint16_t)));
+    const int NYP = (g.NY + 7) / 8 * 8;
+    RETCHK(ctx->rowof.ensure(mn * NYP * sizeof(uint16_t)));
     RETCHK(ctx->yhat.ensure((size_t)m * g.NY * sizeof(int)));
     RETCHK(ctx->xlogx.ensure((size_t)(n + 1) * sizeof(double)));
     RETCHK(ctx->status.ensure(sizeof(int)));
@@ -206,6 +207,7 @@ int prepare_variables(micx_ctx *ctx, const void *X, int dtype, int m, int n, con
     rt.gsize = ctx->gsize.as<int>();
     rt.grank = ctx->grank.as<int>();
     et.NY = g.NY;
+    et.NYP = NYP;
     et.rowof = ctx->rowof.as<uint16_t>();
     et.yhat = ctx->yhat.as<int>();
     et.RS = g.NY + 2;

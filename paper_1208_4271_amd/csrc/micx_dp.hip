@@ -84,7 +84,8 @@ DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol) 
     p.NL = round_up_in(std::min(nf, nlcap), NLS, 17, 36);
     p.YR = round_up_in(y, YRS, 14, 0);
     if (!have_shape(p.NL, p.YR)) p.YR = 0;
-    p.T = (p.NL >= 5 && p.YR > 0 && p.YR <= 12) ? 2 : 1;
+    // two targets per lane pay off where a pass holds many layers (measured)
+    p.T = (p.NL >= 20 && p.YR > 0 && p.YR <= 12) ? 2 : 1;
     const int tforce = env_int("MICX_DP_T", 0);
     if (tforce == 1 || (tforce == 2 && p.NL >= 5 && p.YR > 0 && p.YR <= 12)) p.T = tforce;
     if (x == 2) {                                      // no full layer: the lean shape
@@ -99,15 +100,13 @@ DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol) 
     p.slot_bytes = (size_t)x * (size_t)p.KS * vb;      // layers 0..x-1 (0 unused)
     const int lds_L = align16((size_t)(n + 1) * vb);
     const int lds_rec = align16((size_t)(kh + 1) * p.RS * 4);
-    const int lds_pub = align16((size_t)NLP * vb);
     const int budget = 160 * 1024;
     p.WPB = 4;
     for (p.SB = 64; p.SB >= 8; p.SB >>= 1) {
         const int lds_stage = align16(std::max((size_t)p.SB * NLP * vb, (size_t)n));
-        const int wave = align16((size_t)lds_stage + lds_pub + lds_rec);
+        const int wave = align16((size_t)lds_stage + lds_rec);
         p.lds_L = lds_L;
         p.lds_stage = lds_stage;
-        p.lds_pub = lds_pub;
         p.lds_wave = wave;
         p.lds = lds_L + p.WPB * wave;
         if (p.lds * 2 <= budget) break;     // two workgroups per CU
@@ -151,7 +150,7 @@ hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry
     a.lab = ib.lab; a.lab_row = ib.lab_row; a.lab16 = ib.lab16;
     a.xlogx = xlogx; a.fxtab = fxtab; a.inv_scale = 1.0 / p.scale;
     a.scratch = scratch; a.slot_bytes = p.slot_bytes;
-    a.lds_L = p.lds_L; a.lds_stage = p.lds_stage; a.lds_pub = p.lds_pub; a.lds_wave = p.lds_wave;
+    a.lds_L = p.lds_L; a.lds_stage = p.lds_stage; a.lds_wave = p.lds_wave;
     dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T);
     if (!k) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,

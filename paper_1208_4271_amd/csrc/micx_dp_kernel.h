@@ -58,7 +58,7 @@ struct DpArgs {
     double inv_scale;            // 1 / S (uint32 form)
     void *scratch;
     size_t slot_bytes;           // G table bytes per wavefront
-    int lds_L, lds_stage, lds_pub, lds_wave;
+    int lds_L, lds_stage, lds_wave;
 };
 
 template <class V> struct DpVal;
@@ -69,6 +69,13 @@ template <> struct DpVal<double> {
     __device__ static double mn(double a, double b) { return fmin(a, b); }
     __device__ static double big() { return INFINITY; }
     __device__ static double real(double g, double) { return g; }
+    // value of lane `src` (uniform) in every lane
+    __device__ static double bcast(double v, int src) {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), src);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    }
 };
 
 template <> struct DpVal<uint32_t> {
@@ -77,6 +84,7 @@ template <> struct DpVal<uint32_t> {
     __device__ static uint32_t mn(uint32_t a, uint32_t b) { return a < b ? a : b; }
     __device__ static uint32_t big() { return 0xffffffffu; }
     __device__ static double real(uint32_t g, double inv_scale) { return (double)g * inv_scale; }
+    __device__ static uint32_t bcast(uint32_t v, int src) { return (uint32_t)__builtin_amdgcn_readlane((int)v, src); }
 };
 
 // Build-time tuning knob: MICX_DP_GROUP (16-byte layer packs per scheduling
@@ -128,8 +136,7 @@ __global__ __launch_bounds__(256, (dp_min_waves<V, NL, YR, T>())) void k_dp(DpAr
     __syncthreads();
     unsigned char *wb = smem + a.lds_L + (size_t)wv * a.lds_wave;
     V *stage = (V *)wb;                                        // SB x NLP, or labels and flags
-    V *pub = (V *)(wb + a.lds_stage);                          // NLP
-    int *rec = (int *)(wb + a.lds_stage + a.lds_pub);          // (K+1) x RS: e_t, N_t[0..RS-2]
+    int *rec = (int *)(wb + a.lds_stage);                      // (K+1) x RS: e_t, N_t[0..RS-2]
     const int wpb = blockDim.x >> 6;
     const int gw = blockIdx.x * wpb + wv, nw = gridDim.x * wpb;
     V *G = (V *)((unsigned char *)a.scratch + (size_t)gw * a.slot_bytes);
@@ -322,40 +329,36 @@ __global__ __launch_bounds__(256, (dp_min_waves<V, NL, YR, T>())) void k_dp(DpAr
                     }
                     wave_sync();
                 }
-                // sources inside the chunk, in order: the owning lane publishes
-                // the source's layers; the costs are gathered before the wait
+                // sources inside the chunk, in order: the lane that owns source s
+                // holds its final layers; they are broadcast to the wave through
+                // scalar registers, and the next source's costs are gathered
+                // while this source's cells update
 #pragma unroll
                 for (int jo = 0; jo < T; jo++) {
                     const int sbeg = c0 + 64 * jo + 1;
                     // the chunk's last target is no source for any target of this chunk
                     const int send = min(c0 + 64 * jo + 64, min(c0 + 64 * T, K) - 1);
+                    V hs[T], hn[T];
+                    if (sbeg <= send) hsrc(sbeg, hs);
                     for (int s = sbeg; s <= send; s++) {
                         const int ln = s - sbeg;
-                        V hs[T];
-                        hsrc(s, hs);
-                        if (lane == ln) {
+                        if (s < send) hsrc(s + 1, hn);
 #pragma unroll
-                            for (int q = 0; q < NLP; q += PK) {
-                                Pack<V> w;
+                        for (int q0 = 0; q0 < NL; q0 += 8) {
+                            V src[8];
 #pragma unroll
-                                for (int e = 0; e < PK; e++)
-                                    w.v[e] = (q + e == 0) ? gprev[jo] : g[jo][q + e - 1];
-                                *(Pack<V> *)(pub + q) = w;
+                            for (int e = 0; e < 8; e++)
+                                if (q0 + e < NL) src[e] = DV::bcast(q0 + e == 0 ? gprev[jo] : g[jo][q0 + e - 1], ln);
+#pragma unroll
+                            for (int j = jo; j < T; j++) {
+                                if (j == jo && lane <= ln) continue;
+#pragma unroll
+                                for (int e = 0; e < 8; e++)
+                                    if (q0 + e < NL) g[j][q0 + e] = DV::mn(g[j][q0 + e], src[e] + hs[j]);
                             }
                         }
-                        wave_sync();
 #pragma unroll
-                        for (int j = jo; j < T; j++) {
-                            if (j == jo && lane <= ln) continue;
-#pragma unroll
-                            for (int q = 0; q < NLP; q += PK) {
-                                const Pack<V> v = *(const Pack<V> *)(pub + q);
-#pragma unroll
-                                for (int e = 0; e < PK; e++) g[j][q + e] = DV::mn(g[j][q + e], v.v[e] + hs[j]);
-                                if ((q / PK + 1) % MICX_DP_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
-                            }
-                        }
-                        wave_sync();
+                        for (int j = 0; j < T; j++) hs[j] = hn[j];
                     }
                 }
                 // the chunk's layers become sources for later chunks

@@ -21,7 +21,8 @@ struct RankTables {
 // Per-(variable, row count) equipartition tables.
 struct EquipTables {
     int NY = 0;             // number of row counts: y = 2 .. NY+1
-    uint16_t *rowof = nullptr;  // [v][p][y-2]: 0-based row of the tie group starting at position p
+    int NYP = 0;            // NY rounded up to a multiple of 8 (16-byte rows of rowof)
+    uint16_t *rowof = nullptr;  // [v][p][y-2], NYP per p: 0-based row of the tie group starting at p
     int *yhat = nullptr;        // [v][y-2]: rows produced
     int *rowstart = nullptr;    // [v][y-2][r]: start position of row r (r = 0..yhat), may be null
     int RS = 0;                 // stride of rowstart per (v, y): NY + 2
@@ -48,7 +49,7 @@ struct DpPlan {
     int NL = 0, YR = 0, T = 0;    // kernel template: layers per pass, rows in registers, targets per lane
     int x = 0, KS = 0, RS = 0;    // columns, G-table row stride, count-record stride
     int SB = 0, WPB = 0;          // sources staged per block, wavefronts per workgroup
-    int lds = 0, lds_L = 0, lds_stage = 0, lds_pub = 0, lds_wave = 0;
+    int lds = 0, lds_L = 0, lds_stage = 0, lds_wave = 0;
     int blocks_per_cu = 0, max_waves = 0;
     size_t slot_bytes = 0;        // G table bytes per wavefront
 };

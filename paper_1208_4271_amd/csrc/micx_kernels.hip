@@ -116,7 +116,7 @@ __global__ __launch_bounds__(1024) void k_rank(const void *X, int dtype, int m, 
 // |a + s - R/L| >= |a - R/L| (row not empty) is equivalent to the integer
 // test (2a + s) * L >= 2R, used here so that the partition is bit-exact.
 
-__global__ __launch_bounds__(64) void k_equip(int m, int n, int NY, const int *gsize,
+__global__ __launch_bounds__(64) void k_equip(int m, int n, int NY, int NYP, const int *gsize,
                                               uint16_t *rowof, int *yhat, int *rowstart, int RS) {
     const int nyb = (NY + 63) / 64;
     const int v = blockIdx.x / nyb, yb = blockIdx.x % nyb;
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(64) void k_equip(int m, int n, int NY, const int *g
     const bool act = yi < NY;
     const int y = yi + 2;
     const int *gs = gsize + (size_t)v * n;
-    uint16_t *ro = rowof + (size_t)v * n * NY + yi;
+    uint16_t *ro = rowof + (size_t)v * n * NYP + yi;
     int *rs = rowstart ? rowstart + ((size_t)v * NY + yi) * RS : nullptr;
     int r = 0, a = 0, R = n, L = y;
     if (act && rs) rs[0] = 0;
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(64) void k_equip(int m, int n, int NY, const int *g
             L = y - r;
             if (act && rs) rs[r] = p;
         }
-        if (act) ro[(size_t)p * NY] = (uint16_t)r;
+        if (act) ro[(size_t)p * NYP] = (uint16_t)r;
         a += s;
         p += s;
     }
@@ -164,18 +164,24 @@ __global__ __launch_bounds__(64) void k_equip(int m, int n, int NY, const int *g
 // clump list is kept only while it fits in khat entries.
 
 struct PartArgs {
-    int n, NY, KSUM;
+    int n, NY, NYP, KSUM;
     PairSource ps;
     const int *perm, *gsize, *grank;
-    const uint16_t *rowof;
+    const uint16_t *rowof;       // [v][p][NYP]
     const int *khat, *koff;
     int *cbuf, *sbuf, *K, *k, *src;
     unsigned char *lab;          // row labels in column order, [item][y-2][p]
     size_t lab_row;
-    int lab16;
 };
 
+// LDS tile of one 64-point block: each point's labels for the wave's row
+// counts (up to 64 x 2 bytes), rows 144 bytes apart so that the 16-byte row
+// writes of neighbouring lanes fall in different banks.
+constexpr int PART_TILE = 144;
+
+template <bool L16>
 __global__ __launch_bounds__(64) void k_part(PartArgs a) {
+    __shared__ __align__(16) unsigned char tile[64 * PART_TILE];
     const int nyb = (a.NY + 63) / 64;
     const int w = blockIdx.x;
     const int yb = w % nyb, po = w / nyb;
@@ -184,7 +190,8 @@ __global__ __launch_bounds__(64) void k_part(PartArgs a) {
     pair_of(a.ps, pl, pi, pj);
     const int U = o ? pj : pi, V = o ? pi : pj;
     const int lane = threadIdx.x;
-    const int yi = yb * 64 + lane;
+    const int y0 = yb * 64, yi = y0 + lane;
+    const int nlab = min(64, a.NYP - y0);    // labels per point held in the tile (multiple of 8)
     const bool act = yi < a.NY;
     const int yic = act ? yi : a.NY - 1;
     const int n = a.n;
@@ -195,7 +202,8 @@ __global__ __launch_bounds__(64) void k_part(PartArgs a) {
     const int *permU = a.perm + (size_t)U * n;
     const int *gsU = a.gsize + (size_t)U * n;
     const int *grV = a.grank + (size_t)V * n;
-    const uint16_t *rowV = a.rowof + (size_t)V * n * a.NY + yic;
+    const uint16_t *rowV = a.rowof + (size_t)V * n * a.NYP + y0;
+    uint4 *labo = (uint4 *)(a.lab + ((size_t)po * a.NY + yic) * a.lab_row);
 
     int first = 0, mixed = 0, gstart = 0;   // current tie group of the column variable
     int last = -2;                           // label of the previous group: -2 none, -1 mixed
@@ -223,48 +231,44 @@ __global__ __launch_bounds__(64) void k_part(PartArgs a) {
         last = lg;
     };
 
+    // per-point reads of the next 64-point block, issued one block ahead:
+    // column-group size and the row variable's group rank
+    int gsz_n = 0, grk_n = 0;
+    if (lane < n) {
+        gsz_n = gsU[lane];
+        grk_n = grV[permU[lane]];
+    }
     for (int p0 = 0; p0 < n; p0 += 64) {
-        // stage 64 points: column-group size and row-variable group rank
         const int q = p0 + lane;
-        int gsz = 0, grk = 0;
-        if (q < n) {
-            gsz = gsU[q];
-            grk = grV[permU[q]];
-        }
+        const int gsz = gsz_n, grk = grk_n;
         const int cnt = min(64, n - p0);
-        int labs[64];
+        // this lane's point: its labels for the wave's row counts into the tile
+        if (q < n) {
+            const uint4 *src = (const uint4 *)(rowV + (size_t)grk * a.NYP);
+            uint4 *dst = (uint4 *)(tile + lane * PART_TILE);
 #pragma unroll
-        for (int s = 0; s < 64; s++) {
-            const int g = __builtin_amdgcn_readlane(grk, s);
-            labs[s] = (s < cnt) ? (int)rowV[(size_t)g * a.NY] : 0;
+            for (int v = 0; v < 8; v++)
+                if (8 * v < nlab) dst[v] = src[v];
         }
-        // this lane's row labels of the 64 points, for the DP's count table
-        // (the row is padded to whole 64-point blocks; padding holds 0)
-        if (act) {
-            uint4 *dst = (uint4 *)(a.lab + ((size_t)po * a.NY + yi) * a.lab_row) + (p0 >> (a.lab16 ? 3 : 4));
-            if (a.lab16) {
-#pragma unroll
-                for (int v = 0; v < 8; v++) {
-                    const int *l = labs + 8 * v;
-                    dst[v] = make_uint4(l[0] | l[1] << 16, l[2] | l[3] << 16, l[4] | l[5] << 16, l[6] | l[7] << 16);
-                }
-            } else {
-#pragma unroll
-                for (int v = 0; v < 4; v++) {
-                    const int *l = labs + 16 * v;
-                    dst[v] = make_uint4(l[0] | l[1] << 8 | l[2] << 16 | l[3] << 24,
-                                        l[4] | l[5] << 8 | l[6] << 16 | l[7] << 24,
-                                        l[8] | l[9] << 8 | l[10] << 16 | l[11] << 24,
-                                        l[12] | l[13] << 8 | l[14] << 16 | l[15] << 24);
-                }
-            }
+        if (q + 64 < n) {
+            gsz_n = gsU[q + 64];
+            grk_n = grV[permU[q + 64]];
         }
+        const uint64_t starts = __ballot(q < n && gsz > 0);   // tie-group starts of the block
+        wave_sync();
+        // the points in order; this lane's labels are packed for the DP's
+        // count table as they are read (padding beyond n holds 0)
+        constexpr int NW = L16 ? 32 : 16;
+        uint32_t pk[NW];
+#pragma unroll
+        for (int v = 0; v < NW; v++) pk[v] = 0;
 #pragma unroll
         for (int s = 0; s < 64; s++) {
             if (s < cnt) {
-                const int gs = __builtin_amdgcn_readlane(gsz, s);
-                const int lab = labs[s];
-                if (gs > 0) {
+                const int lab = *(const uint16_t *)(tile + s * PART_TILE + 2 * lane);
+                if (L16) pk[s >> 1] |= (uint32_t)lab << (16 * (s & 1));
+                else pk[s >> 2] |= (uint32_t)lab << (8 * (s & 3));
+                if ((starts >> s) & 1) {
                     if (p0 + s > 0) close_group();
                     first = lab;
                     mixed = 0;
@@ -274,6 +278,12 @@ __global__ __launch_bounds__(64) void k_part(PartArgs a) {
                 }
             }
         }
+        if (act) {
+            uint4 *d = labo + (p0 >> (L16 ? 3 : 4));
+#pragma unroll
+            for (int v = 0; v < NW / 4; v++) d[v] = make_uint4(pk[4 * v], pk[4 * v + 1], pk[4 * v + 2], pk[4 * v + 3]);
+        }
+        wave_sync();   // the tile is rewritten by the next block
     }
     close_group();
     emit_clump(n);
@@ -411,7 +421,7 @@ hipError_t launch_rank(const void *X, int dtype, int m, int n, RankTables &rt, i
 
 hipError_t launch_equip(const RankTables &rt, EquipTables &et, hipStream_t s) {
     const int nyb = (et.NY + 63) / 64;
-    hipLaunchKernelGGL(k_equip, dim3(rt.m * nyb), dim3(64), 0, s, rt.m, rt.n, et.NY, rt.gsize,
+    hipLaunchKernelGGL(k_equip, dim3(rt.m * nyb), dim3(64), 0, s, rt.m, rt.n, et.NY, et.NYP, rt.gsize,
                        et.rowof, et.yhat, et.rowstart, et.RS);
     return hipGetLastError();
 }
@@ -420,12 +430,13 @@ hipError_t launch_part(const RankTables &rt, const EquipTables &et, const Geomet
                        PairSource ps, int npairs, ItemBuffers &ib, hipStream_t s) {
     PartArgs a;
     a.n = rt.n; a.NY = g.NY; a.KSUM = g.KSUM; a.ps = ps;
-    a.perm = rt.perm; a.gsize = rt.gsize; a.grank = rt.grank; a.rowof = et.rowof;
+    a.perm = rt.perm; a.gsize = rt.gsize; a.grank = rt.grank; a.rowof = et.rowof; a.NYP = et.NYP;
     a.khat = g.khat; a.koff = g.koff;
     a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.k = ib.k; a.src = ib.src;
-    a.lab = ib.lab; a.lab_row = ib.lab_row; a.lab16 = ib.lab16;
+    a.lab = ib.lab; a.lab_row = ib.lab_row;
     const int nyb = (g.NY + 63) / 64;
-    hipLaunchKernelGGL(k_part, dim3((unsigned)(2 * npairs * nyb)), dim3(64), 0, s, a);
+    if (ib.lab16) hipLaunchKernelGGL(k_part<true>, dim3((unsigned)(2 * npairs * nyb)), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL(k_part<false>, dim3((unsigned)(2 * npairs * nyb)), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
