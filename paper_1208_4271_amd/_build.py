@@ -70,9 +70,7 @@ def _compile(src, obj, verbose, defines=(), check_spills=True, device_only=False
     if check_spills:
         bad = sorted(k for k, u in usage.items() if u.get("ScratchSize", 0) or u.get("VGPRs Spill", 0))
         if bad:
-            raise RuntimeError("DP kernels of %s spill registers (fx, NL, YR, T): %s; regenerate the "
-                               "occupancy table (python -m paper_1208_4271_amd.gen_dp_occupancy)"
-                               % (src, bad))
+            raise RuntimeError("DP kernels of %s spill registers (fx, NL, YR, T): %s" % (src, bad))
     return usage
 
 

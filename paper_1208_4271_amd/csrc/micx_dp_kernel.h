@@ -38,7 +38,6 @@
 #include <type_traits>
 
 #include "micx_device.h"
-#include "micx_dp_occupancy.h"
 
 namespace micx {
 
@@ -88,28 +87,15 @@ template <> struct DpVal<uint32_t> {
 };
 
 // Build-time tuning knob: MICX_DP_GROUP (16-byte layer packs per scheduling
-// group).  MICX_DP_OCC_FORCE sets one occupancy target for every shape (used
-// only when the occupancy table is regenerated).
+// group).
 #ifndef MICX_DP_GROUP
 #define MICX_DP_GROUP 4
 #endif
 
-// Occupancy target (waves per SIMD) of a kernel shape: the largest target at
-// which the shape compiles without spilling registers, from the generated
-// table; shapes not in it get no target.  A spill-free DP is required: spill
-// code placed inside a divergent region leaves the slots of inactive lanes
-// unwritten, and the build rejects any DP kernel that spills.
-template <class V, int NL, int YR, int T>
-constexpr int dp_min_waves() {
-#ifdef MICX_DP_OCC_FORCE
-    return MICX_DP_OCC_FORCE;
-#else
-    constexpr int fx = std::is_same<V, uint32_t>::value ? 1 : 0;
-    for (const DpOcc &e : kDpOcc)
-        if (e.fx == fx && e.nl == NL && e.yr == YR && e.t == T) return e.waves;
-    return 1;
-#endif
-}
+// No occupancy target is set: the compiler's own register allocation was
+// measured faster than every target that compiles without spills, and the
+// build rejects any DP kernel that spills (spill code placed inside a
+// divergent region leaves the slots of inactive lanes unwritten).
 
 template <class V>
 struct alignas(16) Pack {
@@ -117,7 +103,7 @@ struct alignas(16) Pack {
 };
 
 template <class V, int NL, int YR, int T>
-__global__ __launch_bounds__(256, (dp_min_waves<V, NL, YR, T>())) void k_dp(DpArgs a) {
+__global__ __launch_bounds__(256) void k_dp(DpArgs a) {
     using DV = DpVal<V>;
     constexpr int PK = DV::PK;
     constexpr int NLP = (NL + PK - 1) / PK * PK;
