@@ -136,6 +136,33 @@ int micx_pairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n,
                const int32_t *pairs_host, int64_t npairs,
                double alpha, double c, int mode, double *out_dev, void *stream);
 
+/* One independent pair of a batch: both variables are n consecutive
+ * elements of the packed data buffer, at element offsets off_x and off_y;
+ * alpha and c are the pair's own parameters. */
+typedef struct {
+    int64_t off_x;
+    int64_t off_y;
+    int32_t n;
+    int32_t reserved;     /* set to 0 */
+    double alpha;
+    double c;
+} micx_pair_desc;
+
+/* A stream of independent pairs of uneven n and uneven (alpha, c), each
+ * scored as by micx_compute_score on its own two variables.
+ * data_dev: DEVICE pointer to the packed variables, element type dtype
+ *        (MICX_F32/F64/I32), owned by the caller, read only.
+ * pairs_host: HOST array of npairs descriptors.  Every descriptor is checked
+ *        before any work starts: n in [2, MICX_MAX_N], floor(n^alpha) >= 4,
+ *        alpha in (0, 1], c > 0, offsets >= 0 (the caller guarantees that
+ *        off + n lies inside data_dev).
+ * out_dev: DEVICE pointer to npairs * 4 doubles owned by the caller; pair k
+ *        is written at 4k as (MIC, MAS, MEV, MCN), x the first variable.
+ *        On any error out_dev is left untouched.
+ * Pairs that share (n, alpha, c) run together.  Synchronous on stream. */
+int micx_batch(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pair_desc *pairs_host,
+               int64_t npairs, int mode, double *out_dev, void *stream);
+
 /* Integer stages of one item, read back for bit-exact tests.
  * x, y: HOST arrays of n doubles.  orient 0: columns from x, rows from y;
  * orient 1: swapped.  ry: requested row count, 2 <= ry <= floor(B/2).
@@ -148,7 +175,7 @@ int micx_debug_item(micx_ctx *ctx, const double *x, const double *y, int n,
                     double alpha, double c, int orient, int ry,
                     int *yhat, int *row_starts, int *k, int *K, int *ends);
 
-/* Instrumentation of the pair calls (micx_allpairs, micx_pairs).
+/* Instrumentation of the pair calls (micx_allpairs, micx_pairs, micx_batch).
  * With profiling enabled, each call records HIP events on its stream around
  * every launch of the dynamic-program kernel and counts the algorithmic work
  * of its items from their actual sizes (K (super)clumps, yhat rows, x

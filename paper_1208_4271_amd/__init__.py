@@ -33,7 +33,7 @@ MODE_DP32 = 1
 EXPORTS = (
     "micx_ctx_create", "micx_ctx_destroy", "micx_check_param", "micx_grid_bound",
     "micx_compute_score", "micx_mic", "micx_mas", "micx_mev", "micx_mcn", "micx_free_score",
-    "micx_allpairs", "micx_pairs", "micx_debug_item", "micx_strerror",
+    "micx_allpairs", "micx_pairs", "micx_batch", "micx_debug_item", "micx_strerror",
     "micx_set_profiling", "micx_get_profile", "micx_set_dp32_tolerance",
 )
 
@@ -48,6 +48,11 @@ class _Score(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("B", ctypes.c_int), ("W", ctypes.c_int),
                 ("M", ctypes.POINTER(ctypes.c_double)), ("Axy", ctypes.POINTER(ctypes.c_double)),
                 ("Ayx", ctypes.POINTER(ctypes.c_double)), ("stats", ctypes.c_double * 4)]
+
+
+class _PairDesc(ctypes.Structure):
+    _fields_ = [("off_x", ctypes.c_int64), ("off_y", ctypes.c_int64), ("n", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("alpha", ctypes.c_double), ("c", ctypes.c_double)]
 
 
 class _Profile(ctypes.Structure):
@@ -96,6 +101,8 @@ def load_library():
     lib.micx_pairs.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_int32),
                                ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp, vp]
     lib.micx_pairs.restype = ctypes.c_int
+    lib.micx_batch.argtypes = [vp, vp, ctypes.c_int, P(_PairDesc), ctypes.c_int64, ctypes.c_int, vp, vp]
+    lib.micx_batch.restype = ctypes.c_int
     lib.micx_debug_item.argtypes = [vp, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_int, ctypes.c_int, ip, ip, ip, ip, ip]
     lib.micx_debug_item.restype = ctypes.c_int
@@ -223,6 +230,37 @@ def pairs(X, pair_list, alpha: float = 0.6, c: float = 15.0, mode: int = MODE_FP
                                    float(alpha), float(c), int(mode),
                                    ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
     _check(rc, "micx_pairs")
+    return out
+
+
+def batch(data, off_x, off_y, ns, alphas, cs, mode: int = MODE_FP64, out=None, stream=None):
+    """Independent pairs of uneven n and (alpha, c) from a packed 1-D CUDA
+    tensor `data` (float32/float64/int32): pair k is data[off_x[k]:+ns[k]]
+    against data[off_y[k]:+ns[k]] with parameters (alphas[k], cs[k]).
+    Returns an (npairs, 4) float64 CUDA tensor of (MIC, MAS, MEV, MCN)."""
+    import torch
+    if not data.is_cuda or data.dim() != 1:
+        raise ValueError("data must be a 1-D CUDA tensor")
+    data = data.contiguous()
+    dt = _DTYPES.get(str(data.dtype))
+    if dt is None:
+        raise ValueError("data dtype must be float32, float64 or int32")
+    off_x, off_y, ns = (np.asarray(a, dtype=np.int64).ravel() for a in (off_x, off_y, ns))
+    alphas, cs = (np.asarray(a, dtype=np.float64).ravel() for a in (alphas, cs))
+    npairs = len(ns)
+    if not (len(off_x) == len(off_y) == len(alphas) == len(cs) == npairs) or npairs < 1:
+        raise ValueError("descriptor arrays must be non-empty and of one length")
+    if ((off_x + ns) > data.numel()).any() or ((off_y + ns) > data.numel()).any():
+        raise ValueError("a pair reaches past the end of data")
+    descs = (_PairDesc * npairs)()
+    for k in range(npairs):
+        descs[k] = _PairDesc(int(off_x[k]), int(off_y[k]), int(ns[k]), 0, float(alphas[k]), float(cs[k]))
+    if out is None:
+        out = torch.empty((npairs, 4), dtype=torch.float64, device=data.device)
+    rc = load_library().micx_batch(context(data.device.index or 0), ctypes.c_void_p(data.data_ptr()),
+                                   dt, descs, npairs, int(mode), ctypes.c_void_p(out.data_ptr()),
+                                   _stream_ptr(stream))
+    _check(rc, "micx_batch")
     return out
 
 

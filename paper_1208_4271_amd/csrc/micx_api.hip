@@ -11,6 +11,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <map>
+#include <thread>
+#include <tuple>
 #include <vector>
 
 #include "micx.h"
@@ -53,9 +57,13 @@ struct micx_ctx {
     DevBuf geo;        // xcnt | khat | koff | aoff
     DevBuf cbuf, sbuf, Kb, kb, srcb, A, scratch, pairs, input, out, dense;
     DevBuf counters, fxtab, lab;
+    DevBuf bdata, boffs, bout, bidx;   // micx_batch: gathered variables, offsets, staged results
     double dp32_tol = 1e-7;
     int profiling = 0;
     micx_profile prof = {};
+    // micx_batch workers: sub-contexts (own buffers) with their own streams
+    std::vector<micx_ctx *> workers;
+    std::vector<hipStream_t> wstreams;
 };
 
 #define HIPCHK(expr)                                   \
@@ -113,8 +121,11 @@ extern "C" void micx_ctx_destroy(micx_ctx *c) {
     DevBuf *all[] = {&c->perm, &c->gsize, &c->grank, &c->rowof, &c->yhat, &c->rowstart,
                      &c->xlogx, &c->status, &c->geo, &c->cbuf, &c->sbuf, &c->Kb, &c->kb,
                      &c->srcb, &c->A, &c->scratch, &c->pairs, &c->input, &c->out, &c->dense,
-                     &c->counters, &c->fxtab, &c->lab};
+                     &c->counters, &c->fxtab, &c->lab,
+                     &c->bdata, &c->boffs, &c->bout, &c->bidx};
     for (DevBuf *b : all) b->release();
+    for (micx_ctx *w : c->workers) micx_ctx_destroy(w);
+    for (hipStream_t st : c->wstreams) hipStreamDestroy(st);
     delete c;
 }
 
@@ -161,7 +172,7 @@ void make_geometry(int n, int B, double c, HostGeometry &hg) {
     g.khat_host = hg.khat.data();
 }
 
-int upload_geometry(micx_ctx *ctx, HostGeometry &hg) {
+int upload_geometry(micx_ctx *ctx, HostGeometry &hg, hipStream_t s) {
     const int NY = hg.g.NY;
     RETCHK(ctx->geo.ensure(sizeof(int) * 4 * (size_t)NY));
     int *d = ctx->geo.as<int>();
@@ -170,7 +181,8 @@ int upload_geometry(micx_ctx *ctx, HostGeometry &hg) {
     std::copy(hg.khat.begin(), hg.khat.end(), h.begin() + NY);
     std::copy(hg.koff.begin(), hg.koff.end(), h.begin() + 2 * NY);
     std::copy(hg.aoff.begin(), hg.aoff.end(), h.begin() + 3 * NY);
-    HIPCHK(hipMemcpy(d, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(d, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));   // h is released on return
     hg.g.xcnt = d;
     hg.g.khat = d + NY;
     hg.g.koff = d + 2 * NY;
@@ -383,7 +395,7 @@ extern "C" int micx_allpairs(micx_ctx *ctx, const void *X_dev, int dtype, int m,
     hipStream_t s = (hipStream_t)stream;
     HostGeometry hg;
     make_geometry(n, micx_grid_bound(n, alpha), c, hg);
-    RETCHK(upload_geometry(ctx, hg));
+    RETCHK(upload_geometry(ctx, hg, s));
     RankTables rt;
     EquipTables et;
     RETCHK(prepare_variables(ctx, X_dev, dtype, m, n, hg.g, false, rt, et, s));
@@ -408,7 +420,7 @@ extern "C" int micx_pairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, in
     hipStream_t s = (hipStream_t)stream;
     HostGeometry hg;
     make_geometry(n, micx_grid_bound(n, alpha), c, hg);
-    RETCHK(upload_geometry(ctx, hg));
+    RETCHK(upload_geometry(ctx, hg, s));
     RETCHK(ctx->pairs.ensure((size_t)npairs * 2 * sizeof(int32_t)));
     HIPCHK(hipMemcpyAsync(ctx->pairs.p, pairs_host, (size_t)npairs * 2 * sizeof(int32_t),
                           hipMemcpyHostToDevice, s));
@@ -421,6 +433,151 @@ extern "C" int micx_pairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, in
     return MICX_OK;
 }
 
+namespace {
+
+// One group of a batch: pairs that share (n, alpha, c), run as a pair list
+// over their gathered variables; results go to rows [row0, row0 + P) of the
+// parent's staging buffer.
+struct BatchGroup {
+    int n;
+    double alpha, c, cost;
+    std::vector<int64_t> idx;
+    int64_t row0;
+};
+
+int run_batch_group(micx_ctx *w, const void *data_dev, int dtype, const micx_pair_desc *pairs_host,
+                    const BatchGroup &bg, int mode, double *rows_dev, hipStream_t s) {
+    const int n = bg.n, esize = dtype == MICX_F64 ? 8 : 4;
+    const int64_t P = (int64_t)bg.idx.size();
+    std::vector<int64_t> offs(2 * P);
+    std::vector<int32_t> pl(2 * P);
+    for (int64_t i = 0; i < P; i++) {
+        offs[2 * i] = pairs_host[bg.idx[i]].off_x;
+        offs[2 * i + 1] = pairs_host[bg.idx[i]].off_y;
+        pl[2 * i] = (int32_t)(2 * i);
+        pl[2 * i + 1] = (int32_t)(2 * i + 1);
+    }
+    RETCHK(w->boffs.ensure(offs.size() * sizeof(int64_t)));
+    RETCHK(w->pairs.ensure(pl.size() * sizeof(int32_t)));
+    RETCHK(w->bdata.ensure((size_t)2 * P * n * esize));
+    HIPCHK(hipMemcpyAsync(w->boffs.p, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(w->pairs.p, pl.data(), pl.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_gather(data_dev, esize, w->boffs.as<int64_t>(), (int)(2 * P), n, w->bdata.p, s));
+    HostGeometry hg;
+    make_geometry(n, micx_grid_bound(n, bg.alpha), bg.c, hg);
+    RETCHK(upload_geometry(w, hg, s));
+    RankTables rt;
+    EquipTables et;
+    RETCHK(prepare_variables(w, w->bdata.p, dtype, (int)(2 * P), n, hg.g, false, rt, et, s));
+    RETCHK(run_pairs(w, rt, et, hg.g, w->pairs.as<int32_t>(), P, (int)(2 * P), mode, rows_dev, nullptr,
+                     nullptr, nullptr, s));
+    HIPCHK(hipStreamSynchronize(s));   // offs and pl live until here
+    return MICX_OK;
+}
+
+void add_profile(micx_profile &t, const micx_profile &p) {
+    t.items += p.items;
+    t.dp_cells += p.dp_cells;
+    t.h_evals += p.h_evals;
+    t.h_terms += p.h_terms;
+    t.dp_ms += p.dp_ms;
+    t.dp_launches += p.dp_launches;
+    t.dp32_classes += p.dp32_classes;
+    t.fp64_classes += p.fp64_classes;
+    t.dp32_bound = std::max(t.dp32_bound, p.dp32_bound);
+}
+
+constexpr int kBatchWorkers = 8;
+
+}  // namespace
+
+extern "C" int micx_batch(micx_ctx *ctx, const void *data_dev, int dtype,
+                          const micx_pair_desc *pairs_host, int64_t npairs, int mode, double *out_dev,
+                          void *stream) {
+    if (!ctx || !data_dev || !pairs_host || !out_dev || npairs < 1) return MICX_EINVAL;
+    if (dtype != MICX_F32 && dtype != MICX_F64 && dtype != MICX_I32) return MICX_EINVAL;
+    for (int64_t k = 0; k < npairs; k++) {
+        const micx_pair_desc &d = pairs_host[k];
+        RETCHK(check_common(ctx, d.n, d.alpha, d.c, mode));
+        if (d.off_x < 0 || d.off_y < 0) return MICX_EINVAL;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipStreamSynchronize(s));   // the data is ready for the worker streams
+    // pairs that share (n, alpha, c) share the grid geometry and run as one list;
+    // groups are handed to the workers largest first (cost ~ P n B^3 c^2)
+    std::map<std::tuple<int, double, double>, std::vector<int64_t>> byKey;
+    for (int64_t k = 0; k < npairs; k++)
+        byKey[std::make_tuple(pairs_host[k].n, pairs_host[k].alpha, pairs_host[k].c)].push_back(k);
+    std::vector<BatchGroup> groups;
+    groups.reserve(byKey.size());
+    for (auto &kv : byKey) {
+        BatchGroup g;
+        g.n = std::get<0>(kv.first);
+        g.alpha = std::get<1>(kv.first);
+        g.c = std::get<2>(kv.first);
+        const double B = (double)micx_grid_bound(g.n, g.alpha);
+        g.cost = (double)kv.second.size() * (double)g.n * B * B * B * g.c * g.c;
+        g.idx = std::move(kv.second);
+        groups.push_back(std::move(g));
+    }
+    std::sort(groups.begin(), groups.end(), [](const BatchGroup &a, const BatchGroup &b) { return a.cost > b.cost; });
+    std::vector<int64_t> order;
+    order.reserve(npairs);
+    for (BatchGroup &g : groups) {
+        g.row0 = (int64_t)order.size();
+        order.insert(order.end(), g.idx.begin(), g.idx.end());
+    }
+    RETCHK(ctx->bout.ensure((size_t)npairs * 4 * sizeof(double)));
+    RETCHK(ctx->bidx.ensure((size_t)npairs * sizeof(int64_t)));
+    const int nw = (int)std::min<size_t>(kBatchWorkers, groups.size());
+    while ((int)ctx->workers.size() < nw) {
+        micx_ctx *w = nullptr;
+        RETCHK(micx_ctx_create(&w, ctx->device));
+        hipStream_t ws;
+        if (hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) {
+            micx_ctx_destroy(w);
+            return MICX_EDEVICE;
+        }
+        ctx->workers.push_back(w);
+        ctx->wstreams.push_back(ws);
+    }
+    std::atomic<size_t> next{0};
+    std::atomic<int> err{MICX_OK};
+    double *rows = ctx->bout.as<double>();
+    auto work = [&](int wi) {
+        micx_ctx *w = ctx->workers[wi];
+        hipSetDevice(ctx->device);
+        w->dp32_tol = ctx->dp32_tol;
+        w->profiling = ctx->profiling;
+        micx_profile tot{};
+        for (size_t g; (g = next.fetch_add(1)) < groups.size();) {
+            if (err.load() != MICX_OK) break;
+            const int rc = run_batch_group(w, data_dev, dtype, pairs_host, groups[g], mode,
+                                           rows + 4 * groups[g].row0, ctx->wstreams[wi]);
+            if (rc != MICX_OK) {
+                int expect = MICX_OK;
+                err.compare_exchange_strong(expect, rc);
+                break;
+            }
+            add_profile(tot, w->prof);
+        }
+        w->prof = tot;
+    };
+    std::vector<std::thread> th;
+    for (int wi = 0; wi < nw; wi++) th.emplace_back(work, wi);
+    for (std::thread &t : th) t.join();
+    if (err.load() != MICX_OK) return err.load();
+    micx_profile total{};
+    for (int wi = 0; wi < nw; wi++) add_profile(total, ctx->workers[wi]->prof);
+    HIPCHK(hipMemcpyAsync(ctx->bidx.p, order.data(), order.size() * sizeof(int64_t),
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(launch_scatter_rows(rows, ctx->bidx.as<int64_t>(), npairs, out_dev, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->prof = total;
+    return MICX_OK;
+}
+
 extern "C" int micx_compute_score(micx_ctx *ctx, const double *x, const double *y, int n,
                                   double alpha, double c, int mode, micx_score **out) {
     RETCHK(check_common(ctx, n, alpha, c, mode));
@@ -430,7 +587,7 @@ extern "C" int micx_compute_score(micx_ctx *ctx, const double *x, const double *
     HostGeometry hg;
     const int B = micx_grid_bound(n, alpha);
     make_geometry(n, B, c, hg);
-    RETCHK(upload_geometry(ctx, hg));
+    RETCHK(upload_geometry(ctx, hg, s));
     RETCHK(upload_pair_input(ctx, x, y, n, s));
     RankTables rt;
     EquipTables et;
@@ -522,7 +679,7 @@ extern "C" int micx_debug_item(micx_ctx *ctx, const double *x, const double *y, 
     hipStream_t s = nullptr;
     HostGeometry hg;
     make_geometry(n, B, c, hg);
-    RETCHK(upload_geometry(ctx, hg));
+    RETCHK(upload_geometry(ctx, hg, s));
     RETCHK(upload_pair_input(ctx, x, y, n, s));
     RankTables rt;
     EquipTables et;

@@ -102,14 +102,14 @@ DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol) 
     const int lds_rec = align16((size_t)(kh + 1) * p.RS * 4);
     const int budget = 160 * 1024;
     p.WPB = 4;
-    for (p.SB = 64; p.SB >= 8; p.SB >>= 1) {
+    for (p.SB = 64;; p.SB >>= 1) {
         const int lds_stage = align16(std::max((size_t)p.SB * NLP * vb, (size_t)n));
         const int wave = align16((size_t)lds_stage + lds_rec);
         p.lds_L = lds_L;
         p.lds_stage = lds_stage;
         p.lds_wave = wave;
         p.lds = lds_L + p.WPB * wave;
-        if (p.lds * 2 <= budget) break;     // two workgroups per CU
+        if (p.lds * 2 <= budget || p.SB == 8) break;     // two workgroups per CU
     }
     while (p.lds > budget && p.WPB > 1) {
         p.WPB--;
@@ -120,7 +120,7 @@ DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol) 
     p.blocks_per_cu = std::max(1, budget / std::max(p.lds, 1));
     dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T);
     int occ = 0;
-    if (k && hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds) ==
+    if (k && hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, budget) ==
                  hipSuccess &&
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k, 64 * p.WPB, p.lds) ==
                  hipSuccess &&
@@ -153,8 +153,11 @@ hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry
     a.lds_L = p.lds_L; a.lds_stage = p.lds_stage; a.lds_wave = p.lds_wave;
     dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T);
     if (!k) return hipErrorInvalidValue;
+    // the attribute is the whole LDS budget, the same for every caller (plans
+    // of different sizes may launch one kernel from several threads)
+    if (p.lds > 160 * 1024) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       p.lds);
+                                       160 * 1024);
     if (e != hipSuccess) return e;
     const int waves_needed = a.nitems;
     const int waves = std::min(waves_needed, p.max_waves);

@@ -93,6 +93,10 @@ hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry
 hipError_t launch_stats(const Geometry &g, int npairs, const ItemBuffers &ib, double *out,
                         double *M, double *Axy, double *Ayx, hipStream_t s);
 hipError_t launch_xlogx(int n, double *xlogx, hipStream_t s);
+hipError_t launch_gather(const void *src, int esize, const int64_t *offs, int nv, int n, void *dst,
+                         hipStream_t s);
+hipError_t launch_scatter_rows(const double *src, const int64_t *idx, int64_t rows, double *dst,
+                               hipStream_t s);
 // Accumulates the algorithmic work of a batch into counters[0..3]
 // (items, dp_cells, h_evals, h_terms).
 hipError_t launch_work(const EquipTables &et, const Geometry &g, PairSource ps, int npairs,

@@ -411,8 +411,10 @@ hipError_t launch_rank(const void *X, int dtype, int m, int n, RankTables &rt, i
     while (N2 < n) N2 <<= 1;
     const size_t lds = (size_t)N2 * (8 + 4 + 4);
     const int threads = N2 >= 1024 ? 1024 : (N2 < 64 ? 64 : N2);
+    // the attribute is the whole LDS budget, the same for every caller
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute((const void *)k_rank,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rank, dim3(m), dim3(threads), lds, s, X, dtype, m, n, N2, rt.perm,
                        rt.gsize, rt.grank, status);
@@ -453,6 +455,44 @@ int device_cus(int device) {
     hipDeviceProp_t p;
     if (hipGetDeviceProperties(&p, device) != hipSuccess) return 256;
     return p.multiProcessorCount;
+}
+
+// ------------------------------------------------------ batch gather/scatter
+// Variables of a batch, scattered over a packed buffer, are copied into the
+// rows of an nv x n matrix (one workgroup per variable); results computed in
+// group order go back to the caller's pair order.
+
+template <class E>
+__global__ void k_gather(const E *src, const int64_t *offs, int n, E *dst) {
+    const int v = blockIdx.x;
+    const E *s = src + offs[v];
+    E *d = dst + (size_t)v * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = s[i];
+}
+
+__global__ void k_scatter_rows(const double *src, const int64_t *idx, int64_t rows, double *dst) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 4 * rows) return;
+    dst[4 * idx[k >> 2] + (k & 3)] = src[k];
+}
+
+hipError_t launch_gather(const void *src, int esize, const int64_t *offs, int nv, int n, void *dst,
+                         hipStream_t s) {
+    if (esize == 8)
+        hipLaunchKernelGGL(k_gather<uint64_t>, dim3(nv), dim3(256), 0, s, (const uint64_t *)src, offs,
+                           n, (uint64_t *)dst);
+    else
+        hipLaunchKernelGGL(k_gather<uint32_t>, dim3(nv), dim3(256), 0, s, (const uint32_t *)src, offs,
+                           n, (uint32_t *)dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(const double *src, const int64_t *idx, int64_t rows, double *dst,
+                               hipStream_t s) {
+    const int64_t th = 4 * rows;
+    hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)((th + 255) / 256)), dim3(256), 0, s, src, idx,
+                       rows, dst);
+    return hipGetLastError();
 }
 
 }  // namespace micx

@@ -241,3 +241,89 @@ def test_alternating_forms_full_matrices(micx):
             got = micx.compute_score(x, y, 0.6, 15, mode=mode)
             tol = 1e-10 if mode == micx.MODE_FP64 else _bound(micx)[0] + 1e-12
             _cmp_scores(got, want, tol=tol)
+
+
+# ------------------------------------------------------------ batch stream
+def _stream_case(seed, npairs, nmin, nmax):
+    data, offx, offy, ns, alphas, cs = workloads.cfg5_stream(seed=seed, npairs=npairs, nmin=nmin,
+                                                             nmax=nmax)
+    return data, offx, offy, ns, alphas, cs
+
+
+def _stream_oracle(data, offx, offy, ns, alphas, cs, rows):
+    want = []
+    for k in rows:
+        n = int(ns[k])
+        x = data[offx[k]:offx[k] + n].astype(np.float64)
+        y = data[offy[k]:offy[k] + n].astype(np.float64)
+        want.append(oracle.score(x, y, float(alphas[k]), float(cs[k]))["stats"])
+    return np.array(want)
+
+
+@pytest.mark.parametrize("seed,npairs,nmin,nmax", [(51, 96, 50, 60), (52, 40, 50, 1500)],
+                         ids=["shared_n", "wide_n"])
+def test_batch_stream_matches_oracle(micx, seed, npairs, nmin, nmax):
+    import torch
+    _log("case batch stream seed=%d npairs=%d n in [%d, %d]" % (seed, npairs, nmin, nmax))
+    data, offx, offy, ns, alphas, cs = _stream_case(seed, npairs, nmin, nmax)
+    got = micx.batch(torch.from_numpy(data).cuda(), offx, offy, ns, alphas, cs).cpu().numpy()
+    want = _stream_oracle(data, offx, offy, ns, alphas, cs, range(npairs))
+    assert np.abs(got[:, :3] - want[:, :3]).max() <= TOL
+    assert (np.abs(got[:, 3] - want[:, 3]) < 1e-9).all()
+    # the DP32 form stays within its stated bound
+    got32 = micx.batch(torch.from_numpy(data).cuda(), offx, offy, ns, alphas, cs,
+                       mode=micx.MODE_DP32).cpu().numpy()
+    bound = micx.get_profile()["dp32_bound"]
+    assert np.abs(got32[:, :3] - want[:, :3]).max() <= max(bound, 1e-12) + 1e-12
+
+
+def test_batch_equals_single_pair_calls(micx):
+    import torch
+    _log("case batch vs compute_score")
+    data, offx, offy, ns, alphas, cs = _stream_case(53, 12, 60, 900)
+    got = micx.batch(torch.from_numpy(data).cuda(), offx, offy, ns, alphas, cs).cpu().numpy()
+    for k in range(len(ns)):
+        n = int(ns[k])
+        x = data[offx[k]:offx[k] + n].astype(np.float64)
+        y = data[offy[k]:offy[k] + n].astype(np.float64)
+        one = micx.compute_score(x, y, float(alphas[k]), float(cs[k]))["stats"]
+        assert np.abs(got[k] - one).max() <= 1e-12, (k, got[k], one)
+
+
+def test_batch_largest_pair(micx):
+    # the heaviest kind of pair in the stream: n near the maximum at alpha 0.75
+    import torch
+    _log("case batch largest pair n=7966 alpha=0.75")
+    rng = np.random.default_rng(54)
+    n = 7966
+    x = rng.uniform(0, 1, n)
+    y = np.sin(6 * x) + rng.normal(0, 0.3, n)
+    data = np.concatenate([x, y]).astype(np.float32)
+    got = micx.batch(torch.from_numpy(data).cuda(), [0], [n], [n], [0.75], [15.0]).cpu().numpy()
+    want = oracle.score(data[:n].astype(np.float64), data[n:].astype(np.float64), 0.75, 15)["stats"]
+    assert np.abs(got[0, :3] - want[:3]).max() <= TOL, (got, want)
+    assert abs(got[0, 3] - want[3]) < 1e-9
+
+
+def test_batch_errors_leave_output(micx):
+    import torch
+    _log("case batch errors")
+    data, offx, offy, ns, alphas, cs = _stream_case(55, 6, 50, 200)
+    dd = torch.from_numpy(data).cuda()
+    out = torch.full((6, 4), -7.0, dtype=torch.float64, device="cuda")
+    bad_n = ns.copy()
+    bad_n[3] = 6                       # floor(6^alpha) < 4 for alpha <= 0.75: no grid cell
+    with pytest.raises(micx.MicxError) as e:
+        micx.batch(dd, offx, offy, bad_n, alphas, cs, out=out)
+    assert e.value.code == micx.MICX_ESMALLN
+    bad_a = alphas.copy()
+    bad_a[2] = 1.5
+    with pytest.raises(micx.MicxError) as e:
+        micx.batch(dd, offx, offy, ns, bad_a, cs, out=out)
+    assert e.value.code == micx.MICX_EINVAL
+    nan_data = data.copy()
+    nan_data[offy[4] + 3] = np.nan
+    with pytest.raises(micx.MicxError) as e:
+        micx.batch(torch.from_numpy(nan_data).cuda(), offx, offy, ns, alphas, cs, out=out)
+    assert e.value.code == micx.MICX_ENONFINITE
+    assert (out == -7.0).all(), "outputs must stay untouched on error"
