@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="pairs timed on the CPU oracle (0 disables the baseline)")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--no-stream", action="store_true",
+                    help="skip the uneven pair-stream leg (micx_batch, 8,192 pairs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="end with one plain device copy of MIB MiB, the reference "
                          "for scaling hardware byte counters")
@@ -135,6 +137,48 @@ def parity_of(got, ref):
             "max_dMEV": float(d[:, 2].max()), "mcn_mismatch": int((d[:, 3] > 1e-9).sum())}
 
 
+def stream_leg(micx, with_oracle):
+    """The uneven stream (8,192 independent pairs, n log-uniform in [50, 8000],
+    alpha in {0.55, 0.6, 0.75}, c in {5, 15}) through micx_batch: one warm-up,
+    then one timed call per form; parity on a seeded sample of pairs with
+    n <= 2000 against the oracle."""
+    import torch
+    import workloads
+    data, offx, offy, ns, alphas, cs = workloads.cfg5_stream()
+    dd = torch.from_numpy(data).cuda()
+    out = torch.empty((len(ns), 4), dtype=torch.float64, device="cuda")
+    micx.batch(dd, offx, offy, ns, alphas, cs, mode=micx.MODE_DP32, out=out)
+    print("bench: stream warm-up done", file=sys.stderr, flush=True)
+    leg = {"pairs": int(len(ns)), "groups": int(len(set(zip(ns.tolist(), alphas.tolist(), cs.tolist())))),
+           "data": "synthetic"}
+    hosts = {}
+    for form, mode in (("dp32", micx.MODE_DP32), ("fp64", micx.MODE_FP64)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        micx.batch(dd, offx, offy, ns, alphas, cs, mode=mode, out=out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        hosts[form] = out.cpu().numpy()
+        leg[form] = {"value": round(len(ns) / dt, 2), "unit": "pairs/s", "ms": round(dt * 1e3, 1)}
+        print("bench: stream %s done" % form, file=sys.stderr, flush=True)
+    if with_oracle:
+        import oracle
+        rng = np.random.default_rng(777)
+        cand = np.flatnonzero(ns <= 2000)
+        sample = np.sort(rng.choice(cand, size=min(64, len(cand)), replace=False))
+        ref = []
+        for k in sample:
+            n = int(ns[k])
+            x = data[offx[k]:offx[k] + n].astype(np.float64)
+            y = data[offy[k]:offy[k] + n].astype(np.float64)
+            ref.append(oracle.score(x, y, float(alphas[k]), float(cs[k]))["stats"])
+        ref = np.array(ref)
+        for form in hosts:
+            leg[form]["parity"] = parity_of(hosts[form][sample], ref)
+        leg["parity_sample"] = "%d seeded pairs with n <= 2000" % len(sample)
+    return leg
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -215,6 +259,8 @@ def main():
         result["parity"] = parity_of(results[main_form][2][idx], ref)
         for form in results:
             forms[form]["parity"] = parity_of(results[form][2][idx], ref)
+    if not args.no_stream and args.m == 1000:
+        result["batch_stream"] = stream_leg(micx, args.cpu_sample > 0)
     if args.copy_calibration > 0:
         nb = args.copy_calibration << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")

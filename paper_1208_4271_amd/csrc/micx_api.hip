@@ -11,9 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
-#include <atomic>
 #include <map>
-#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -61,9 +59,8 @@ struct micx_ctx {
     double dp32_tol = 1e-7;
     int profiling = 0;
     micx_profile prof = {};
-    // micx_batch workers: sub-contexts (own buffers) with their own streams
-    std::vector<micx_ctx *> workers;
-    std::vector<hipStream_t> wstreams;
+    DevBuf arena, gitems;              // micx_batch: per-pass group buffers, DP item lists
+    std::vector<hipStream_t> dstreams; // micx_batch: DP launches of different shapes run side by side
 };
 
 #define HIPCHK(expr)                                   \
@@ -124,8 +121,9 @@ extern "C" void micx_ctx_destroy(micx_ctx *c) {
                      &c->counters, &c->fxtab, &c->lab,
                      &c->bdata, &c->boffs, &c->bout, &c->bidx};
     for (DevBuf *b : all) b->release();
-    for (micx_ctx *w : c->workers) micx_ctx_destroy(w);
-    for (hipStream_t st : c->wstreams) hipStreamDestroy(st);
+    c->arena.release();
+    c->gitems.release();
+    for (hipStream_t st : c->dstreams) hipStreamDestroy(st);
     delete c;
 }
 
@@ -435,44 +433,64 @@ extern "C" int micx_pairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, in
 
 namespace {
 
-// One group of a batch: pairs that share (n, alpha, c), run as a pair list
-// over their gathered variables; results go to rows [row0, row0 + P) of the
-// parent's staging buffer.
+// One group of a batch stream: pairs that share (n, alpha, c).
 struct BatchGroup {
     int n;
     double alpha, c, cost;
-    std::vector<int64_t> idx;
-    int64_t row0;
+    std::vector<int64_t> idx;   // the caller's pair indices
+    int64_t row0;               // first staged result row
 };
 
-int run_batch_group(micx_ctx *w, const void *data_dev, int dtype, const micx_pair_desc *pairs_host,
-                    const BatchGroup &bg, int mode, double *rows_dev, hipStream_t s) {
-    const int n = bg.n, esize = dtype == MICX_F64 ? 8 : 4;
-    const int64_t P = (int64_t)bg.idx.size();
-    std::vector<int64_t> offs(2 * P);
-    std::vector<int32_t> pl(2 * P);
-    for (int64_t i = 0; i < P; i++) {
-        offs[2 * i] = pairs_host[bg.idx[i]].off_x;
-        offs[2 * i + 1] = pairs_host[bg.idx[i]].off_y;
-        pl[2 * i] = (int32_t)(2 * i);
-        pl[2 * i + 1] = (int32_t)(2 * i + 1);
-    }
-    RETCHK(w->boffs.ensure(offs.size() * sizeof(int64_t)));
-    RETCHK(w->pairs.ensure(pl.size() * sizeof(int32_t)));
-    RETCHK(w->bdata.ensure((size_t)2 * P * n * esize));
-    HIPCHK(hipMemcpyAsync(w->boffs.p, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(w->pairs.p, pl.data(), pl.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    HIPCHK(launch_gather(data_dev, esize, w->boffs.as<int64_t>(), (int)(2 * P), n, w->bdata.p, s));
+// Device layout of one group inside the batch arena (byte offsets).
+struct GroupLayout {
     HostGeometry hg;
-    make_geometry(n, micx_grid_bound(n, bg.alpha), bg.c, hg);
-    RETCHK(upload_geometry(w, hg, s));
-    RankTables rt;
-    EquipTables et;
-    RETCHK(prepare_variables(w, w->bdata.p, dtype, (int)(2 * P), n, hg.g, false, rt, et, s));
-    RETCHK(run_pairs(w, rt, et, hg.g, w->pairs.as<int32_t>(), P, (int)(2 * P), mode, rows_dev, nullptr,
-                     nullptr, nullptr, s));
-    HIPCHK(hipStreamSynchronize(s));   // offs and pl live until here
-    return MICX_OK;
+    int NYP = 0;
+    size_t X, perm, gsize, grank, rowof, yhat, geo, pairs, offs;
+    size_t cbuf, sbuf, K, k, src, lab, A;
+    size_t lab_row = 0;
+    int lab16 = 0;
+};
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Assigns the arena offsets of a group: the parts the host fills (geometry,
+// pair list, gather offsets) from *hc, the device-only parts from *dc.
+void layout_group(const BatchGroup &bg, int esize, size_t &hc, size_t &dc, GroupLayout &L) {
+    make_geometry(bg.n, micx_grid_bound(bg.n, bg.alpha), bg.c, L.hg);
+    const Geometry &g = L.hg.g;
+    const size_t P = bg.idx.size(), nv = 2 * P, n = (size_t)bg.n, NY = (size_t)g.NY;
+    L.NYP = (g.NY + 7) / 8 * 8;
+    L.lab16 = lab_bytes(g) == 2;
+    L.lab_row = lab_row_bytes(g);
+    auto take = [](size_t &cur, size_t bytes) {
+        const size_t at = cur;
+        cur += align256(bytes);
+        return at;
+    };
+    L.geo = take(hc, 4 * NY * 4);
+    L.pairs = take(hc, nv * 4);
+    L.offs = take(hc, nv * 8);
+    L.X = take(dc, nv * n * esize);
+    L.perm = take(dc, nv * n * 4);
+    L.gsize = take(dc, nv * n * 4);
+    L.grank = take(dc, nv * n * 4);
+    L.rowof = take(dc, nv * n * L.NYP * 2);
+    L.yhat = take(dc, nv * NY * 4);
+    L.cbuf = take(dc, nv * g.KSUM * 4);
+    L.sbuf = take(dc, nv * g.KSUM * 4);
+    L.K = take(dc, nv * NY * 4);
+    L.k = take(dc, nv * NY * 4);
+    L.src = take(dc, nv * NY * 4);
+    L.lab = take(dc, nv * NY * L.lab_row);
+    L.A = take(dc, nv * g.ASUM * 8);
+}
+
+// Arena bytes of a group (both parts).
+size_t group_bytes(const BatchGroup &bg, int esize) {
+    GroupLayout L;
+    size_t hc = 0, dc = 0;
+    layout_group(bg, esize, hc, dc, L);
+    return hc + dc;
 }
 
 void add_profile(micx_profile &t, const micx_profile &p) {
@@ -487,7 +505,335 @@ void add_profile(micx_profile &t, const micx_profile &p) {
     t.dp32_bound = std::max(t.dp32_bound, p.dp32_bound);
 }
 
-constexpr int kBatchWorkers = 8;
+// DP launch key of a batch: kernel shape, plus the fixed-point scale bucket
+// (classes whose scales lie within a factor 2 share one table).
+struct DpKey {
+    int fx, NL, YR, T, sb;
+    bool operator<(const DpKey &o) const {
+        return std::tie(fx, NL, YR, T, sb) < std::tie(o.fx, o.NL, o.YR, o.T, o.sb);
+    }
+};
+struct DpBucket {
+    DpPlan plan;
+    int nmax = 0;
+    size_t rec = 0, slot = 0;
+    double scale = 0.0, bound = 0.0;
+    std::vector<std::pair<double, std::pair<int, int>>> classes;   // (cost, (group, yi))
+    std::vector<int> items;
+};
+
+constexpr size_t kArenaBytes = (size_t)16 << 30;  // per pass over the stream (of 288 GB)
+constexpr int kDpStreams = 4;
+
+// Runs groups[g0, g1) of a batch: per-group ranks, equipartitions and
+// partitions, then one DP launch per key over all their items (spread over
+// the context's DP streams), then per-group statistics into the staging rows.
+int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pair_desc *pairs_host,
+                   std::vector<BatchGroup> &groups, size_t g0, size_t g1, int mode, hipStream_t s,
+                   micx_profile &prof) {
+    const int esize = dtype == MICX_F64 ? 8 : 4;
+    const size_t ng = g1 - g0;
+    std::vector<GroupLayout> lay(ng);
+    size_t hc = 0, dc = 0;
+    int nmax = 0;
+    for (size_t i = 0; i < ng; i++) {
+        layout_group(groups[g0 + i], esize, hc, dc, lay[i]);
+        nmax = std::max(nmax, groups[g0 + i].n);
+    }
+    const size_t tab_off = hc;                                      // DpGroup table
+    const size_t host_bytes = align256(hc + ng * sizeof(DpGroup));
+    for (GroupLayout &L : lay)
+        for (size_t *o : {&L.X, &L.perm, &L.gsize, &L.grank, &L.rowof, &L.yhat, &L.cbuf, &L.sbuf,
+                          &L.K, &L.k, &L.src, &L.lab, &L.A})
+            *o += host_bytes;
+    const size_t bytes = host_bytes + dc;
+    RETCHK(ctx->arena.ensure(bytes));
+    unsigned char *ar = ctx->arena.as<unsigned char>();
+    // host-side inputs at the front of the arena: geometry, pair lists,
+    // gather offsets, group table
+    std::vector<unsigned char> blob(host_bytes, 0);
+    std::vector<DpGroup> tab(ng);
+    for (size_t i = 0; i < ng; i++) {
+        const BatchGroup &bg = groups[g0 + i];
+        GroupLayout &L = lay[i];
+        const int NY = L.hg.g.NY;
+        int *geo = (int *)(blob.data() + L.geo);
+        std::copy(L.hg.xcnt.begin(), L.hg.xcnt.end(), geo);
+        std::copy(L.hg.khat.begin(), L.hg.khat.end(), geo + NY);
+        std::copy(L.hg.koff.begin(), L.hg.koff.end(), geo + 2 * NY);
+        std::copy(L.hg.aoff.begin(), L.hg.aoff.end(), geo + 3 * NY);
+        int32_t *pl = (int32_t *)(blob.data() + L.pairs);
+        int64_t *of = (int64_t *)(blob.data() + L.offs);
+        for (size_t p = 0; p < bg.idx.size(); p++) {
+            pl[2 * p] = (int32_t)(2 * p);
+            pl[2 * p + 1] = (int32_t)(2 * p + 1);
+            of[2 * p] = pairs_host[bg.idx[p]].off_x;
+            of[2 * p + 1] = pairs_host[bg.idx[p]].off_y;
+        }
+        Geometry &g = L.hg.g;
+        g.xcnt = (int *)(ar + L.geo);
+        g.khat = g.xcnt + NY;
+        g.koff = g.xcnt + 2 * NY;
+        g.aoff = g.xcnt + 3 * NY;
+        DpGroup &t = tab[i];
+        t.n = bg.n;
+        t.NY = NY;
+        t.KSUM = g.KSUM;
+        t.ASUM = g.ASUM;
+        t.lab16 = L.lab16;
+        t.lab_row = L.lab_row;
+        t.xcnt = g.xcnt;
+        t.khat = g.khat;
+        t.koff = g.koff;
+        t.aoff = g.aoff;
+        t.yhat = (const int *)(ar + L.yhat);
+        t.cbuf = (const int *)(ar + L.cbuf);
+        t.sbuf = (const int *)(ar + L.sbuf);
+        t.K = (const int *)(ar + L.K);
+        t.src = (const int *)(ar + L.src);
+        t.lab = ar + L.lab;
+        t.A = (double *)(ar + L.A);
+    }
+    memcpy(blob.data() + tab_off, tab.data(), ng * sizeof(DpGroup));
+    HIPCHK(hipMemcpyAsync(ar, blob.data(), host_bytes, hipMemcpyHostToDevice, s));
+    RETCHK(ctx->xlogx.ensure((size_t)(nmax + 1) * sizeof(double)));
+    RETCHK(ctx->status.ensure(sizeof(int)));
+    int *status = ctx->status.as<int>();
+    HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
+    HIPCHK(launch_xlogx(nmax, ctx->xlogx.as<double>(), s));
+    unsigned long long *counters = nullptr;
+    if (ctx->profiling) {
+        RETCHK(ctx->counters.ensure(4 * sizeof(unsigned long long)));
+        counters = ctx->counters.as<unsigned long long>();
+        HIPCHK(hipMemsetAsync(counters, 0, 4 * sizeof(unsigned long long), s));
+    }
+    // per group, spread over the DP streams: gather, rank, equipartition,
+    // partition (each group's kernels are small; groups are independent)
+    while ((int)ctx->dstreams.size() < kDpStreams) {
+        hipStream_t st;
+        HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        ctx->dstreams.push_back(st);
+    }
+    auto fork = [&]() -> int {
+        hipEvent_t e;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(e, s));
+        for (hipStream_t st : ctx->dstreams) HIPCHK(hipStreamWaitEvent(st, e, 0));
+        HIPCHK(hipEventDestroy(e));
+        return MICX_OK;
+    };
+    auto join = [&]() -> int {
+        for (hipStream_t st : ctx->dstreams) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            HIPCHK(hipEventRecord(e, st));
+            HIPCHK(hipStreamWaitEvent(s, e, 0));
+            HIPCHK(hipEventDestroy(e));
+        }
+        return MICX_OK;
+    };
+    RETCHK(fork());
+    std::vector<RankTables> rts(ng);
+    std::vector<EquipTables> ets(ng);
+    std::vector<ItemBuffers> ibs(ng);
+    for (size_t i = 0; i < ng; i++) {
+        const BatchGroup &bg = groups[g0 + i];
+        GroupLayout &L = lay[i];
+        const int nv = (int)(2 * bg.idx.size()), n = bg.n;
+        hipStream_t gs = ctx->dstreams[i % kDpStreams];
+        HIPCHK(launch_gather(data_dev, esize, (const int64_t *)(ar + L.offs), nv, n, ar + L.X, gs));
+        RankTables &rt = rts[i];
+        rt.m = nv;
+        rt.n = n;
+        rt.perm = (int *)(ar + L.perm);
+        rt.gsize = (int *)(ar + L.gsize);
+        rt.grank = (int *)(ar + L.grank);
+        EquipTables &et = ets[i];
+        et.NY = L.hg.g.NY;
+        et.NYP = L.NYP;
+        et.rowof = (uint16_t *)(ar + L.rowof);
+        et.yhat = (int *)(ar + L.yhat);
+        et.rowstart = nullptr;
+        et.RS = et.NY + 2;
+        HIPCHK(launch_rank(ar + L.X, dtype, nv, n, rt, status, gs));
+        HIPCHK(launch_equip(rt, et, gs));
+        ItemBuffers &ib = ibs[i];
+        ib.cbuf = (int *)(ar + L.cbuf);
+        ib.sbuf = (int *)(ar + L.sbuf);
+        ib.K = (int *)(ar + L.K);
+        ib.k = (int *)(ar + L.k);
+        ib.src = (int *)(ar + L.src);
+        ib.lab = ar + L.lab;
+        ib.lab_row = L.lab_row;
+        ib.lab16 = L.lab16;
+        ib.A = (double *)(ar + L.A);
+        PairSource ps;
+        ps.pairs = (const int32_t *)(ar + L.pairs);
+        ps.p0 = 0;
+        ps.m = nv;
+        HIPCHK(launch_part(rt, et, L.hg.g, ps, (int)bg.idx.size(), ib, gs));
+        if (counters) HIPCHK(launch_work(et, L.hg.g, ps, (int)bg.idx.size(), ib, counters, gs));
+    }
+    RETCHK(join());
+    int hstatus = 0;
+    HIPCHK(hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hstatus & 1) return MICX_ENONFINITE;
+    if (hstatus) return MICX_EDEVICE;
+    // DP keys: every (group, row count) class goes to the launch of its shape
+    std::map<DpKey, DpBucket> buckets;
+    for (size_t i = 0; i < ng; i++) {
+        const BatchGroup &bg = groups[g0 + i];
+        const Geometry &g = lay[i].hg.g;
+        for (int yi = 0; yi < g.NY; yi++) {
+            DpPlan p = dp_shape(g, bg.n, yi, mode, ctx->dp32_tol);
+            // a shared table uses the smallest scale of its bucket, at most a
+            // factor 2 below the class's own: keep the bound within tolerance
+            if (p.fx && 2.0 * p.bound > ctx->dp32_tol) p.fx = false;
+            DpKey key{p.fx ? 1 : 0, p.NL, p.YR, p.T, p.fx ? (int)floor(log2(p.scale)) : 0};
+            DpBucket &b = buckets[key];
+            if (b.classes.empty()) b.plan = p;
+            b.nmax = std::max(b.nmax, bg.n);
+            b.rec = std::max(b.rec, (size_t)p.KS * p.RS * 4);
+            b.slot = std::max(b.slot, (size_t)p.x * p.KS * (p.fx ? 4 : 8));
+            if (p.fx) b.scale = b.scale == 0.0 ? p.scale : std::min(b.scale, p.scale);
+            b.classes.push_back({(double)p.x * p.KS * p.KS, {(int)i, yi}});
+        }
+    }
+    // keys run largest first (their longest items start at once), round-robin
+    // over the DP streams
+    std::vector<std::pair<const DpKey, DpBucket> *> keys;
+    for (auto &kv : buckets) keys.push_back(&kv);
+    size_t nitems = 0, tabs = 0;
+    for (auto *kp : keys) {
+        DpBucket &b = kp->second;
+        std::sort(b.classes.begin(), b.classes.end(),
+                  [](const std::pair<double, std::pair<int, int>> &u,
+                     const std::pair<double, std::pair<int, int>> &v) { return u.first > v.first; });
+        for (auto &c : b.classes) {
+            const int gi = c.second.first, yi = c.second.second;
+            const int npo = (int)(2 * groups[g0 + gi].idx.size());
+            for (int po = 0; po < npo; po++) {
+                b.items.push_back(gi);
+                b.items.push_back(yi);
+                b.items.push_back(po);
+            }
+        }
+        nitems += b.items.size() / 3;
+        DpPlan &p = b.plan;
+        p.scale = b.scale;
+        p.slot_bytes = b.slot;
+        dp_fit_lds(p, b.nmax, b.rec, ctx->cus);
+        if (p.fx) tabs++;
+    }
+    std::sort(keys.begin(), keys.end(), [](const std::pair<const DpKey, DpBucket> *u,
+                                           const std::pair<const DpKey, DpBucket> *v) {
+        return u->second.classes.front().first > v->second.classes.front().first;
+    });
+    // item lists and fixed-point tables, one region per key
+    RETCHK(ctx->gitems.ensure(nitems * 3 * sizeof(int)));
+    RETCHK(ctx->fxtab.ensure(std::max<size_t>(tabs, 1) * (size_t)(nmax + 1) * sizeof(uint32_t)));
+    std::vector<int> allitems;
+    allitems.reserve(nitems * 3);
+    for (auto *kp : keys) allitems.insert(allitems.end(), kp->second.items.begin(), kp->second.items.end());
+    HIPCHK(hipMemcpyAsync(ctx->gitems.p, allitems.data(), allitems.size() * sizeof(int),
+                          hipMemcpyHostToDevice, s));
+    // scratch per DP stream: the largest need among the keys it runs
+    std::vector<size_t> need(kDpStreams, 0);
+    {
+        int k = 0;
+        for (auto *kp : keys) {
+            const DpBucket &b = kp->second;
+            const size_t waves = std::min<size_t>(b.items.size() / 3, (size_t)b.plan.max_waves);
+            const size_t w = (waves + b.plan.WPB - 1) / b.plan.WPB * b.plan.WPB;
+            need[k % kDpStreams] = std::max(need[k % kDpStreams], w * b.plan.slot_bytes);
+            k++;
+        }
+    }
+    size_t scr = 0;
+    std::vector<size_t> scr_off(kDpStreams);
+    for (int k = 0; k < kDpStreams; k++) {
+        scr_off[k] = scr;
+        scr += align256(need[k]);
+    }
+    RETCHK(ctx->scratch.ensure(std::max<size_t>(scr, 1)));
+    RETCHK(fork());
+    std::vector<hipEvent_t> ev;
+    {
+        int k = 0, t = 0;
+        size_t off = 0;
+        for (auto *kp : keys) {
+            DpBucket &b = kp->second;
+            hipStream_t st = ctx->dstreams[k % kDpStreams];
+            const uint32_t *tab = nullptr;
+            if (b.plan.fx) {
+                uint32_t *tp = ctx->fxtab.as<uint32_t>() + (size_t)t * (nmax + 1);
+                HIPCHK(launch_fxtable(b.nmax, b.plan, ctx->xlogx.as<double>(), tp, st));
+                tab = tp;
+                t++;
+            }
+            if (ctx->profiling) {
+                hipEvent_t e0, e1;
+                HIPCHK(hipEventCreate(&e0));
+                HIPCHK(hipEventCreate(&e1));
+                ev.push_back(e0);
+                ev.push_back(e1);
+                HIPCHK(hipEventRecord(e0, st));
+            }
+            const int nit = (int)(b.items.size() / 3);
+            HIPCHK(launch_dp_items((const DpGroup *)(ar + tab_off), ctx->gitems.as<int>() + off, nit, b.nmax,
+                                   ctx->xlogx.as<double>(), tab,
+                                   ctx->scratch.as<unsigned char>() + scr_off[k % kDpStreams], b.plan, st));
+            if (ctx->profiling) HIPCHK(hipEventRecord(ev.back(), st));
+            off += b.items.size();
+            k++;
+        }
+    }
+    // statistics per group into the staging rows: once every DP key is done
+    RETCHK(join());
+    RETCHK(fork());
+    for (size_t i = 0; i < ng; i++) {
+        const BatchGroup &bg = groups[g0 + i];
+        HIPCHK(launch_stats(lay[i].hg.g, (int)bg.idx.size(), ibs[i], ctx->bout.as<double>() + 4 * bg.row0,
+                            nullptr, nullptr, nullptr, ctx->dstreams[i % kDpStreams]));
+    }
+    RETCHK(join());
+    HIPCHK(hipStreamSynchronize(s));
+    micx_profile pp{};
+    if (ctx->profiling) {
+        for (size_t k = 0; k + 1 < ev.size(); k += 2) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+            pp.dp_ms += ms;
+        }
+        unsigned long long h[4];
+        HIPCHK(hipMemcpy(h, counters, sizeof(h), hipMemcpyDeviceToHost));
+        pp.items = (int64_t)h[0];
+        pp.dp_cells = (int64_t)h[1];
+        pp.h_evals = (int64_t)h[2];
+        pp.h_terms = (int64_t)h[3];
+        pp.dp_launches = (int)(ev.size() / 2);
+    }
+    for (hipEvent_t e : ev) hipEventDestroy(e);
+    for (auto &kv : buckets) {
+        const DpBucket &b = kv.second;
+        for (auto &c : b.classes) {
+            if (b.plan.fx) {
+                // the class's bound at the bucket's shared scale
+                const GroupLayout &L = lay[c.second.first];
+                const int y = c.second.second + 2, x = L.hg.xcnt[c.second.second];
+                const double bnd = 0.5 * (double)(y + 1) * (double)x /
+                                   (b.plan.scale * (double)groups[g0 + c.second.first].n * log(2.0));
+                pp.dp32_classes++;
+                pp.dp32_bound = std::max(pp.dp32_bound, bnd);
+            } else {
+                pp.fp64_classes++;
+            }
+        }
+    }
+    add_profile(prof, pp);
+    return MICX_OK;
+}
 
 }  // namespace
 
@@ -503,24 +849,31 @@ extern "C" int micx_batch(micx_ctx *ctx, const void *data_dev, int dtype,
     }
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    HIPCHK(hipStreamSynchronize(s));   // the data is ready for the worker streams
-    // pairs that share (n, alpha, c) share the grid geometry and run as one list;
-    // groups are handed to the workers largest first (cost ~ P n B^3 c^2)
+    const int esize = dtype == MICX_F64 ? 8 : 4;
+    // pairs that share (n, alpha, c) share the grid geometry; a group whose
+    // buffers would fill a large part of the arena is split
     std::map<std::tuple<int, double, double>, std::vector<int64_t>> byKey;
     for (int64_t k = 0; k < npairs; k++)
         byKey[std::make_tuple(pairs_host[k].n, pairs_host[k].alpha, pairs_host[k].c)].push_back(k);
     std::vector<BatchGroup> groups;
-    groups.reserve(byKey.size());
     for (auto &kv : byKey) {
         BatchGroup g;
         g.n = std::get<0>(kv.first);
         g.alpha = std::get<1>(kv.first);
         g.c = std::get<2>(kv.first);
+        g.idx = {kv.second.front()};
+        const size_t per_pair = group_bytes(g, esize);   // upper bound per pair
+        const size_t maxp = std::max<size_t>(1, kArenaBytes / 4 / std::max<size_t>(per_pair, 1));
         const double B = (double)micx_grid_bound(g.n, g.alpha);
-        g.cost = (double)kv.second.size() * (double)g.n * B * B * B * g.c * g.c;
-        g.idx = std::move(kv.second);
-        groups.push_back(std::move(g));
+        for (size_t i0 = 0; i0 < kv.second.size(); i0 += maxp) {
+            BatchGroup part = g;
+            part.idx.assign(kv.second.begin() + i0,
+                            kv.second.begin() + std::min(kv.second.size(), i0 + maxp));
+            part.cost = (double)part.idx.size() * (double)g.n * B * B * B * g.c * g.c;
+            groups.push_back(std::move(part));
+        }
     }
+    // largest first, so the longest items start early in each pass
     std::sort(groups.begin(), groups.end(), [](const BatchGroup &a, const BatchGroup &b) { return a.cost > b.cost; });
     std::vector<int64_t> order;
     order.reserve(npairs);
@@ -530,49 +883,21 @@ extern "C" int micx_batch(micx_ctx *ctx, const void *data_dev, int dtype,
     }
     RETCHK(ctx->bout.ensure((size_t)npairs * 4 * sizeof(double)));
     RETCHK(ctx->bidx.ensure((size_t)npairs * sizeof(int64_t)));
-    const int nw = (int)std::min<size_t>(kBatchWorkers, groups.size());
-    while ((int)ctx->workers.size() < nw) {
-        micx_ctx *w = nullptr;
-        RETCHK(micx_ctx_create(&w, ctx->device));
-        hipStream_t ws;
-        if (hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) {
-            micx_ctx_destroy(w);
-            return MICX_EDEVICE;
-        }
-        ctx->workers.push_back(w);
-        ctx->wstreams.push_back(ws);
-    }
-    std::atomic<size_t> next{0};
-    std::atomic<int> err{MICX_OK};
-    double *rows = ctx->bout.as<double>();
-    auto work = [&](int wi) {
-        micx_ctx *w = ctx->workers[wi];
-        hipSetDevice(ctx->device);
-        w->dp32_tol = ctx->dp32_tol;
-        w->profiling = ctx->profiling;
-        micx_profile tot{};
-        for (size_t g; (g = next.fetch_add(1)) < groups.size();) {
-            if (err.load() != MICX_OK) break;
-            const int rc = run_batch_group(w, data_dev, dtype, pairs_host, groups[g], mode,
-                                           rows + 4 * groups[g].row0, ctx->wstreams[wi]);
-            if (rc != MICX_OK) {
-                int expect = MICX_OK;
-                err.compare_exchange_strong(expect, rc);
-                break;
-            }
-            add_profile(tot, w->prof);
-        }
-        w->prof = tot;
-    };
-    std::vector<std::thread> th;
-    for (int wi = 0; wi < nw; wi++) th.emplace_back(work, wi);
-    for (std::thread &t : th) t.join();
-    if (err.load() != MICX_OK) return err.load();
     micx_profile total{};
-    for (int wi = 0; wi < nw; wi++) add_profile(total, ctx->workers[wi]->prof);
+    for (size_t g0 = 0; g0 < groups.size();) {
+        size_t g1 = g0, bytes = 0;
+        while (g1 < groups.size()) {
+            const size_t b = group_bytes(groups[g1], esize);
+            if (g1 > g0 && bytes + b > kArenaBytes) break;
+            bytes += b;
+            g1++;
+        }
+        RETCHK(run_batch_pass(ctx, data_dev, dtype, pairs_host, groups, g0, g1, mode, s, total));
+        g0 = g1;
+    }
     HIPCHK(hipMemcpyAsync(ctx->bidx.p, order.data(), order.size() * sizeof(int64_t),
                           hipMemcpyHostToDevice, s));
-    HIPCHK(launch_scatter_rows(rows, ctx->bidx.as<int64_t>(), npairs, out_dev, s));
+    HIPCHK(launch_scatter_rows(ctx->bout.as<double>(), ctx->bidx.as<int64_t>(), npairs, out_dev, s));
     HIPCHK(hipStreamSynchronize(s));
     ctx->prof = total;
     return MICX_OK;

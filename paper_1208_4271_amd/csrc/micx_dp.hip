@@ -3,6 +3,10 @@
 // tables of the 32-bit form.
 #include <math.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "micx_dp_kernel.h"
 
 namespace micx {
@@ -66,7 +70,7 @@ __global__ void k_fxtable(int n, double scale, const double *xlogx, uint32_t *ta
 // a partition into at most l <= x columns by l(yhat+1)/2, so an entry M of
 // the class is off by at most (y+1) x / (2 S n ln 2).  Classes whose bound
 // exceeds the tolerance run in FP64.
-DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol) {
+DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol) {
     static const int NLS[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32, 36};
     static const int YRS[] = {2, 3, 4, 5, 6, 7, 8, 10, 12, 16, 20, 24, 32, 40};
     DpPlan p;
@@ -98,12 +102,54 @@ DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol) 
     p.RS = (p.YR > 0 ? p.YR : y) + 1;
     p.x = x;
     p.slot_bytes = (size_t)x * (size_t)p.KS * vb;      // layers 0..x-1 (0 unused)
-    const int lds_L = align16((size_t)(n + 1) * vb);
-    const int lds_rec = align16((size_t)(kh + 1) * p.RS * 4);
+    return p;
+}
+
+DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol) {
+    DpPlan p = dp_shape(g, n, yi, mode, tol);
+    dp_fit_lds(p, n, (size_t)p.KS * p.RS * 4, cus);
+    return p;
+}
+
+namespace {
+
+// Resident workgroups per CU for (kernel, workgroup size, LDS bytes), asked
+// of the runtime once and remembered.
+int cached_occupancy(dp_kernel_t k, int threads, int lds) {
+    static std::mutex mu;
+    static std::map<std::tuple<const void *, int, int>, int> memo;
+    const auto key = std::make_tuple((const void *)k, threads, lds);
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = memo.find(key);
+        if (it != memo.end()) return it->second;
+    }
+    int occ = 0;
+    if (hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k, threads, lds) != hipSuccess)
+        occ = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    memo[key] = occ;
+    return occ;
+}
+
+}  // namespace
+
+// LDS split of a DP launch: the L table (nmax+1 values), then per wavefront
+// a staging buffer (SB sources x NLP layers, at least nmax bytes for the
+// set-up flags) and the count records (rec_bytes).  SB and the wavefronts
+// per workgroup shrink until two workgroups fit a CU (one at the least).
+void dp_fit_lds(DpPlan &p, int nmax, size_t rec_bytes, int cus) {
+    const int vb = p.fx ? 4 : 8;
+    const int PK = 16 / vb;
+    const int NLP = (p.NL + PK - 1) / PK * PK;
+    const int lds_L = align16((size_t)(nmax + 1) * vb);
+    const int lds_rec = align16(rec_bytes);
     const int budget = 160 * 1024;
     p.WPB = 4;
     for (p.SB = 64;; p.SB >>= 1) {
-        const int lds_stage = align16(std::max((size_t)p.SB * NLP * vb, (size_t)n));
+        const int lds_stage = align16(std::max((size_t)p.SB * NLP * vb, (size_t)nmax));
         const int wave = align16((size_t)lds_stage + lds_rec);
         p.lds_L = lds_L;
         p.lds_stage = lds_stage;
@@ -119,15 +165,9 @@ DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol) 
     // registers and LDS), capped by the LDS budget
     p.blocks_per_cu = std::max(1, budget / std::max(p.lds, 1));
     dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T);
-    int occ = 0;
-    if (k && hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, budget) ==
-                 hipSuccess &&
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k, 64 * p.WPB, p.lds) ==
-                 hipSuccess &&
-        occ > 0)
-        p.blocks_per_cu = std::min(p.blocks_per_cu, occ);
+    const int occ = k ? cached_occupancy(k, 64 * p.WPB, p.lds) : 0;
+    if (occ > 0) p.blocks_per_cu = std::min(p.blocks_per_cu, occ);
     p.max_waves = cus * p.blocks_per_cu * p.WPB;
-    return p;
 }
 
 hipError_t launch_fxtable(int n, const DpPlan &p, const double *xlogx, uint32_t *tab,
@@ -151,6 +191,7 @@ hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry
     a.xlogx = xlogx; a.fxtab = fxtab; a.inv_scale = 1.0 / p.scale;
     a.scratch = scratch; a.slot_bytes = p.slot_bytes;
     a.lds_L = p.lds_L; a.lds_stage = p.lds_stage; a.lds_wave = p.lds_wave;
+    a.groups = nullptr; a.gitems = nullptr;
     dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T);
     if (!k) return hipErrorInvalidValue;
     // the attribute is the whole LDS budget, the same for every caller (plans
@@ -161,6 +202,30 @@ hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry
     if (e != hipSuccess) return e;
     const int waves_needed = a.nitems;
     const int waves = std::min(waves_needed, p.max_waves);
+    const int blocks = (waves + p.WPB - 1) / p.WPB;
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * p.WPB), p.lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dp_items(const DpGroup *groups, const int *gitems, int nitems, int nmax,
+                           const double *xlogx, const uint32_t *fxtab, void *scratch,
+                           const DpPlan &p, hipStream_t s) {
+    DpArgs a = {};
+    a.n = nmax;
+    a.nitems = nitems;
+    a.SB = p.SB;
+    a.groups = groups;
+    a.gitems = gitems;
+    a.xlogx = xlogx; a.fxtab = fxtab; a.inv_scale = p.fx ? 1.0 / p.scale : 0.0;
+    a.scratch = scratch; a.slot_bytes = p.slot_bytes;
+    a.lds_L = p.lds_L; a.lds_stage = p.lds_stage; a.lds_wave = p.lds_wave;
+    dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T);
+    if (!k) return hipErrorInvalidValue;
+    if (p.lds > 160 * 1024) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024);
+    if (e != hipSuccess) return e;
+    const int waves = std::min(nitems, p.max_waves);
     const int blocks = (waves + p.WPB - 1) / p.WPB;
     hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * p.WPB), p.lds, s, a);
     return hipGetLastError();

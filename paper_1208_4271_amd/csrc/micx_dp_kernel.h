@@ -57,6 +57,11 @@ struct DpArgs {
     double inv_scale;            // 1 / S (uint32 form)
     void *scratch;
     size_t slot_bytes;           // G table bytes per wavefront
+    // items from several groups of a batch stream (null for one dataset):
+    // 3 ints per item (group, y-2, pair*2+orientation); n is then the
+    // largest n of the launch
+    const DpGroup *groups;
+    const int *gitems;
     int lds_L, lds_stage, lds_wave;
 };
 
@@ -109,13 +114,13 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
     constexpr int NLP = (NL + PK - 1) / PK * PK;
     constexpr bool FX = std::is_same<V, uint32_t>::value;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int n = a.n, NY = a.NY, RS = a.RS, KS = a.KS, x = a.x, yi = a.yi, SB = a.SB;
+    const int nmax = a.n, SB = a.SB;
     const int sbs = __builtin_ctz(SB);
     // the wavefront index is uniform across the wave; saying so keeps the item
     // index, its sizes and pointers in scalar registers and its branches scalar
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     V *L = (V *)smem;
-    for (int j = threadIdx.x; j <= n; j += blockDim.x) {
+    for (int j = threadIdx.x; j <= nmax; j += blockDim.x) {
         if constexpr (FX) L[j] = a.fxtab[j];
         else L[j] = a.xlogx[j];
     }
@@ -127,24 +132,57 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
     const int gw = blockIdx.x * wpb + wv, nw = gridDim.x * wpb;
     V *G = (V *)((unsigned char *)a.scratch + (size_t)gw * a.slot_bytes);
 
-    for (int po = gw; po < a.nitems; po += nw) {
-        const int o = po & 1, pl = po >> 1;
-        int pi, pj;
-        pair_of(a.ps, pl, pi, pj);
-        const int U = o ? pj : pi, Vv = o ? pi : pj;
-        const size_t it = (size_t)po * NY + yi;
-        const int K = __builtin_amdgcn_readfirstlane(a.K[it]);
-        const int yh = __builtin_amdgcn_readfirstlane(a.yhat[(size_t)Vv * NY + yi]);
-        const int *ends = (a.src[it] ? a.sbuf : a.cbuf) + (size_t)po * a.KSUM + a.koff[yi];
+    for (int wi = gw; wi < a.nitems; wi += nw) {
+        // the item: its sample count n, columns x, G-table and count-record
+        // strides, superclump count K, rows yhat and buffers
+        int n, x, KS, RS, K, yh;
+        const int *ends;
+        const unsigned char *lb8;
+        bool l16;
+        double *Aout;
+        if (a.groups) {
+            const int *d = a.gitems + 3 * (size_t)wi;
+            const int gi = __builtin_amdgcn_readfirstlane(d[0]);
+            const int yi = __builtin_amdgcn_readfirstlane(d[1]);
+            const int po = __builtin_amdgcn_readfirstlane(d[2]);
+            const DpGroup &gr = a.groups[gi];
+            const int pl = po >> 1, Vv = (po & 1) ? 2 * pl : 2 * pl + 1;
+            const size_t it = (size_t)po * gr.NY + yi;
+            n = gr.n;
+            x = gr.xcnt[yi];
+            KS = gr.khat[yi] + 1;
+            RS = YR > 0 ? YR + 1 : yi + 3;
+            K = __builtin_amdgcn_readfirstlane(gr.K[it]);
+            yh = __builtin_amdgcn_readfirstlane(gr.yhat[(size_t)Vv * gr.NY + yi]);
+            ends = (gr.src[it] ? gr.sbuf : gr.cbuf) + (size_t)po * gr.KSUM + gr.koff[yi];
+            lb8 = gr.lab + it * gr.lab_row;
+            l16 = gr.lab16 != 0;
+            Aout = gr.A + (size_t)po * gr.ASUM + gr.aoff[yi];
+        } else {
+            const int po = wi, yi = a.yi, NY = a.NY;
+            const int o = po & 1, pl = po >> 1;
+            int pi, pj;
+            pair_of(a.ps, pl, pi, pj);
+            const int Vv = o ? pi : pj;
+            const size_t it = (size_t)po * NY + yi;
+            n = a.n;
+            x = a.x;
+            KS = a.KS;
+            RS = a.RS;
+            K = __builtin_amdgcn_readfirstlane(a.K[it]);
+            yh = __builtin_amdgcn_readfirstlane(a.yhat[(size_t)Vv * NY + yi]);
+            ends = (a.src[it] ? a.sbuf : a.cbuf) + (size_t)po * a.KSUM + a.koff[yi];
+            lb8 = a.lab + it * a.lab_row;
+            l16 = a.lab16 != 0;
+            Aout = a.A + (size_t)po * a.ASUM + a.aoff[yi];
+        }
 
         // ---- cumulative counts (item 10a); rows beyond yhat stay 0 ----
         // A flag per superclump start gives each point its superclump through
         // a ballot scan; the point's row label (stored in column order by the
         // partition kernel) selects the count, and LDS atomics count.
         unsigned char *F = (unsigned char *)stage;
-        const unsigned char *lb8 = a.lab + ((size_t)po * NY + yi) * a.lab_row;
         const uint16_t *lb16 = (const uint16_t *)lb8;
-        const bool l16 = a.lab16 != 0;
         for (int k = lane; k < (K + 1) * RS; k += 64) rec[k] = 0;
         for (int p = lane; p < n; p += 64) F[p] = 0;
         wave_sync();
@@ -375,7 +413,6 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
         double sq = 0.0;
         for (int r = 0; r < yh; r++) sq += a.xlogx[rec[K * RS + 1 + r]];
         const double Ln = a.xlogx[n];
-        double *Aout = a.A + (size_t)po * a.ASUM + a.aoff[yi];
         for (int l = 2 + lane; l <= x; l += 64) {
             const V Gl = (l == x) ? best : G[(size_t)l * KS + K];
             const double I = (Ln - sq - DV::real(Gl, a.inv_scale)) / (double)n;

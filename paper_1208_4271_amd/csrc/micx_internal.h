@@ -70,6 +70,19 @@ struct ItemBuffers {
     double *A = nullptr;   // normalised scores, ASUM per (pair, orientation)
 };
 
+// One group of a batch stream on the device (pairs sharing n, alpha and c):
+// its geometry and item buffers, for DP launches that mix groups.  The
+// group's variables are rows 2i and 2i+1 for its pair i.
+struct DpGroup {
+    int n = 0, NY = 0, KSUM = 0, ASUM = 0, lab16 = 0, pad = 0;
+    size_t lab_row = 0;
+    const int *xcnt = nullptr, *khat = nullptr, *koff = nullptr, *aoff = nullptr;
+    const int *yhat = nullptr;
+    const int *cbuf = nullptr, *sbuf = nullptr, *K = nullptr, *src = nullptr;
+    const unsigned char *lab = nullptr;
+    double *A = nullptr;
+};
+
 // Pair source for a batch: either an explicit list (pairs != null) or the
 // row-major upper triangle starting at global pair index p0.
 struct PairSource {
@@ -84,6 +97,15 @@ hipError_t launch_equip(const RankTables &rt, EquipTables &et, hipStream_t s);
 hipError_t launch_part(const RankTables &rt, const EquipTables &et, const Geometry &g,
                        PairSource ps, int npairs, ItemBuffers &ib, hipStream_t s);
 DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol);
+DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol);   // without the LDS split
+void dp_fit_lds(DpPlan &p, int nmax, size_t rec_bytes, int cus);
+// DP over items of several groups (see DpGroup): gitems holds 3 ints per item
+// (group, y-2, pair*2+orientation); the plan's shape, scale and LDS split
+// cover every item; scratch holds min(nitems, p.max_waves) G tables of
+// p.slot_bytes.
+hipError_t launch_dp_items(const DpGroup *groups, const int *gitems, int nitems, int nmax,
+                           const double *xlogx, const uint32_t *fxtab, void *scratch,
+                           const DpPlan &p, hipStream_t s);
 hipError_t launch_fxtable(int n, const DpPlan &p, const double *xlogx, uint32_t *tab,
                           hipStream_t s);
 hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry &g,

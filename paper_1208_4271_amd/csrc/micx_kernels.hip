@@ -118,12 +118,14 @@ __global__ __launch_bounds__(1024) void k_rank(const void *X, int dtype, int m, 
 
 __global__ __launch_bounds__(64) void k_equip(int m, int n, int NY, int NYP, const int *gsize,
                                               uint16_t *rowof, int *yhat, int *rowstart, int RS) {
+    extern __shared__ int gs[];   // the variable's tie-group sizes, copied once (coalesced)
     const int nyb = (NY + 63) / 64;
     const int v = blockIdx.x / nyb, yb = blockIdx.x % nyb;
     const int yi = yb * 64 + threadIdx.x;
     const bool act = yi < NY;
     const int y = yi + 2;
-    const int *gs = gsize + (size_t)v * n;
+    for (int p = threadIdx.x; p < n; p += 64) gs[p] = gsize[(size_t)v * n + p];
+    __syncthreads();
     uint16_t *ro = rowof + (size_t)v * n * NYP + yi;
     int *rs = rowstart ? rowstart + ((size_t)v * NY + yi) * RS : nullptr;
     int r = 0, a = 0, R = n, L = y;
@@ -423,7 +425,8 @@ hipError_t launch_rank(const void *X, int dtype, int m, int n, RankTables &rt, i
 
 hipError_t launch_equip(const RankTables &rt, EquipTables &et, hipStream_t s) {
     const int nyb = (et.NY + 63) / 64;
-    hipLaunchKernelGGL(k_equip, dim3(rt.m * nyb), dim3(64), 0, s, rt.m, rt.n, et.NY, et.NYP, rt.gsize,
+    hipLaunchKernelGGL(k_equip, dim3(rt.m * nyb), dim3(64), (size_t)rt.n * sizeof(int), s, rt.m, rt.n,
+                       et.NY, et.NYP, rt.gsize,
                        et.rowof, et.yhat, et.rowstart, et.RS);
     return hipGetLastError();
 }
