@@ -723,6 +723,7 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
         DpPlan &p = b.plan;
         p.scale = b.scale;
         p.slot_bytes = b.slot;
+        p.groups = true;
         dp_fit_lds(p, b.nmax, b.rec, ctx->cus);
         if (p.fx) tabs++;
     }

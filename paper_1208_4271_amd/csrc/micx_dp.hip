@@ -19,23 +19,28 @@ dp_kernel_t dp_pick_u32_0(int NL, int YR, int T);
 dp_kernel_t dp_pick_u32_1(int NL, int YR, int T);
 dp_kernel_t dp_pick_u32_2(int NL, int YR, int T);
 dp_kernel_t dp_pick_u32_3(int NL, int YR, int T);
+dp_kernel_t dp_pickg_f64_0(int NL, int YR, int T);
+dp_kernel_t dp_pickg_f64_1(int NL, int YR, int T);
+dp_kernel_t dp_pickg_f64_2(int NL, int YR, int T);
+dp_kernel_t dp_pickg_f64_3(int NL, int YR, int T);
+dp_kernel_t dp_pickg_u32_0(int NL, int YR, int T);
+dp_kernel_t dp_pickg_u32_1(int NL, int YR, int T);
+dp_kernel_t dp_pickg_u32_2(int NL, int YR, int T);
+dp_kernel_t dp_pickg_u32_3(int NL, int YR, int T);
 
 namespace {
 
-dp_kernel_t pick(bool fx, int NL, int YR, int T) {
-    dp_kernel_t k;
-    if (fx) {
-        k = dp_pick_u32_0(NL, YR, T);
-        if (!k) k = dp_pick_u32_1(NL, YR, T);
-        if (!k) k = dp_pick_u32_2(NL, YR, T);
-        if (!k) k = dp_pick_u32_3(NL, YR, T);
-    } else {
-        k = dp_pick_f64_0(NL, YR, T);
-        if (!k) k = dp_pick_f64_1(NL, YR, T);
-        if (!k) k = dp_pick_f64_2(NL, YR, T);
-        if (!k) k = dp_pick_f64_3(NL, YR, T);
-    }
-    return k;
+// gr: the instances that take per-item descriptors (batch streams)
+dp_kernel_t pick(bool fx, int NL, int YR, int T, bool gr = false) {
+    typedef dp_kernel_t (*pick_t)(int, int, int);
+    static const pick_t tab[2][2][4] = {
+        {{dp_pick_f64_0, dp_pick_f64_1, dp_pick_f64_2, dp_pick_f64_3},
+         {dp_pick_u32_0, dp_pick_u32_1, dp_pick_u32_2, dp_pick_u32_3}},
+        {{dp_pickg_f64_0, dp_pickg_f64_1, dp_pickg_f64_2, dp_pickg_f64_3},
+         {dp_pickg_u32_0, dp_pickg_u32_1, dp_pickg_u32_2, dp_pickg_u32_3}}};
+    for (pick_t f : tab[gr ? 1 : 0][fx ? 1 : 0])
+        if (dp_kernel_t k = f(NL, YR, T)) return k;
+    return nullptr;
 }
 
 bool have_shape(int NL, int YR) { return pick(false, NL, YR, 1) != nullptr; }
@@ -164,7 +169,7 @@ void dp_fit_lds(DpPlan &p, int nmax, size_t rec_bytes, int cus) {
     // resident workgroups per CU: the runtime's figure for this kernel (its
     // registers and LDS), capped by the LDS budget
     p.blocks_per_cu = std::max(1, budget / std::max(p.lds, 1));
-    dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T);
+    dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T, p.groups);
     const int occ = k ? cached_occupancy(k, 64 * p.WPB, p.lds) : 0;
     if (occ > 0) p.blocks_per_cu = std::min(p.blocks_per_cu, occ);
     p.max_waves = cus * p.blocks_per_cu * p.WPB;
@@ -219,7 +224,7 @@ hipError_t launch_dp_items(const DpGroup *groups, const int *gitems, int nitems,
     a.xlogx = xlogx; a.fxtab = fxtab; a.inv_scale = p.fx ? 1.0 / p.scale : 0.0;
     a.scratch = scratch; a.slot_bytes = p.slot_bytes;
     a.lds_L = p.lds_L; a.lds_stage = p.lds_stage; a.lds_wave = p.lds_wave;
-    dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T);
+    dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T, true);
     if (!k) return hipErrorInvalidValue;
     if (p.lds > 160 * 1024) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,

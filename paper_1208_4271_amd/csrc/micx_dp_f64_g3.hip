@@ -1,0 +1,23 @@
+// micx_dp_f64_g3.hip -- DP kernel instances taking batch-stream item descriptors (double values) for count-row classes YR=10, YR=12, YR=16, YR=20, YR=24, YR=32, YR=40, YR=0.
+#include "micx_dp_kernel.h"
+
+#define MICX_GR true
+#define MICX_V double
+#include "micx_dp_shapes.h"
+
+namespace micx {
+
+dp_kernel_t dp_pickg_f64_3(int NL, int YR, int T) {
+    MICX_NL_SMALL(MICX_CASE, 10)
+    MICX_NL_SMALL(MICX_CASE, 12)
+    MICX_NL_SMALL(MICX_CASE1, 16)
+    MICX_NL_TINY(MICX_CASE1, 20)
+    MICX_NL_TINY(MICX_CASE1, 24)
+    MICX_NL_TINY(MICX_CASE1, 32)
+    MICX_NL_TINY(MICX_CASE1, 40)
+    MICX_NL_LIST(MICX_CASE1, 0)
+    MICX_CASE1(0, 0)
+    return nullptr;
+}
+
+}  // namespace micx

@@ -1,6 +1,7 @@
 // micx_dp_f64_i0.hip -- DP kernel instances (double values) for count-row classes YR=2, YR=3.
 #include "micx_dp_kernel.h"
 
+#define MICX_GR false
 #define MICX_V double
 #include "micx_dp_shapes.h"
 

@@ -1,6 +1,7 @@
 // micx_dp_f64_i3.hip -- DP kernel instances (double values) for count-row classes YR=10, YR=12, YR=16, YR=20, YR=24, YR=32, YR=40, YR=0.
 #include "micx_dp_kernel.h"
 
+#define MICX_GR false
 #define MICX_V double
 #include "micx_dp_shapes.h"
 

@@ -57,9 +57,9 @@ struct DpArgs {
     double inv_scale;            // 1 / S (uint32 form)
     void *scratch;
     size_t slot_bytes;           // G table bytes per wavefront
-    // items from several groups of a batch stream (null for one dataset):
-    // 3 ints per item (group, y-2, pair*2+orientation); n is then the
-    // largest n of the launch
+    // items from several groups of a batch stream (the GR instances): 3 ints
+    // per item (group, y-2, pair*2+orientation); n is then the largest n of
+    // the launch
     const DpGroup *groups;
     const int *gitems;
     int lds_L, lds_stage, lds_wave;
@@ -107,7 +107,7 @@ struct alignas(16) Pack {
     V v[DpVal<V>::PK];
 };
 
-template <class V, int NL, int YR, int T>
+template <class V, int NL, int YR, int T, bool GR>
 __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
     using DV = DpVal<V>;
     constexpr int PK = DV::PK;
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
         const unsigned char *lb8;
         bool l16;
         double *Aout;
-        if (a.groups) {
+        if constexpr (GR) {
             const int *d = a.gitems + 3 * (size_t)wi;
             const int gi = __builtin_amdgcn_readfirstlane(d[0]);
             const int yi = __builtin_amdgcn_readfirstlane(d[1]);

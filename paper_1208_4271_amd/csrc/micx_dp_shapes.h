@@ -1,7 +1,9 @@
 // micx_dp_shapes.h -- the DP kernel shapes compiled into the library:
 // NL (full layers per pass) x YR (count rows held in registers; 0 = read from
 // LDS) x T (targets per lane), for the value type MICX_V of the including
-// file.  Each micx_dp_{f64,u32}_i*.hip instantiates a slice.
+// file.  Each micx_dp_{f64,u32}_i*.hip instantiates a slice; MICX_GR selects
+// the instances that take per-item descriptors of a batch stream
+// (micx_dp_{f64,u32}_g*.hip).
 #pragma once
 
 #define MICX_NL_LIST(X, YR) X(1, YR) X(2, YR) X(3, YR) X(4, YR) X(5, YR) X(6, YR) X(7, YR) X(8, YR) \
@@ -9,6 +11,7 @@
 #define MICX_NL_SMALL(X, YR) X(1, YR) X(2, YR) X(3, YR) X(4, YR) X(5, YR) X(6, YR) X(8, YR)
 #define MICX_NL_TINY(X, YR) X(1, YR) X(2, YR) X(3, YR) X(4, YR)
 #define MICX_CASE(NLv, YRv) \
-    if (NL == NLv && YR == YRv) return T == 1 ? k_dp<MICX_V, NLv, YRv, 1> : k_dp<MICX_V, NLv, YRv, 2>;
+    if (NL == NLv && YR == YRv) \
+        return T == 1 ? k_dp<MICX_V, NLv, YRv, 1, MICX_GR> : k_dp<MICX_V, NLv, YRv, 2, MICX_GR>;
 #define MICX_CASE1(NLv, YRv) \
-    if (NL == NLv && YR == YRv) return T == 1 ? k_dp<MICX_V, NLv, YRv, 1> : nullptr;
+    if (NL == NLv && YR == YRv) return T == 1 ? k_dp<MICX_V, NLv, YRv, 1, MICX_GR> : nullptr;

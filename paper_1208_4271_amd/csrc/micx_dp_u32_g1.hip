@@ -1,0 +1,16 @@
+// micx_dp_u32_g1.hip -- DP kernel instances taking batch-stream item descriptors (uint32_t values) for count-row classes YR=4, YR=5.
+#include "micx_dp_kernel.h"
+
+#define MICX_GR true
+#define MICX_V uint32_t
+#include "micx_dp_shapes.h"
+
+namespace micx {
+
+dp_kernel_t dp_pickg_u32_1(int NL, int YR, int T) {
+    MICX_NL_LIST(MICX_CASE, 4)
+    MICX_NL_LIST(MICX_CASE, 5)
+    return nullptr;
+}
+
+}  // namespace micx

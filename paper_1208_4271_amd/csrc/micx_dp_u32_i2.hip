@@ -1,6 +1,7 @@
 // micx_dp_u32_i2.hip -- DP kernel instances (uint32_t values) for count-row classes YR=6, YR=7, YR=8.
 #include "micx_dp_kernel.h"
 
+#define MICX_GR false
 #define MICX_V uint32_t
 #include "micx_dp_shapes.h"
 

@@ -1,6 +1,7 @@
 // micx_dp_u32_i3.hip -- DP kernel instances (uint32_t values) for count-row classes YR=10, YR=12, YR=16, YR=20, YR=24, YR=32, YR=40, YR=0.
 #include "micx_dp_kernel.h"
 
+#define MICX_GR false
 #define MICX_V uint32_t
 #include "micx_dp_shapes.h"
 

@@ -52,6 +52,7 @@ struct DpPlan {
     int lds = 0, lds_L = 0, lds_stage = 0, lds_wave = 0;
     int blocks_per_cu = 0, max_waves = 0;
     size_t slot_bytes = 0;        // G table bytes per wavefront
+    bool groups = false;          // launched over batch-stream item descriptors
 };
 
 // Per-batch item buffers.
