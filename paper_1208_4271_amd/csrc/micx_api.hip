@@ -540,8 +540,28 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
         layout_group(groups[g0 + i], esize, hc, dc, lay[i]);
         nmax = std::max(nmax, groups[g0 + i].n);
     }
+    // block maps of the fused per-group stages (group, block inside the group)
+    std::vector<int2> mvar, mequip, mpart, mstats;
+    for (size_t i = 0; i < ng; i++) {
+        const int P = (int)groups[g0 + i].idx.size(), nyb = (lay[i].hg.g.NY + 63) / 64;
+        for (int v = 0; v < 2 * P; v++) mvar.push_back(make_int2((int)i, v));
+        for (int b = 0; b < 2 * P * nyb; b++) mequip.push_back(make_int2((int)i, b));
+        for (int b = 0; b < 2 * P * nyb; b++) mpart.push_back(make_int2((int)i, b));
+        for (int p = 0; p < P; p += 64) mstats.push_back(make_int2((int)i, p));
+    }
     const size_t tab_off = hc;                                      // DpGroup table
-    const size_t host_bytes = align256(hc + ng * sizeof(DpGroup));
+    hc += align256(ng * sizeof(DpGroup));
+    const size_t gdev_off = hc;                                     // GroupDev table
+    hc += align256(ng * sizeof(GroupDev));
+    const size_t mvar_off = hc;
+    hc += align256(mvar.size() * sizeof(int2));
+    const size_t mequip_off = hc;
+    hc += align256(mequip.size() * sizeof(int2));
+    const size_t mpart_off = hc;
+    hc += align256(mpart.size() * sizeof(int2));
+    const size_t mstats_off = hc;
+    hc += align256(mstats.size() * sizeof(int2));
+    const size_t host_bytes = align256(hc);
     for (GroupLayout &L : lay)
         for (size_t *o : {&L.X, &L.perm, &L.gsize, &L.grank, &L.rowof, &L.yhat, &L.cbuf, &L.sbuf,
                           &L.K, &L.k, &L.src, &L.lab, &L.A})
@@ -553,6 +573,7 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
     // gather offsets, group table
     std::vector<unsigned char> blob(host_bytes, 0);
     std::vector<DpGroup> tab(ng);
+    std::vector<GroupDev> gdev(ng);
     for (size_t i = 0; i < ng; i++) {
         const BatchGroup &bg = groups[g0 + i];
         GroupLayout &L = lay[i];
@@ -593,8 +614,45 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
         t.src = (const int *)(ar + L.src);
         t.lab = ar + L.lab;
         t.A = (double *)(ar + L.A);
+        GroupDev &d = gdev[i];
+        d.n = bg.n;
+        d.NY = NY;
+        d.NYP = L.NYP;
+        d.KSUM = g.KSUM;
+        d.ASUM = g.ASUM;
+        d.B = g.B;
+        d.W = g.W;
+        d.nv = (int)(2 * bg.idx.size());
+        d.npairs = (int)bg.idx.size();
+        d.lab16 = L.lab16;
+        d.lab_row = L.lab_row;
+        d.offs = (const int64_t *)(ar + L.offs);
+        d.X = ar + L.X;
+        d.perm = (int *)(ar + L.perm);
+        d.gsize = (int *)(ar + L.gsize);
+        d.grank = (int *)(ar + L.grank);
+        d.rowof = (uint16_t *)(ar + L.rowof);
+        d.yhat = (int *)(ar + L.yhat);
+        d.xcnt = g.xcnt;
+        d.khat = g.khat;
+        d.koff = g.koff;
+        d.aoff = g.aoff;
+        d.cbuf = (int *)(ar + L.cbuf);
+        d.sbuf = (int *)(ar + L.sbuf);
+        d.K = (int *)(ar + L.K);
+        d.k = (int *)(ar + L.k);
+        d.src = (int *)(ar + L.src);
+        d.lab = ar + L.lab;
+        d.A = (double *)(ar + L.A);
+        d.pairs = (const int32_t *)(ar + L.pairs);
+        d.out = ctx->bout.as<double>() + 4 * bg.row0;
     }
     memcpy(blob.data() + tab_off, tab.data(), ng * sizeof(DpGroup));
+    memcpy(blob.data() + gdev_off, gdev.data(), ng * sizeof(GroupDev));
+    memcpy(blob.data() + mvar_off, mvar.data(), mvar.size() * sizeof(int2));
+    memcpy(blob.data() + mequip_off, mequip.data(), mequip.size() * sizeof(int2));
+    memcpy(blob.data() + mpart_off, mpart.data(), mpart.size() * sizeof(int2));
+    memcpy(blob.data() + mstats_off, mstats.data(), mstats.size() * sizeof(int2));
     HIPCHK(hipMemcpyAsync(ar, blob.data(), host_bytes, hipMemcpyHostToDevice, s));
     RETCHK(ctx->xlogx.ensure((size_t)(nmax + 1) * sizeof(double)));
     RETCHK(ctx->status.ensure(sizeof(int)));
@@ -607,8 +665,6 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
         counters = ctx->counters.as<unsigned long long>();
         HIPCHK(hipMemsetAsync(counters, 0, 4 * sizeof(unsigned long long), s));
     }
-    // per group, spread over the DP streams: gather, rank, equipartition,
-    // partition (each group's kernels are small; groups are independent)
     while ((int)ctx->dstreams.size() < kDpStreams) {
         hipStream_t st;
         HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -632,49 +688,27 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
         }
         return MICX_OK;
     };
-    RETCHK(fork());
-    std::vector<RankTables> rts(ng);
-    std::vector<EquipTables> ets(ng);
-    std::vector<ItemBuffers> ibs(ng);
-    for (size_t i = 0; i < ng; i++) {
-        const BatchGroup &bg = groups[g0 + i];
-        GroupLayout &L = lay[i];
-        const int nv = (int)(2 * bg.idx.size()), n = bg.n;
-        hipStream_t gs = ctx->dstreams[i % kDpStreams];
-        HIPCHK(launch_gather(data_dev, esize, (const int64_t *)(ar + L.offs), nv, n, ar + L.X, gs));
-        RankTables &rt = rts[i];
-        rt.m = nv;
-        rt.n = n;
-        rt.perm = (int *)(ar + L.perm);
-        rt.gsize = (int *)(ar + L.gsize);
-        rt.grank = (int *)(ar + L.grank);
-        EquipTables &et = ets[i];
-        et.NY = L.hg.g.NY;
-        et.NYP = L.NYP;
-        et.rowof = (uint16_t *)(ar + L.rowof);
-        et.yhat = (int *)(ar + L.yhat);
-        et.rowstart = nullptr;
-        et.RS = et.NY + 2;
-        HIPCHK(launch_rank(ar + L.X, dtype, nv, n, rt, status, gs));
-        HIPCHK(launch_equip(rt, et, gs));
-        ItemBuffers &ib = ibs[i];
-        ib.cbuf = (int *)(ar + L.cbuf);
-        ib.sbuf = (int *)(ar + L.sbuf);
-        ib.K = (int *)(ar + L.K);
-        ib.k = (int *)(ar + L.k);
-        ib.src = (int *)(ar + L.src);
-        ib.lab = ar + L.lab;
-        ib.lab_row = L.lab_row;
-        ib.lab16 = L.lab16;
-        ib.A = (double *)(ar + L.A);
-        PairSource ps;
-        ps.pairs = (const int32_t *)(ar + L.pairs);
-        ps.p0 = 0;
-        ps.m = nv;
-        HIPCHK(launch_part(rt, et, L.hg.g, ps, (int)bg.idx.size(), ib, gs));
-        if (counters) HIPCHK(launch_work(et, L.hg.g, ps, (int)bg.idx.size(), ib, counters, gs));
+    // per-group stages, each one launch over all groups of the pass
+    const GroupDev *gd = (const GroupDev *)(ar + gdev_off);
+    HIPCHK(launch_gather_g(data_dev, esize, gd, (const int2 *)(ar + mvar_off), (int)mvar.size(), s));
+    HIPCHK(launch_rank_g(gd, (const int2 *)(ar + mvar_off), (int)mvar.size(), nmax, dtype, status, s));
+    HIPCHK(launch_equip_g(gd, (const int2 *)(ar + mequip_off), (int)mequip.size(), nmax, s));
+    HIPCHK(launch_part_g(gd, (const int2 *)(ar + mpart_off), (int)mpart.size(), s));
+    if (counters) {
+        for (size_t i = 0; i < ng; i++) {
+            GroupLayout &L = lay[i];
+            ItemBuffers ib;
+            ib.K = (int *)(ar + L.K);
+            EquipTables et;
+            et.NY = L.hg.g.NY;
+            et.yhat = (int *)(ar + L.yhat);
+            PairSource ps;
+            ps.pairs = (const int32_t *)(ar + L.pairs);
+            ps.p0 = 0;
+            ps.m = (int)(2 * groups[g0 + i].idx.size());
+            HIPCHK(launch_work(et, L.hg.g, ps, (int)groups[g0 + i].idx.size(), ib, counters, s));
+        }
     }
-    RETCHK(join());
     int hstatus = 0;
     HIPCHK(hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -790,15 +824,9 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
             k++;
         }
     }
-    // statistics per group into the staging rows: once every DP key is done
+    // statistics into the staging rows, once every DP key is done
     RETCHK(join());
-    RETCHK(fork());
-    for (size_t i = 0; i < ng; i++) {
-        const BatchGroup &bg = groups[g0 + i];
-        HIPCHK(launch_stats(lay[i].hg.g, (int)bg.idx.size(), ibs[i], ctx->bout.as<double>() + 4 * bg.row0,
-                            nullptr, nullptr, nullptr, ctx->dstreams[i % kDpStreams]));
-    }
-    RETCHK(join());
+    HIPCHK(launch_stats_g(gd, (const int2 *)(ar + mstats_off), (int)mstats.size(), s));
     HIPCHK(hipStreamSynchronize(s));
     micx_profile pp{};
     if (ctx->profiling) {

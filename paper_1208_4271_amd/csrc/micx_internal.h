@@ -84,6 +84,34 @@ struct DpGroup {
     double *A = nullptr;
 };
 
+// One group of a batch pass for the per-group stages run as single launches
+// over all groups (gather, rank, equipartition, partition, statistics).
+struct GroupDev {
+    int n = 0, NY = 0, NYP = 0, KSUM = 0, ASUM = 0, B = 0, W = 0, nv = 0, npairs = 0, lab16 = 0;
+    size_t lab_row = 0;
+    const int64_t *offs = nullptr;   // element offset of each variable in the packed data
+    void *X = nullptr;               // gathered variables, nv x n
+    int *perm = nullptr, *gsize = nullptr, *grank = nullptr;
+    uint16_t *rowof = nullptr;
+    int *yhat = nullptr;
+    const int *xcnt = nullptr, *khat = nullptr, *koff = nullptr, *aoff = nullptr;
+    int *cbuf = nullptr, *sbuf = nullptr, *K = nullptr, *k = nullptr, *src = nullptr;
+    unsigned char *lab = nullptr;
+    double *A = nullptr;
+    const int32_t *pairs = nullptr;  // (2i, 2i+1) per pair
+    double *out = nullptr;           // 4 doubles per pair
+};
+
+// Fused per-group stages: map[b] = (group, index of the block inside the
+// group's own launch of that stage).
+hipError_t launch_gather_g(const void *data, int esize, const GroupDev *G, const int2 *map, int blocks,
+                           hipStream_t s);
+hipError_t launch_rank_g(const GroupDev *G, const int2 *map, int blocks, int nmax, int dtype,
+                         int *status, hipStream_t s);
+hipError_t launch_equip_g(const GroupDev *G, const int2 *map, int blocks, int nmax, hipStream_t s);
+hipError_t launch_part_g(const GroupDev *G, const int2 *map, int blocks, hipStream_t s);
+hipError_t launch_stats_g(const GroupDev *G, const int2 *map, int blocks, hipStream_t s);
+
 // Pair source for a batch: either an explicit list (pairs != null) or the
 // row-major upper triangle starting at global pair index p0.
 struct PairSource {

@@ -8,7 +8,7 @@
 //   k_part   per item (pair, orientation, y), one item per lane:
 //            GetClumpsPartition (Algorithm 1) and GetSuperclumpsPartition
 //            (Algorithm 2) streamed over the points in column order
-//   k_dp64   (micx_dp.hip) per item, one wavefront: cumulative count table
+//   k_dp     (micx_dp.hip) per item, one wavefront: cumulative count table
 //            (App. A item 10a), column costs (item 10b) and the OptimizeXAxis
 //            dynamic program over the superclump boundaries
 //   k_stats  per pair: characteristic matrix from both orientations and
@@ -47,13 +47,12 @@ __global__ void k_xlogx(int n, double *L) {
 // One workgroup per variable.  Bitonic sort of (key, sample index) pairs in
 // LDS (N2 = next power of two >= n), then tie-group starts by a max-scan.
 
-__global__ __launch_bounds__(1024) void k_rank(const void *X, int dtype, int m, int n, int N2,
-                                               int *perm, int *gsize, int *grank, int *status) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void rank_body(const void *X, int dtype, int v, int n, int N2, int *perm,
+                                          int *gsize, int *grank, int *status, unsigned char *smem) {
     uint64_t *key = (uint64_t *)smem;
     int *idx = (int *)(key + N2);
     int *gst = idx + N2;
-    const int v = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
     const size_t base = (size_t)v * n;
     for (int i = tid; i < N2; i += nt) {
         if (i < n) {
@@ -108,6 +107,12 @@ __global__ __launch_bounds__(1024) void k_rank(const void *X, int dtype, int m, 
     }
 }
 
+__global__ __launch_bounds__(1024) void k_rank(const void *X, int dtype, int m, int n, int N2,
+                                               int *perm, int *gsize, int *grank, int *status) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    rank_body(X, dtype, blockIdx.x, n, N2, perm, gsize, grank, status, smem);
+}
+
 // ------------------------------------------------------------------ k_equip
 // EquipartitionYAxis (App. A items 3-4), one (variable, y) per lane.  The
 // greedy walks the tie groups in order; with a the current row's size, s the
@@ -116,11 +121,9 @@ __global__ __launch_bounds__(1024) void k_rank(const void *X, int dtype, int m, 
 // |a + s - R/L| >= |a - R/L| (row not empty) is equivalent to the integer
 // test (2a + s) * L >= 2R, used here so that the partition is bit-exact.
 
-__global__ __launch_bounds__(64) void k_equip(int m, int n, int NY, int NYP, const int *gsize,
-                                              uint16_t *rowof, int *yhat, int *rowstart, int RS) {
-    extern __shared__ int gs[];   // the variable's tie-group sizes, copied once (coalesced)
-    const int nyb = (NY + 63) / 64;
-    const int v = blockIdx.x / nyb, yb = blockIdx.x % nyb;
+__device__ __forceinline__ void equip_body(int v, int yb, int n, int NY, int NYP, const int *gsize,
+                                           uint16_t *rowof, int *yhat, int *rowstart, int RS, int *gs) {
+    // gs: the variable's tie-group sizes in LDS, copied once (coalesced)
     const int yi = yb * 64 + threadIdx.x;
     const bool act = yi < NY;
     const int y = yi + 2;
@@ -147,6 +150,13 @@ __global__ __launch_bounds__(64) void k_equip(int m, int n, int NY, int NYP, con
         yhat[(size_t)v * NY + yi] = r + 1;
         if (rs) rs[r + 1] = n;
     }
+}
+
+__global__ __launch_bounds__(64) void k_equip(int m, int n, int NY, int NYP, const int *gsize,
+                                              uint16_t *rowof, int *yhat, int *rowstart, int RS) {
+    extern __shared__ int gsl[];
+    const int nyb = (NY + 63) / 64;
+    equip_body(blockIdx.x / nyb, blockIdx.x % nyb, n, NY, NYP, gsize, rowof, yhat, rowstart, RS, gsl);
 }
 
 // ------------------------------------------------------------------- k_part
@@ -182,10 +192,8 @@ struct PartArgs {
 constexpr int PART_TILE = 144;
 
 template <bool L16>
-__global__ __launch_bounds__(64) void k_part(PartArgs a) {
-    __shared__ __align__(16) unsigned char tile[64 * PART_TILE];
+__device__ __forceinline__ void part_body(const PartArgs &a, int w, unsigned char *tile) {
     const int nyb = (a.NY + 63) / 64;
-    const int w = blockIdx.x;
     const int yb = w % nyb, po = w / nyb;
     const int o = po & 1, pl = po >> 1;
     int pi, pj;
@@ -303,6 +311,12 @@ __global__ __launch_bounds__(64) void k_part(PartArgs a) {
     }
 }
 
+template <bool L16>
+__global__ __launch_bounds__(64) void k_part(PartArgs a) {
+    __shared__ __align__(16) unsigned char tile[64 * PART_TILE];
+    part_body<L16>(a, blockIdx.x, tile);
+}
+
 // ------------------------------------------------------------------ k_stats
 // Characteristic matrix and statistics of one pair per thread.
 // M_{x,y} (x bins of the first variable, y of the second) is the larger of
@@ -317,9 +331,7 @@ struct StatsArgs {
     double *out, *M, *Axy, *Ayx;
 };
 
-__global__ void k_stats(StatsArgs a) {
-    const int pl = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pl >= a.npairs) return;
+__device__ __forceinline__ void stats_body(const StatsArgs &a, int pl) {
     const double *A0 = a.A + (size_t)(2 * pl) * a.ASUM;
     const double *A1 = a.A + (size_t)(2 * pl + 1) * a.ASUM;
     const int Bh = a.B / 2;
@@ -350,6 +362,11 @@ __global__ void k_stats(StatsArgs a) {
                 a.Ayx[q] = ok ? A1[a.aoff[r - 2] + cc - 2] : NAN;
             }
     }
+}
+
+__global__ void k_stats(StatsArgs a) {
+    const int pl = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pl < a.npairs) stats_body(a, pl);
 }
 
 // ------------------------------------------------------------------- k_work
@@ -495,6 +512,101 @@ hipError_t launch_scatter_rows(const double *src, const int64_t *idx, int64_t ro
     const int64_t th = 4 * rows;
     hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)((th + 255) / 256)), dim3(256), 0, s, src, idx,
                        rows, dst);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------ fused per-group stages
+// A batch pass runs each per-group stage as one launch over all its groups:
+// block b serves group map[b].x with the block index map[b].y that the
+// group's own launch would give it.
+
+__global__ void k_gather_g(const unsigned char *data, int esize, const GroupDev *G, const int2 *map) {
+    const int2 m = map[blockIdx.x];
+    const GroupDev &g = G[m.x];
+    const unsigned char *src = data + (size_t)g.offs[m.y] * esize;
+    unsigned char *dst = (unsigned char *)g.X + (size_t)m.y * g.n * esize;
+    if (esize == 8) {
+        for (int i = threadIdx.x; i < g.n; i += blockDim.x) ((uint64_t *)dst)[i] = ((const uint64_t *)src)[i];
+    } else {
+        for (int i = threadIdx.x; i < g.n; i += blockDim.x) ((uint32_t *)dst)[i] = ((const uint32_t *)src)[i];
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_rank_g(const GroupDev *G, const int2 *map, int dtype, int *status) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 m = map[blockIdx.x];
+    const GroupDev &g = G[m.x];
+    int N2 = 1;
+    while (N2 < g.n) N2 <<= 1;
+    rank_body(g.X, dtype, m.y, g.n, N2, g.perm, g.gsize, g.grank, status, smem);
+}
+
+__global__ __launch_bounds__(64) void k_equip_g(const GroupDev *G, const int2 *map) {
+    extern __shared__ int gsl[];
+    const int2 m = map[blockIdx.x];
+    const GroupDev &g = G[m.x];
+    const int nyb = (g.NY + 63) / 64;
+    equip_body(m.y / nyb, m.y % nyb, g.n, g.NY, g.NYP, g.gsize, g.rowof, g.yhat, nullptr, g.NY + 2, gsl);
+}
+
+__global__ __launch_bounds__(64) void k_part_g(const GroupDev *G, const int2 *map) {
+    __shared__ __align__(16) unsigned char tile[64 * PART_TILE];
+    const int2 m = map[blockIdx.x];
+    const GroupDev &g = G[m.x];
+    PartArgs a;
+    a.n = g.n; a.NY = g.NY; a.NYP = g.NYP; a.KSUM = g.KSUM;
+    a.ps.pairs = g.pairs; a.ps.p0 = 0; a.ps.m = g.nv;
+    a.perm = g.perm; a.gsize = g.gsize; a.grank = g.grank; a.rowof = g.rowof;
+    a.khat = g.khat; a.koff = g.koff;
+    a.cbuf = g.cbuf; a.sbuf = g.sbuf; a.K = g.K; a.k = g.k; a.src = g.src;
+    a.lab = g.lab; a.lab_row = g.lab_row;
+    if (g.lab16) part_body<true>(a, m.y, tile);
+    else part_body<false>(a, m.y, tile);
+}
+
+// 64 pairs per block: map[b].y is the group's first pair of the block
+__global__ void k_stats_g(const GroupDev *G, const int2 *map) {
+    const int2 m = map[blockIdx.x];
+    const GroupDev &g = G[m.x];
+    const int pl = m.y + threadIdx.x;
+    if (pl >= g.npairs) return;
+    StatsArgs a;
+    a.npairs = g.npairs; a.B = g.B; a.NY = g.NY; a.W = g.W; a.ASUM = g.ASUM;
+    a.aoff = g.aoff; a.A = g.A; a.out = g.out; a.M = nullptr; a.Axy = nullptr; a.Ayx = nullptr;
+    stats_body(a, pl);
+}
+
+hipError_t launch_gather_g(const void *data, int esize, const GroupDev *G, const int2 *map, int blocks,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_g, dim3(blocks), dim3(256), 0, s, (const unsigned char *)data, esize, G, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank_g(const GroupDev *G, const int2 *map, int blocks, int nmax, int dtype,
+                         int *status, hipStream_t s) {
+    int N2 = 1;
+    while (N2 < nmax) N2 <<= 1;
+    const size_t lds = (size_t)N2 * (8 + 4 + 4);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute((const void *)k_rank_g,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rank_g, dim3(blocks), dim3(1024), lds, s, G, map, dtype, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_equip_g(const GroupDev *G, const int2 *map, int blocks, int nmax, hipStream_t s) {
+    hipLaunchKernelGGL(k_equip_g, dim3(blocks), dim3(64), (size_t)nmax * sizeof(int), s, G, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_part_g(const GroupDev *G, const int2 *map, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_part_g, dim3(blocks), dim3(64), 0, s, G, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats_g(const GroupDev *G, const int2 *map, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_stats_g, dim3(blocks), dim3(64), 0, s, G, map);
     return hipGetLastError();
 }
 
