@@ -60,3 +60,26 @@ def test_workloads_shapes():
     assert X.shape == (64, 400) and X.dtype == np.float32
     x, y = workloads.cfg1_single_pair()
     assert len(x) == 200 and x.dtype == np.float64
+
+
+def test_build_reads_dp_resource_usage():
+    # The build rejects DP kernels that spill; it reads the compiler's
+    # kernel-resource-usage remarks.  The parser must key each DP instance by
+    # (fixed-point, NL, YR, T) and pick up its scratch and spill figures.
+    from paper_1208_4271_amd import _build
+    text = "\n".join([
+        "x.h:1:1: remark: Function Name: _ZN4micx4k_dpIjLi36ELi2ELi2ELb0EEEvNS_6DpArgsE [-Rpass-analysis]",
+        "x.h:1:1: remark:     VGPRs: 180 [-Rpass-analysis]",
+        "x.h:1:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis]",
+        "x.h:1:1: remark:     VGPRs Spill: 0 [-Rpass-analysis]",
+        "x.h:1:1: remark: Function Name: _ZN4micx4k_dpIdLi10ELi5ELi1ELb1EEEvNS_6DpArgsE [-Rpass-analysis]",
+        "x.h:1:1: remark:     VGPRs: 128 [-Rpass-analysis]",
+        "x.h:1:1: remark:     ScratchSize [bytes/lane]: 152 [-Rpass-analysis]",
+        "x.h:1:1: remark:     VGPRs Spill: 37 [-Rpass-analysis]",
+        "x.h:1:1: remark: Function Name: _ZN4micx6k_partILb0EEEvNS_8PartArgsE [-Rpass-analysis]",
+        "x.h:1:1: remark:     ScratchSize [bytes/lane]: 64 [-Rpass-analysis]",
+    ])
+    u = _build.dp_resource_usage(text)
+    assert set(u) == {(1, 36, 2, 2), (0, 10, 5, 1)}
+    assert u[(1, 36, 2, 2)]["ScratchSize"] == 0 and u[(1, 36, 2, 2)]["VGPRs"] == 180
+    assert u[(0, 10, 5, 1)]["ScratchSize"] == 152 and u[(0, 10, 5, 1)]["VGPRs Spill"] == 37
