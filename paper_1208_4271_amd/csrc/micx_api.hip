@@ -723,7 +723,10 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
             DpPlan p = dp_shape(g, bg.n, yi, mode, ctx->dp32_tol);
             // a shared table uses the smallest scale of its bucket, at most a
             // factor 2 below the class's own: keep the bound within tolerance
-            if (p.fx && 2.0 * p.bound > ctx->dp32_tol) p.fx = false;
+            if (p.fx && 2.0 * p.bound > ctx->dp32_tol) {
+                p.fx = false;
+                if (p.T == 3) p.T = 2;   // three targets per lane exist in 32 bits only
+            }
             DpKey key{p.fx ? 1 : 0, p.NL, p.YR, p.T, p.fx ? (int)floor(log2(p.scale)) : 0};
             DpBucket &b = buckets[key];
             if (b.classes.empty()) b.plan = p;

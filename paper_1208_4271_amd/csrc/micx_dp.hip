@@ -93,8 +93,10 @@ DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol) {
     p.NL = round_up_in(std::min(nf, nlcap), NLS, 17, 36);
     p.YR = round_up_in(y, YRS, 14, 0);
     if (!have_shape(p.NL, p.YR)) p.YR = 0;
-    // two targets per lane pay off where a pass holds many layers (measured)
+    // more targets per lane pay off where a pass holds many layers (measured):
+    // three in the 32-bit form with few rows, else two; one for smaller passes
     p.T = (p.NL >= 20 && p.YR > 0 && p.YR <= 12) ? 2 : 1;
+    if (p.fx && p.NL >= 20 && p.YR > 0 && p.YR <= 5) p.T = 3;
     const int tforce = env_int("MICX_DP_T", 0);
     if (tforce == 1 || (tforce == 2 && p.NL >= 5 && p.YR > 0 && p.YR <= 12)) p.T = tforce;
     if (x == 2) {                                      // no full layer: the lean shape

@@ -13,5 +13,9 @@
 #define MICX_CASE(NLv, YRv) \
     if (NL == NLv && YR == YRv) \
         return T == 1 ? k_dp<MICX_V, NLv, YRv, 1, MICX_GR> : k_dp<MICX_V, NLv, YRv, 2, MICX_GR>;
+// three targets per lane: passes of >= 20 layers with few rows (32-bit form)
+#define MICX_CASE3(NLv, YRv) \
+    if (NL == NLv && YR == YRv && T == 3) return k_dp<MICX_V, NLv, YRv, 3, MICX_GR>;
+#define MICX_NL_BIG(X, YR) X(20, YR) X(24, YR) X(28, YR) X(32, YR) X(36, YR)
 #define MICX_CASE1(NLv, YRv) \
     if (NL == NLv && YR == YRv) return T == 1 ? k_dp<MICX_V, NLv, YRv, 1, MICX_GR> : nullptr;

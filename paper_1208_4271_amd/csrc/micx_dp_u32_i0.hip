@@ -8,6 +8,8 @@
 namespace micx {
 
 dp_kernel_t dp_pick_u32_0(int NL, int YR, int T) {
+    MICX_NL_BIG(MICX_CASE3, 2)
+    MICX_NL_BIG(MICX_CASE3, 3)
     MICX_NL_LIST(MICX_CASE, 2)
     MICX_NL_LIST(MICX_CASE, 3)
     return nullptr;

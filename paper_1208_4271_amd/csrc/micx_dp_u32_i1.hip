@@ -8,6 +8,8 @@
 namespace micx {
 
 dp_kernel_t dp_pick_u32_1(int NL, int YR, int T) {
+    MICX_NL_BIG(MICX_CASE3, 4)
+    MICX_NL_BIG(MICX_CASE3, 5)
     MICX_NL_LIST(MICX_CASE, 4)
     MICX_NL_LIST(MICX_CASE, 5)
     return nullptr;
