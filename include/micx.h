@@ -64,7 +64,7 @@ extern "C" {
  * integer arithmetic, and every matrix entry is then within a bound that the
  * library computes per row count y, (y+1) x / (2 S n ln 2) with
  * S ~ 2^32 / (n ln y).  Row counts whose bound exceeds the tolerance (see
- * micx_set_dp32_tolerance, default 1e-7) run in FP64.  Scores, the
+ * micx_set_dp32_tolerance, default 5e-7) run in FP64.  Scores, the
  * H(Q) term and all statistics are computed in FP64 in both forms. */
 #define MICX_MODE_FP64  0   /* DP in FP64 */
 #define MICX_MODE_DP32  1   /* DP in 32-bit fixed point with a per-class error bound, FP64 elsewhere */
@@ -199,7 +199,8 @@ typedef struct {
 int micx_set_profiling(micx_ctx *ctx, int enable);
 int micx_get_profile(micx_ctx *ctx, micx_profile *out);
 
-/* Tolerance on |dM| for MICX_MODE_DP32 (default 1e-7): a row count whose
+/* Tolerance on |dM| for MICX_MODE_DP32 (default 5e-7, half of the 1e-6
+ * agreement required of the scores): a row count whose
  * fixed-point bound exceeds it runs in FP64.  Returns MICX_EINVAL unless
  * tol > 0. */
 int micx_set_dp32_tolerance(micx_ctx *ctx, double tol);

@@ -56,7 +56,7 @@ struct micx_ctx {
     DevBuf cbuf, sbuf, Kb, kb, srcb, A, scratch, pairs, input, out, dense;
     DevBuf counters, fxtab, lab;
     DevBuf bdata, boffs, bout, bidx;   // micx_batch: gathered variables, offsets, staged results
-    double dp32_tol = 1e-7;
+    double dp32_tol = 5e-7;   // half of the 1e-6 agreement required of the scores
     int profiling = 0;
     micx_profile prof = {};
     DevBuf arena, gitems;              // micx_batch: per-pass group buffers, DP item lists
