@@ -48,7 +48,7 @@ extern "C" {
 #define MICX_ENONFINITE  -3   /* NaN or infinity in the input */
 #define MICX_ENOMEM      -4   /* device or host allocation failed */
 #define MICX_EDEVICE     -5   /* HIP runtime error or device status word set */
-#define MICX_ETOOBIG     -6   /* n > MICX_MAX_N */
+#define MICX_ETOOBIG     -6   /* n > MICX_MAX_N, or a DP item larger than one CU's LDS (large n with large alpha) */
 
 /* Largest sample size: ranking sorts one variable inside one workgroup's LDS. */
 #define MICX_MAX_N 8192

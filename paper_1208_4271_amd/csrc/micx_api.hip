@@ -81,7 +81,7 @@ extern "C" const char *micx_strerror(int code) {
         case MICX_ENONFINITE: return "input holds NaN or infinity";
         case MICX_ENOMEM: return "out of memory";
         case MICX_EDEVICE: return "HIP runtime error or device status word set";
-        case MICX_ETOOBIG: return "sample size above MICX_MAX_N";
+        case MICX_ETOOBIG: return "problem too large: n above MICX_MAX_N, or a DP item above one compute unit's LDS";
         default: return "unknown error";
     }
 }
@@ -393,6 +393,7 @@ extern "C" int micx_allpairs(micx_ctx *ctx, const void *X_dev, int dtype, int m,
     hipStream_t s = (hipStream_t)stream;
     HostGeometry hg;
     make_geometry(n, micx_grid_bound(n, alpha), c, hg);
+    if (!dp_fits(hg.g, n)) return MICX_ETOOBIG;
     RETCHK(upload_geometry(ctx, hg, s));
     RankTables rt;
     EquipTables et;
@@ -418,6 +419,7 @@ extern "C" int micx_pairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, in
     hipStream_t s = (hipStream_t)stream;
     HostGeometry hg;
     make_geometry(n, micx_grid_bound(n, alpha), c, hg);
+    if (!dp_fits(hg.g, n)) return MICX_ETOOBIG;
     RETCHK(upload_geometry(ctx, hg, s));
     RETCHK(ctx->pairs.ensure((size_t)npairs * 2 * sizeof(int32_t)));
     HIPCHK(hipMemcpyAsync(ctx->pairs.p, pairs_host, (size_t)npairs * 2 * sizeof(int32_t),
@@ -507,10 +509,12 @@ void add_profile(micx_profile &t, const micx_profile &p) {
 
 // DP launch key of a batch: kernel shape, plus the fixed-point scale bucket
 // (classes whose scales lie within a factor 2 share one table).
+inline size_t align16b(size_t b) { return (b + 15) & ~(size_t)15; }
+
 struct DpKey {
-    int fx, NL, YR, T, sb;
+    int fx, NL, YR, T, sb, grp;   // grp: part of a key split to fit the LDS
     bool operator<(const DpKey &o) const {
-        return std::tie(fx, NL, YR, T, sb) < std::tie(o.fx, o.NL, o.YR, o.T, o.sb);
+        return std::tie(fx, NL, YR, T, sb, grp) < std::tie(o.fx, o.NL, o.YR, o.T, o.sb, o.grp);
     }
 };
 struct DpBucket {
@@ -715,7 +719,13 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
     if (hstatus & 1) return MICX_ENONFINITE;
     if (hstatus) return MICX_EDEVICE;
     // DP keys: every (group, row count) class goes to the launch of its shape
-    std::map<DpKey, DpBucket> buckets;
+    struct DpClass {
+        DpPlan p;
+        int gi, yi, n;
+        size_t rec, slot;
+        double cost;
+    };
+    std::map<DpKey, std::vector<DpClass>> byShape;
     for (size_t i = 0; i < ng; i++) {
         const BatchGroup &bg = groups[g0 + i];
         const Geometry &g = lay[i].hg.g;
@@ -727,14 +737,42 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
                 p.fx = false;
                 if (p.T == 3) p.T = 2;   // three targets per lane exist in 32 bits only
             }
-            DpKey key{p.fx ? 1 : 0, p.NL, p.YR, p.T, p.fx ? (int)floor(log2(p.scale)) : 0};
+            DpKey key{p.fx ? 1 : 0, p.NL, p.YR, p.T, p.fx ? (int)floor(log2(p.scale)) : 0, -1};
+            byShape[key].push_back({p, (int)i, yi, bg.n, (size_t)p.KS * p.RS * 4,
+                                    (size_t)p.x * p.KS * (p.fx ? 4 : 8), (double)p.x * p.KS * p.KS});
+        }
+    }
+    // one launch per key, unless its largest table and its largest count
+    // records together exceed the LDS: then it is split, largest n first,
+    // into launches that fit (every class fits on its own)
+    std::map<DpKey, DpBucket> buckets;
+    for (auto &kv : byShape) {
+        std::vector<DpClass> &cl = kv.second;
+        std::sort(cl.begin(), cl.end(), [](const DpClass &u, const DpClass &v) { return u.n > v.n; });
+        const int vb = kv.first.fx ? 4 : 8;
+        const int NLP = (kv.first.NL + 16 / vb - 1) / (16 / vb) * (16 / vb);
+        auto need = [&](int nmax, size_t rec) {
+            return (size_t)align16b((size_t)(nmax + 1) * vb) + align16b(std::max((size_t)8 * NLP * vb, (size_t)nmax)) +
+                   align16b(rec);
+        };
+        int part = -1, nmax = 0;
+        size_t rec = 0;
+        for (const DpClass &c : cl) {
+            if (part < 0 || need(nmax, std::max(rec, c.rec)) > 160 * 1024) {
+                part++;
+                nmax = c.n;
+                rec = 0;
+            }
+            rec = std::max(rec, c.rec);
+            DpKey key = kv.first;
+            key.grp = part;
             DpBucket &b = buckets[key];
-            if (b.classes.empty()) b.plan = p;
-            b.nmax = std::max(b.nmax, bg.n);
-            b.rec = std::max(b.rec, (size_t)p.KS * p.RS * 4);
-            b.slot = std::max(b.slot, (size_t)p.x * p.KS * (p.fx ? 4 : 8));
-            if (p.fx) b.scale = b.scale == 0.0 ? p.scale : std::min(b.scale, p.scale);
-            b.classes.push_back({(double)p.x * p.KS * p.KS, {(int)i, yi}});
+            if (b.classes.empty()) b.plan = c.p;
+            b.nmax = std::max(b.nmax, c.n);
+            b.rec = std::max(b.rec, c.rec);
+            b.slot = std::max(b.slot, c.slot);
+            if (c.p.fx) b.scale = b.scale == 0.0 ? c.p.scale : std::min(b.scale, c.p.scale);
+            b.classes.push_back({c.cost, {c.gi, c.yi}});
         }
     }
     // keys run largest first (their longest items start at once), round-robin
@@ -879,14 +917,20 @@ extern "C" int micx_batch(micx_ctx *ctx, const void *data_dev, int dtype,
         RETCHK(check_common(ctx, d.n, d.alpha, d.c, mode));
         if (d.off_x < 0 || d.off_y < 0) return MICX_EINVAL;
     }
-    HIPCHK(hipSetDevice(ctx->device));
-    hipStream_t s = (hipStream_t)stream;
-    const int esize = dtype == MICX_F64 ? 8 : 4;
     // pairs that share (n, alpha, c) share the grid geometry; a group whose
     // buffers would fill a large part of the arena is split
     std::map<std::tuple<int, double, double>, std::vector<int64_t>> byKey;
     for (int64_t k = 0; k < npairs; k++)
         byKey[std::make_tuple(pairs_host[k].n, pairs_host[k].alpha, pairs_host[k].c)].push_back(k);
+    for (auto &kv : byKey) {
+        HostGeometry hg;
+        const int n = std::get<0>(kv.first);
+        make_geometry(n, micx_grid_bound(n, std::get<1>(kv.first)), std::get<2>(kv.first), hg);
+        if (!dp_fits(hg.g, n)) return MICX_ETOOBIG;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int esize = dtype == MICX_F64 ? 8 : 4;
     std::vector<BatchGroup> groups;
     for (auto &kv : byKey) {
         BatchGroup g;
@@ -944,6 +988,7 @@ extern "C" int micx_compute_score(micx_ctx *ctx, const double *x, const double *
     HostGeometry hg;
     const int B = micx_grid_bound(n, alpha);
     make_geometry(n, B, c, hg);
+    if (!dp_fits(hg.g, n)) return MICX_ETOOBIG;
     RETCHK(upload_geometry(ctx, hg, s));
     RETCHK(upload_pair_input(ctx, x, y, n, s));
     RankTables rt;
@@ -1036,6 +1081,7 @@ extern "C" int micx_debug_item(micx_ctx *ctx, const double *x, const double *y, 
     hipStream_t s = nullptr;
     HostGeometry hg;
     make_geometry(n, B, c, hg);
+    if (!dp_fits(hg.g, n)) return MICX_ETOOBIG;
     RETCHK(upload_geometry(ctx, hg, s));
     RETCHK(upload_pair_input(ctx, x, y, n, s));
     RankTables rt;

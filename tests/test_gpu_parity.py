@@ -327,3 +327,21 @@ def test_batch_errors_leave_output(micx):
         micx.batch(torch.from_numpy(nan_data).cuda(), offx, offy, ns, alphas, cs, out=out)
     assert e.value.code == micx.MICX_ENONFINITE
     assert (out == -7.0).all(), "outputs must stay untouched on error"
+
+
+def test_too_large_grid_is_rejected(micx):
+    # alpha = 1 at n = 8192 gives B = 8192: the y = 2 item would need about
+    # 8,192 superclumps of count records beside the table, more than one
+    # compute unit's LDS.  The call must refuse before any work.
+    import torch
+    _log("case too large")
+    x = np.linspace(0, 1, 8192)
+    with pytest.raises(micx.MicxError) as e:
+        micx.compute_score(x, x[::-1].copy(), 1.0, 15)
+    assert e.value.code == micx.MICX_ETOOBIG
+    out = torch.full((1, 4), -7.0, dtype=torch.float64, device="cuda")
+    data = torch.from_numpy(np.concatenate([x, x]).astype(np.float32)).cuda()
+    with pytest.raises(micx.MicxError) as e:
+        micx.batch(data, [0], [8192], [8192], [1.0], [15.0], out=out)
+    assert e.value.code == micx.MICX_ETOOBIG
+    assert (out == -7.0).all()
