@@ -99,6 +99,7 @@ DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol) {
     if (p.fx && p.NL >= 20 && p.YR > 0 && p.YR <= 5) p.T = 3;
     const int tforce = env_int("MICX_DP_T", 0);
     if (tforce == 1 || (tforce == 2 && p.NL >= 5 && p.YR > 0 && p.YR <= 12)) p.T = tforce;
+    if (tforce == 3 && p.fx && p.YR > 0 && pick(true, p.NL, p.YR, 3)) p.T = 3;
     if (x == 2) {                                      // no full layer: the lean shape
         p.NL = 0;
         p.YR = 0;

@@ -12,7 +12,7 @@
 #define MICX_NL_TINY(X, YR) X(1, YR) X(2, YR) X(3, YR) X(4, YR)
 #define MICX_CASE(NLv, YRv) \
     if (NL == NLv && YR == YRv) \
-        return T == 1 ? k_dp<MICX_V, NLv, YRv, 1, MICX_GR> : k_dp<MICX_V, NLv, YRv, 2, MICX_GR>;
+        return T == 1 ? k_dp<MICX_V, NLv, YRv, 1, MICX_GR> : T == 2 ? k_dp<MICX_V, NLv, YRv, 2, MICX_GR> : nullptr;
 // three targets per lane: passes of >= 20 layers with few rows (32-bit form)
 #define MICX_CASE3(NLv, YRv) \
     if (NL == NLv && YR == YRv && T == 3) return k_dp<MICX_V, NLv, YRv, 3, MICX_GR>;
