@@ -220,24 +220,28 @@ __device__ __forceinline__ void part_body(const PartArgs &a, int w, unsigned cha
     int cstart = 0, k = 0;                   // current clump start, clumps emitted
     int sa = 0, sP0 = 0, sR = n, sL = kh, sr = 0;   // superclump greedy state
 
-    auto emit_clump = [&](int ce) {
+    // A clump boundary at ce when e (per lane): the clump list and the
+    // superclump greedy (EquipartitionYAxis over the clump sizes, same
+    // integer test as k_equip) advance through selects; only the two stores
+    // are conditional.  (2a + s) <= 3n and L <= n with n <= MICX_MAX_N, so
+    // the product fits 32 bits.
+    auto emit_clump = [&](bool e, int ce) {
         const int size = ce - cstart;
-        k++;
-        if (act && k <= kh) cb[k - 1] = ce;
-        if (sa != 0 && (int64_t)(2 * sa + size) * sL >= 2 * (int64_t)sR) {
-            if (act) sb[sr] = sP0 + sa;
-            sr++;
-            sP0 += sa;
-            sa = 0;
-            sR = n - sP0;
-            sL = kh - sr;
-        }
-        sa += size;
-        cstart = ce;
+        k += e ? 1 : 0;
+        if (e & act & (k <= kh)) cb[k - 1] = ce;
+        const bool sup = e & (sa != 0) & ((2 * sa + size) * sL >= 2 * sR);   // no short-circuit
+        if (sup & act) sb[sr] = sP0 + sa;
+        sr += sup ? 1 : 0;
+        sP0 += sup ? sa : 0;
+        sa = sup ? 0 : sa;
+        sR = n - sP0;
+        sL = kh - sr;
+        sa += e ? size : 0;
+        cstart = e ? ce : cstart;
     };
     auto close_group = [&]() {
         const int lg = mixed ? -1 : first;
-        if (last != -2 && (lg == -1 || last == -1 || lg != last)) emit_clump(gstart);
+        emit_clump((last != -2) & ((lg == -1) | (last == -1) | (lg != last)), gstart);
         last = lg;
     };
 
@@ -296,7 +300,7 @@ __device__ __forceinline__ void part_body(const PartArgs &a, int w, unsigned cha
         wave_sync();   // the tile is rewritten by the next block
     }
     close_group();
-    emit_clump(n);
+    emit_clump(true, n);
     if (act) sb[sr] = n;
     if (act) {
         const size_t it = (size_t)po * a.NY + yi;
