@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="pairs timed on the CPU oracle (0 disables the baseline)")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--sweep", action="store_true",
+                    help="also run the grid-bound scaling sweep (uniform random data, "
+                         "alpha in {0.5, 0.6, 0.7}, growing n)")
     ap.add_argument("--no-stream", action="store_true",
                     help="skip the uneven pair-stream leg (micx_batch, 8,192 pairs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -179,6 +182,38 @@ def stream_leg(micx, with_oracle):
     return leg
 
 
+def sweep_leg(micx):
+    """The paper's timing experiment over the grid bound B = n^alpha (Sec. 2C):
+    independent uniform variables, alpha in {0.5, 0.6, 0.7}, n from 250 to
+    8000.  Per point: all pairs of 64 variables (2,016 pairs) in the DP32
+    form after one warm-up call.  The cost model of the DP is about
+    c^2 B^3 per pair, so the time per pair should grow like n^(3 alpha); the
+    fitted exponent is reported beside it."""
+    import torch
+    out = []
+    for alpha in (0.5, 0.6, 0.7):
+        pts = []
+        for n in (250, 500, 1000, 2000, 4000, 8000):
+            rng = np.random.default_rng(2000 + n)
+            X = torch.from_numpy(rng.uniform(0.0, 1.0, (64, n)).astype(np.float32)).cuda()
+            micx.allpairs(X, alpha, 15.0, micx.MODE_DP32)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            micx.allpairs(X, alpha, 15.0, micx.MODE_DP32)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            pts.append({"n": n, "B": micx.grid_bound(n, alpha), "ms": round(dt * 1e3, 2),
+                        "pairs_per_s": round(2016 / dt, 1)})
+            print("bench: sweep alpha=%.1f n=%d done" % (alpha, n), file=sys.stderr, flush=True)
+        # slope of log(time) over the upper half of n (small n is launch-bound)
+        ln = np.log([p["n"] for p in pts[2:]])
+        lt = np.log([p["ms"] for p in pts[2:]])
+        slope = float(np.polyfit(ln, lt, 1)[0])
+        out.append({"alpha": alpha, "points": pts, "fitted_exponent_n_ge_1000": round(slope, 3),
+                    "model_exponent": round(3 * alpha, 2)})
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -261,6 +296,8 @@ def main():
             forms[form]["parity"] = parity_of(results[form][2][idx], ref)
     if not args.no_stream and args.m == 1000:
         result["batch_stream"] = stream_leg(micx, args.cpu_sample > 0)
+    if args.sweep:
+        result["sweep"] = sweep_leg(micx)
     if args.copy_calibration > 0:
         nb = args.copy_calibration << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")

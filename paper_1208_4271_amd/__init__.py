@@ -264,6 +264,17 @@ def batch(data, off_x, off_y, ns, alphas, cs, mode: int = MODE_FP64, out=None, s
     return out
 
 
+def master(X, i: int, alpha: float = 0.6, c: float = 15.0, mode: int = MODE_FP64, out=None,
+           stream=None):
+    """One variable against all others (the paper's master-variable mode):
+    rows (i, j) of X for every j != i, in increasing j, through micx_pairs.
+    Returns an (m-1, 4) float64 CUDA tensor of (MIC, MAS, MEV, MCN)."""
+    m = X.shape[0]
+    if not 0 <= i < m:
+        raise ValueError("master variable out of range")
+    return pairs(X, [(i, j) for j in range(m) if j != i], alpha, c, mode, out, stream)
+
+
 def debug_item(x, y, alpha: float, c: float, orient: int, ry: int, device: int = 0):
     """Integer stages of one item (see micx_debug_item)."""
     x, y = _f64(x), _f64(y)

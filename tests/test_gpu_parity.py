@@ -345,3 +345,19 @@ def test_too_large_grid_is_rejected(micx):
         micx.batch(data, [0], [8192], [8192], [1.0], [15.0], out=out)
     assert e.value.code == micx.MICX_ETOOBIG
     assert (out == -7.0).all()
+
+
+def test_master_variable_mode(micx):
+    # one variable against all others equals the matching rows of all pairs
+    import torch
+    _log("case master variable")
+    X = workloads.cfg2_matrix()[:14]
+    Xd = torch.from_numpy(X).cuda()
+    allp = micx.allpairs(Xd, 0.6, 15).cpu().numpy()
+    m = X.shape[0]
+    idx = {p: k for k, p in enumerate([(a, b) for a in range(m) for b in range(a + 1, m)])}
+    for i in (0, 5, m - 1):
+        got = micx.master(Xd, i, 0.6, 15).cpu().numpy()
+        assert got.shape == (m - 1, 4)
+        for r, j in enumerate([j for j in range(m) if j != i]):
+            assert np.abs(got[r] - allp[idx[(min(i, j), max(i, j))]]).max() <= 1e-12
