@@ -69,13 +69,33 @@ extern "C" {
 #define MICX_MODE_FP64  0   /* DP in FP64 */
 #define MICX_MODE_DP32  1   /* DP in 32-bit fixed point with a per-class error bound, FP64 elsewhere */
 
+/* Compatibility variants of readings the paper leaves open (micx_set_compat;
+ * default 0 = the readings this library takes).  Each reproduces a variant
+ * the paper discusses:
+ *   TIE_STRICT     EquipartitionYAxis closes a row on '>' instead of '>='
+ *                  (App. A item 3 with a strict comparison);
+ *   DESIRED_INT    the desired row size is cast to an integer (App. A
+ *                  item 3's integer variable);
+ *   COMBINE_INDEX  the two orientations are combined at equal
+ *                  (equipartitioned, optimised) index, not equal grid shape;
+ *   NORM_BY_Y      entries are normalised by ln min(x, y), the requested
+ *                  rows, instead of ln min(x, yhat) (App. A item 4);
+ *   BOUND_STRICT   cells satisfy xy < B instead of xy <= B (App. A item 1);
+ *   KHAT_PLUS1     up to khat + 1 superclumps (App. A item 7's behaviour). */
+#define MICX_COMPAT_TIE_STRICT     1
+#define MICX_COMPAT_DESIRED_INT    2
+#define MICX_COMPAT_COMBINE_INDEX  4
+#define MICX_COMPAT_NORM_BY_Y      8
+#define MICX_COMPAT_BOUND_STRICT  16
+#define MICX_COMPAT_KHAT_PLUS1    32
+
 /* Opaque context: device, workspace, cached tables. */
 typedef struct micx_ctx micx_ctx;
 
 /* Score of one pair: the characteristic matrix (the paper's score structure). */
 typedef struct {
     int n;            /* sample size */
-    int B;            /* grid bound floor(n^alpha) */
+    int B;            /* largest cell count xy: floor(n^alpha) (minus 1 with MICX_COMPAT_BOUND_STRICT) */
     int W;            /* matrix side, floor(B/2) - 1 */
     double *M;        /* W*W doubles, M[(y-2)*W + (x-2)] = M_{x,y}; NaN where x*y > B */
     double *Axy;      /* W*W: first variable into l columns (DP), second equipartitioned into r rows: Axy[(r-2)*W + (l-2)] */
@@ -204,6 +224,10 @@ int micx_get_profile(micx_ctx *ctx, micx_profile *out);
  * fixed-point bound exceeds it runs in FP64.  Returns MICX_EINVAL unless
  * tol > 0. */
 int micx_set_dp32_tolerance(micx_ctx *ctx, double tol);
+
+/* Compatibility flags (MICX_COMPAT_*, OR-ed) for every later call on ctx.
+ * Returns MICX_EINVAL for unknown bits. */
+int micx_set_compat(micx_ctx *ctx, int flags);
 
 /* Message for a return code (static string). */
 const char *micx_strerror(int code);

@@ -29,12 +29,21 @@ F32, F64, I32 = 0, 1, 2
 MODE_FP64 = 0
 MODE_DP32 = 1
 
+# Compatibility variants (include/micx.h, MICX_COMPAT_*); same bit values as
+# the oracle's reading flags.
+COMPAT_TIE_STRICT = 1
+COMPAT_DESIRED_INT = 2
+COMPAT_COMBINE_INDEX = 4
+COMPAT_NORM_BY_Y = 8
+COMPAT_BOUND_STRICT = 16
+COMPAT_KHAT_PLUS1 = 32
+
 # Every symbol declared in include/micx.h.
 EXPORTS = (
     "micx_ctx_create", "micx_ctx_destroy", "micx_check_param", "micx_grid_bound",
     "micx_compute_score", "micx_mic", "micx_mas", "micx_mev", "micx_mcn", "micx_free_score",
     "micx_allpairs", "micx_pairs", "micx_batch", "micx_debug_item", "micx_strerror",
-    "micx_set_profiling", "micx_get_profile", "micx_set_dp32_tolerance",
+    "micx_set_profiling", "micx_get_profile", "micx_set_dp32_tolerance", "micx_set_compat",
 )
 
 
@@ -112,6 +121,8 @@ def load_library():
     lib.micx_get_profile.restype = ctypes.c_int
     lib.micx_set_dp32_tolerance.argtypes = [vp, ctypes.c_double]
     lib.micx_set_dp32_tolerance.restype = ctypes.c_int
+    lib.micx_set_compat.argtypes = [vp, ctypes.c_int]
+    lib.micx_set_compat.restype = ctypes.c_int
     lib.micx_strerror.argtypes = [ctypes.c_int]
     lib.micx_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -308,3 +319,8 @@ def set_dp32_tolerance(tol: float, device: int = 0):
     """Largest |dM| allowed for a row count to run the DP in 32-bit fixed point."""
     _check(load_library().micx_set_dp32_tolerance(context(device), float(tol)),
            "micx_set_dp32_tolerance")
+
+
+def set_compat(flags: int, device: int = 0):
+    """Compatibility variants (COMPAT_* OR-ed) for every later call on the device."""
+    _check(load_library().micx_set_compat(context(device), int(flags)), "micx_set_compat")

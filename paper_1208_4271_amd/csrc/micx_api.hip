@@ -57,6 +57,7 @@ struct micx_ctx {
     DevBuf counters, fxtab, lab;
     DevBuf bdata, boffs, bout, bidx;   // micx_batch: gathered variables, offsets, staged results
     double dp32_tol = 5e-7;   // half of the 1e-6 agreement required of the scores
+    int compat = 0;           // MICX_COMPAT_* flags
     int profiling = 0;
     micx_profile prof = {};
     DevBuf arena, gitems;              // micx_batch: per-pass group buffers, DP item lists
@@ -137,8 +138,10 @@ struct HostGeometry {
 // Grid geometry for (n, B, c): row counts y = 2..floor(B/2), x(y) = floor(B/y),
 // khat(y) = max(1, min(floor(c x(y)), n)) (Algorithm 2's bound; it never
 // needs to exceed n, the largest possible clump count).
-void make_geometry(int n, int B, double c, HostGeometry &hg) {
+void make_geometry(int n, int B, double c, HostGeometry &hg, int compat = 0) {
     Geometry &g = hg.g;
+    if (compat & MICX_COMPAT_BOUND_STRICT) B -= 1;   // cells with xy < B
+    g.compat = compat;
     g.n = n;
     g.B = B;
     g.xmax = B / 2;
@@ -152,6 +155,7 @@ void make_geometry(int n, int B, double c, HostGeometry &hg) {
     for (int yi = 0; yi < g.NY; yi++) {
         const int y = yi + 2, x = B / y;
         double kd = floor(c * (double)x);
+        if (compat & MICX_COMPAT_KHAT_PLUS1) kd += 1.0;
         int kh = kd >= (double)n ? n : (int)kd;
         if (kh < 1) kh = 1;
         hg.xcnt[yi] = x;
@@ -194,7 +198,8 @@ int check_common(micx_ctx *ctx, int n, double alpha, double c, int mode) {
     if (mode != MICX_MODE_FP64 && mode != MICX_MODE_DP32) return MICX_EINVAL;
     if (n < 2) return MICX_EINVAL;
     if (n > MICX_MAX_N) return MICX_ETOOBIG;
-    if (micx_grid_bound(n, alpha) < 4) return MICX_ESMALLN;
+    if (micx_grid_bound(n, alpha) - ((ctx->compat & MICX_COMPAT_BOUND_STRICT) ? 1 : 0) < 4)
+        return MICX_ESMALLN;
     return MICX_OK;
 }
 
@@ -218,6 +223,7 @@ int prepare_variables(micx_ctx *ctx, const void *X, int dtype, int m, int n, con
     rt.grank = ctx->grank.as<int>();
     et.NY = g.NY;
     et.NYP = NYP;
+    et.compat = g.compat;
     et.rowof = ctx->rowof.as<uint16_t>();
     et.yhat = ctx->yhat.as<int>();
     et.RS = g.NY + 2;
@@ -392,7 +398,7 @@ extern "C" int micx_allpairs(micx_ctx *ctx, const void *X_dev, int dtype, int m,
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     HostGeometry hg;
-    make_geometry(n, micx_grid_bound(n, alpha), c, hg);
+    make_geometry(n, micx_grid_bound(n, alpha), c, hg, ctx->compat);
     if (!dp_fits(hg.g, n)) return MICX_ETOOBIG;
     RETCHK(upload_geometry(ctx, hg, s));
     RankTables rt;
@@ -418,7 +424,7 @@ extern "C" int micx_pairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, in
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     HostGeometry hg;
-    make_geometry(n, micx_grid_bound(n, alpha), c, hg);
+    make_geometry(n, micx_grid_bound(n, alpha), c, hg, ctx->compat);
     if (!dp_fits(hg.g, n)) return MICX_ETOOBIG;
     RETCHK(upload_geometry(ctx, hg, s));
     RETCHK(ctx->pairs.ensure((size_t)npairs * 2 * sizeof(int32_t)));
@@ -457,8 +463,8 @@ inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Assigns the arena offsets of a group: the parts the host fills (geometry,
 // pair list, gather offsets) from *hc, the device-only parts from *dc.
-void layout_group(const BatchGroup &bg, int esize, size_t &hc, size_t &dc, GroupLayout &L) {
-    make_geometry(bg.n, micx_grid_bound(bg.n, bg.alpha), bg.c, L.hg);
+void layout_group(const BatchGroup &bg, int esize, size_t &hc, size_t &dc, GroupLayout &L, int compat) {
+    make_geometry(bg.n, micx_grid_bound(bg.n, bg.alpha), bg.c, L.hg, compat);
     const Geometry &g = L.hg.g;
     const size_t P = bg.idx.size(), nv = 2 * P, n = (size_t)bg.n, NY = (size_t)g.NY;
     L.NYP = (g.NY + 7) / 8 * 8;
@@ -491,7 +497,7 @@ void layout_group(const BatchGroup &bg, int esize, size_t &hc, size_t &dc, Group
 size_t group_bytes(const BatchGroup &bg, int esize) {
     GroupLayout L;
     size_t hc = 0, dc = 0;
-    layout_group(bg, esize, hc, dc, L);
+    layout_group(bg, esize, hc, dc, L, 0);
     return hc + dc;
 }
 
@@ -541,7 +547,7 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
     size_t hc = 0, dc = 0;
     int nmax = 0;
     for (size_t i = 0; i < ng; i++) {
-        layout_group(groups[g0 + i], esize, hc, dc, lay[i]);
+        layout_group(groups[g0 + i], esize, hc, dc, lay[i], ctx->compat);
         nmax = std::max(nmax, groups[g0 + i].n);
     }
     // block maps of the fused per-group stages (group, block inside the group)
@@ -650,6 +656,7 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
         d.A = (double *)(ar + L.A);
         d.pairs = (const int32_t *)(ar + L.pairs);
         d.out = ctx->bout.as<double>() + 4 * bg.row0;
+        d.compat = ctx->compat;
     }
     memcpy(blob.data() + tab_off, tab.data(), ng * sizeof(DpGroup));
     memcpy(blob.data() + gdev_off, gdev.data(), ng * sizeof(GroupDev));
@@ -859,7 +866,8 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
             const int nit = (int)(b.items.size() / 3);
             HIPCHK(launch_dp_items((const DpGroup *)(ar + tab_off), ctx->gitems.as<int>() + off, nit, b.nmax,
                                    ctx->xlogx.as<double>(), tab,
-                                   ctx->scratch.as<unsigned char>() + scr_off[k % kDpStreams], b.plan, st));
+                                   ctx->scratch.as<unsigned char>() + scr_off[k % kDpStreams], b.plan,
+                                   ctx->compat, st));
             if (ctx->profiling) HIPCHK(hipEventRecord(ev.back(), st));
             off += b.items.size();
             k++;
@@ -925,7 +933,7 @@ extern "C" int micx_batch(micx_ctx *ctx, const void *data_dev, int dtype,
     for (auto &kv : byKey) {
         HostGeometry hg;
         const int n = std::get<0>(kv.first);
-        make_geometry(n, micx_grid_bound(n, std::get<1>(kv.first)), std::get<2>(kv.first), hg);
+        make_geometry(n, micx_grid_bound(n, std::get<1>(kv.first)), std::get<2>(kv.first), hg, ctx->compat);
         if (!dp_fits(hg.g, n)) return MICX_ETOOBIG;
     }
     HIPCHK(hipSetDevice(ctx->device));
@@ -987,7 +995,7 @@ extern "C" int micx_compute_score(micx_ctx *ctx, const double *x, const double *
     hipStream_t s = nullptr;
     HostGeometry hg;
     const int B = micx_grid_bound(n, alpha);
-    make_geometry(n, B, c, hg);
+    make_geometry(n, B, c, hg, ctx->compat);
     if (!dp_fits(hg.g, n)) return MICX_ETOOBIG;
     RETCHK(upload_geometry(ctx, hg, s));
     RETCHK(upload_pair_input(ctx, x, y, n, s));
@@ -1006,7 +1014,7 @@ extern "C" int micx_compute_score(micx_ctx *ctx, const double *x, const double *
     micx_score *sc = (micx_score *)calloc(1, sizeof(micx_score));
     if (!sc) return MICX_ENOMEM;
     sc->n = n;
-    sc->B = B;
+    sc->B = hg.g.B;
     sc->W = W;
     sc->M = (double *)malloc(WW * sizeof(double));
     sc->Axy = (double *)malloc(WW * sizeof(double));
@@ -1026,6 +1034,14 @@ extern "C" int micx_compute_score(micx_ctx *ctx, const double *x, const double *
 extern "C" int micx_set_profiling(micx_ctx *ctx, int enable) {
     if (!ctx) return MICX_EINVAL;
     ctx->profiling = enable ? 1 : 0;
+    return MICX_OK;
+}
+
+extern "C" int micx_set_compat(micx_ctx *ctx, int flags) {
+    const int all = MICX_COMPAT_TIE_STRICT | MICX_COMPAT_DESIRED_INT | MICX_COMPAT_COMBINE_INDEX |
+                    MICX_COMPAT_NORM_BY_Y | MICX_COMPAT_BOUND_STRICT | MICX_COMPAT_KHAT_PLUS1;
+    if (!ctx || (flags & ~all)) return MICX_EINVAL;
+    ctx->compat = flags;
     return MICX_OK;
 }
 
@@ -1080,7 +1096,7 @@ extern "C" int micx_debug_item(micx_ctx *ctx, const double *x, const double *y, 
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t s = nullptr;
     HostGeometry hg;
-    make_geometry(n, B, c, hg);
+    make_geometry(n, B, c, hg, ctx->compat);
     if (!dp_fits(hg.g, n)) return MICX_ETOOBIG;
     RETCHK(upload_geometry(ctx, hg, s));
     RETCHK(upload_pair_input(ctx, x, y, n, s));

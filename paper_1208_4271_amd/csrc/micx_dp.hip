@@ -214,7 +214,7 @@ hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry
     a.xlogx = xlogx; a.fxtab = fxtab; a.inv_scale = 1.0 / p.scale;
     a.scratch = scratch; a.slot_bytes = p.slot_bytes;
     a.lds_L = p.lds_L; a.lds_stage = p.lds_stage; a.lds_wave = p.lds_wave;
-    a.groups = nullptr; a.gitems = nullptr;
+    a.groups = nullptr; a.gitems = nullptr; a.compat = g.compat;
     dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T);
     if (!k) return hipErrorInvalidValue;
     // the attribute is the whole LDS budget, the same for every caller (plans
@@ -232,8 +232,9 @@ hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry
 
 hipError_t launch_dp_items(const DpGroup *groups, const int *gitems, int nitems, int nmax,
                            const double *xlogx, const uint32_t *fxtab, void *scratch,
-                           const DpPlan &p, hipStream_t s) {
+                           const DpPlan &p, int compat, hipStream_t s) {
     DpArgs a = {};
+    a.compat = compat;
     a.n = nmax;
     a.nitems = nitems;
     a.SB = p.SB;

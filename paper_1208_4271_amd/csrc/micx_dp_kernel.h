@@ -62,6 +62,7 @@ struct DpArgs {
     // the launch
     const DpGroup *groups;
     const int *gitems;
+    int compat;                  // MICX_COMPAT_* flags (MICX_COMPAT_NORM_BY_Y acts here)
     int lds_L, lds_stage, lds_wave;
 };
 
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
     for (int wi = gw; wi < a.nitems; wi += nw) {
         // the item: its sample count n, columns x, G-table and count-record
         // strides, superclump count K, rows yhat and buffers
-        int n, x, KS, RS, K, yh;
+        int n, x, KS, RS, K, yh, ycls;
         const int *ends;
         const unsigned char *lb8;
         bool l16;
@@ -149,6 +150,7 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
             const int pl = po >> 1, Vv = (po & 1) ? 2 * pl : 2 * pl + 1;
             const size_t it = (size_t)po * gr.NY + yi;
             n = gr.n;
+            ycls = yi + 2;
             x = gr.xcnt[yi];
             KS = gr.khat[yi] + 1;
             RS = YR > 0 ? YR + 1 : yi + 3;
@@ -166,6 +168,7 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
             const int Vv = o ? pi : pj;
             const size_t it = (size_t)po * NY + yi;
             n = a.n;
+            ycls = yi + 2;
             x = a.x;
             KS = a.KS;
             RS = a.RS;
@@ -416,7 +419,7 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
         for (int l = 2 + lane; l <= x; l += 64) {
             const V Gl = (l == x) ? best : G[(size_t)l * KS + K];
             const double I = (Ln - sq - DV::real(Gl, a.inv_scale)) / (double)n;
-            const int norm = min(l, yh);
+            const int norm = min(l, (a.compat & MICX_COMPAT_NORM_BY_Y) ? ycls : yh);
             // ln(norm) = (norm ln norm) / norm from the j ln j table
             Aout[l - 2] = norm >= 2 ? I * (double)norm / a.xlogx[norm] : 0.0;
         }

@@ -26,6 +26,7 @@ struct EquipTables {
     int *yhat = nullptr;        // [v][y-2]: rows produced
     int *rowstart = nullptr;    // [v][y-2][r]: start position of row r (r = 0..yhat), may be null
     int RS = 0;                 // stride of rowstart per (v, y): NY + 2
+    int compat = 0;             // MICX_COMPAT_* flags
 };
 
 // Grid geometry of one (n, alpha, c) configuration, computed on the host.
@@ -39,6 +40,7 @@ struct Geometry {
     int *aoff = nullptr;   // offsets of per-item score rows inside one (pair, orientation)
     int KSUM = 0, ASUM = 0, KMAX = 0, KYMAX = 0;   // sums and maxima over y
     const int *khat_host = nullptr;                // khat per y-2 (host copy)
+    int compat = 0;                                // MICX_COMPAT_* flags
 };
 
 // Launch shape of the DP for one row count y.
@@ -100,6 +102,7 @@ struct GroupDev {
     double *A = nullptr;
     const int32_t *pairs = nullptr;  // (2i, 2i+1) per pair
     double *out = nullptr;           // 4 doubles per pair
+    int compat = 0;                  // MICX_COMPAT_* flags
 };
 
 // Fused per-group stages: map[b] = (group, index of the block inside the
@@ -135,7 +138,7 @@ void dp_fit_lds(DpPlan &p, int nmax, size_t rec_bytes, int cus);
 // p.slot_bytes.
 hipError_t launch_dp_items(const DpGroup *groups, const int *gitems, int nitems, int nmax,
                            const double *xlogx, const uint32_t *fxtab, void *scratch,
-                           const DpPlan &p, hipStream_t s);
+                           const DpPlan &p, int compat, hipStream_t s);
 hipError_t launch_fxtable(int n, const DpPlan &p, const double *xlogx, uint32_t *tab,
                           hipStream_t s);
 hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry &g,

@@ -36,6 +36,20 @@ __device__ __forceinline__ uint64_t order_key(double d) {
     return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
 
+// EquipartitionYAxis row-closing test on integers (App. A item 3): a points
+// in the open row, s in the next tie group, R points left when the row
+// opened, L rows left including it.  |a + s - d| >= |a - d| with d = R/L
+// is (2a + s) L >= 2R.  Compatibility flags: MICX_COMPAT_TIE_STRICT closes
+// on '>' only; MICX_COMPAT_DESIRED_INT takes d = floor(R/L), giving
+// 2a + s >= 2 floor(R/L).  (2a + s) <= 3n and L <= n, so 32 bits hold
+// the products for n <= MICX_MAX_N; L >= 1 always (the last row never
+// closes).
+__device__ __forceinline__ bool closes_row(int a, int s, int R, int L, int compat) {
+    const int lhs = (compat & MICX_COMPAT_DESIRED_INT) ? 2 * a + s : (2 * a + s) * L;
+    const int rhs = (compat & MICX_COMPAT_DESIRED_INT) ? 2 * (R / L) : 2 * R;
+    return (compat & MICX_COMPAT_TIE_STRICT) ? lhs > rhs : lhs >= rhs;
+}
+
 // ------------------------------------------------------------------ k_xlogx
 
 __global__ void k_xlogx(int n, double *L) {
@@ -122,7 +136,8 @@ __global__ __launch_bounds__(1024) void k_rank(const void *X, int dtype, int m, 
 // test (2a + s) * L >= 2R, used here so that the partition is bit-exact.
 
 __device__ __forceinline__ void equip_body(int v, int yb, int n, int NY, int NYP, const int *gsize,
-                                           uint16_t *rowof, int *yhat, int *rowstart, int RS, int *gs) {
+                                           uint16_t *rowof, int *yhat, int *rowstart, int RS, int *gs,
+                                           int compat) {
     // gs: the variable's tie-group sizes in LDS, copied once (coalesced)
     const int yi = yb * 64 + threadIdx.x;
     const bool act = yi < NY;
@@ -135,7 +150,7 @@ __device__ __forceinline__ void equip_body(int v, int yb, int n, int NY, int NYP
     if (act && rs) rs[0] = 0;
     for (int p = 0; p < n;) {
         const int s = gs[p];
-        if (a != 0 && (int64_t)(2 * a + s) * L >= 2 * (int64_t)R) {
+        if (a != 0 && closes_row(a, s, R, L, compat)) {
             r++;
             a = 0;
             R = n - p;
@@ -153,10 +168,10 @@ __device__ __forceinline__ void equip_body(int v, int yb, int n, int NY, int NYP
 }
 
 __global__ __launch_bounds__(64) void k_equip(int m, int n, int NY, int NYP, const int *gsize,
-                                              uint16_t *rowof, int *yhat, int *rowstart, int RS) {
+                                              uint16_t *rowof, int *yhat, int *rowstart, int RS, int compat) {
     extern __shared__ int gsl[];
     const int nyb = (NY + 63) / 64;
-    equip_body(blockIdx.x / nyb, blockIdx.x % nyb, n, NY, NYP, gsize, rowof, yhat, rowstart, RS, gsl);
+    equip_body(blockIdx.x / nyb, blockIdx.x % nyb, n, NY, NYP, gsize, rowof, yhat, rowstart, RS, gsl, compat);
 }
 
 // ------------------------------------------------------------------- k_part
@@ -184,6 +199,7 @@ struct PartArgs {
     int *cbuf, *sbuf, *K, *k, *src;
     unsigned char *lab;          // row labels in column order, [item][y-2][p]
     size_t lab_row;
+    int compat;                  // MICX_COMPAT_* flags
 };
 
 // LDS tile of one 64-point block: each point's labels for the wave's row
@@ -229,7 +245,7 @@ __device__ __forceinline__ void part_body(const PartArgs &a, int w, unsigned cha
         const int size = ce - cstart;
         k += e ? 1 : 0;
         if (e & act & (k <= kh)) cb[k - 1] = ce;
-        const bool sup = e & (sa != 0) & ((2 * sa + size) * sL >= 2 * sR);   // no short-circuit
+        const bool sup = e & (sa != 0) & closes_row(sa, size, sR, sL, a.compat);   // no short-circuit
         if (sup & act) sb[sr] = sP0 + sa;
         sr += sup ? 1 : 0;
         sP0 += sup ? sa : 0;
@@ -329,7 +345,7 @@ __global__ __launch_bounds__(64) void k_part(PartArgs a) {
 // optimised into y columns with the first equipartitioned into x rows.
 
 struct StatsArgs {
-    int npairs, B, NY, W, ASUM;
+    int npairs, B, NY, W, ASUM, compat;
     const int *aoff;
     const double *A;
     double *out, *M, *Axy, *Ayx;
@@ -340,7 +356,12 @@ __device__ __forceinline__ void stats_body(const StatsArgs &a, int pl) {
     const double *A1 = a.A + (size_t)(2 * pl + 1) * a.ASUM;
     const int Bh = a.B / 2;
     auto Mxy = [&](int xx, int yy) -> double {
-        return fmax(A0[a.aoff[yy - 2] + xx - 2], A1[a.aoff[xx - 2] + yy - 2]);
+        // the other orientation at the same grid shape (x bins of the first
+        // variable, y of the second); MICX_COMPAT_COMBINE_INDEX pairs equal
+        // (equipartitioned, optimised) indices instead
+        return fmax(A0[a.aoff[yy - 2] + xx - 2], (a.compat & MICX_COMPAT_COMBINE_INDEX)
+                                                     ? A1[a.aoff[yy - 2] + xx - 2]
+                                                     : A1[a.aoff[xx - 2] + yy - 2]);
     };
     double mic = 0.0;
     for (int yy = 2; yy <= Bh; yy++)
@@ -448,7 +469,7 @@ hipError_t launch_equip(const RankTables &rt, EquipTables &et, hipStream_t s) {
     const int nyb = (et.NY + 63) / 64;
     hipLaunchKernelGGL(k_equip, dim3(rt.m * nyb), dim3(64), (size_t)rt.n * sizeof(int), s, rt.m, rt.n,
                        et.NY, et.NYP, rt.gsize,
-                       et.rowof, et.yhat, et.rowstart, et.RS);
+                       et.rowof, et.yhat, et.rowstart, et.RS, et.compat);
     return hipGetLastError();
 }
 
@@ -459,7 +480,7 @@ hipError_t launch_part(const RankTables &rt, const EquipTables &et, const Geomet
     a.perm = rt.perm; a.gsize = rt.gsize; a.grank = rt.grank; a.rowof = et.rowof; a.NYP = et.NYP;
     a.khat = g.khat; a.koff = g.koff;
     a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.k = ib.k; a.src = ib.src;
-    a.lab = ib.lab; a.lab_row = ib.lab_row;
+    a.lab = ib.lab; a.lab_row = ib.lab_row; a.compat = et.compat;
     const int nyb = (g.NY + 63) / 64;
     if (ib.lab16) hipLaunchKernelGGL(k_part<true>, dim3((unsigned)(2 * npairs * nyb)), dim3(64), 0, s, a);
     else hipLaunchKernelGGL(k_part<false>, dim3((unsigned)(2 * npairs * nyb)), dim3(64), 0, s, a);
@@ -470,7 +491,7 @@ hipError_t launch_stats(const Geometry &g, int npairs, const ItemBuffers &ib, do
                         double *M, double *Axy, double *Ayx, hipStream_t s) {
     StatsArgs a;
     a.npairs = npairs; a.B = g.B; a.NY = g.NY; a.W = g.W; a.ASUM = g.ASUM;
-    a.aoff = g.aoff; a.A = ib.A; a.out = out; a.M = M; a.Axy = Axy; a.Ayx = Ayx;
+    a.aoff = g.aoff; a.A = ib.A; a.out = out; a.M = M; a.Axy = Axy; a.Ayx = Ayx; a.compat = g.compat;
     hipLaunchKernelGGL(k_stats, dim3((npairs + 127) / 128), dim3(128), 0, s, a);
     return hipGetLastError();
 }
@@ -550,7 +571,8 @@ __global__ __launch_bounds__(64) void k_equip_g(const GroupDev *G, const int2 *m
     const int2 m = map[blockIdx.x];
     const GroupDev &g = G[m.x];
     const int nyb = (g.NY + 63) / 64;
-    equip_body(m.y / nyb, m.y % nyb, g.n, g.NY, g.NYP, g.gsize, g.rowof, g.yhat, nullptr, g.NY + 2, gsl);
+    equip_body(m.y / nyb, m.y % nyb, g.n, g.NY, g.NYP, g.gsize, g.rowof, g.yhat, nullptr, g.NY + 2, gsl,
+               g.compat);
 }
 
 __global__ __launch_bounds__(64) void k_part_g(const GroupDev *G, const int2 *map) {
@@ -563,7 +585,7 @@ __global__ __launch_bounds__(64) void k_part_g(const GroupDev *G, const int2 *ma
     a.perm = g.perm; a.gsize = g.gsize; a.grank = g.grank; a.rowof = g.rowof;
     a.khat = g.khat; a.koff = g.koff;
     a.cbuf = g.cbuf; a.sbuf = g.sbuf; a.K = g.K; a.k = g.k; a.src = g.src;
-    a.lab = g.lab; a.lab_row = g.lab_row;
+    a.lab = g.lab; a.lab_row = g.lab_row; a.compat = g.compat;
     if (g.lab16) part_body<true>(a, m.y, tile);
     else part_body<false>(a, m.y, tile);
 }
@@ -577,6 +599,7 @@ __global__ void k_stats_g(const GroupDev *G, const int2 *map) {
     StatsArgs a;
     a.npairs = g.npairs; a.B = g.B; a.NY = g.NY; a.W = g.W; a.ASUM = g.ASUM;
     a.aoff = g.aoff; a.A = g.A; a.out = g.out; a.M = nullptr; a.Axy = nullptr; a.Ayx = nullptr;
+    a.compat = g.compat;
     stats_body(a, pl);
 }
 

@@ -361,3 +361,62 @@ def test_master_variable_mode(micx):
         assert got.shape == (m - 1, 4)
         for r, j in enumerate([j for j in range(m) if j != i]):
             assert np.abs(got[r] - allp[idx[(min(i, j), max(i, j))]]).max() <= 1e-12
+
+
+# ----------------------------------------------------- compatibility variants
+_COMPAT_CASES = [1, 2, 4, 8, 16, 32, 1 | 2 | 32, 4 | 8 | 16]
+
+
+def _compat_inputs():
+    rng = np.random.default_rng(61)
+    n = 500
+    tied = (np.floor(rng.uniform(0, 40, n)), np.floor(rng.uniform(0, 25, n)))
+    # three row values: yhat stays below the requested row count (normalisation variant)
+    three = (rng.uniform(0, 1, 400), np.floor(rng.uniform(0, 3, 400)))
+    return [("tied", tied), ("three", three), ("cpp", workloads.cpp_example()),
+            ("cfg1", workloads.cfg1_single_pair())]
+
+
+@pytest.mark.parametrize("flags", _COMPAT_CASES)
+def test_compat_variants_match_oracle(micx, flags):
+    _log("case compat flags=%d" % flags)
+    micx.set_compat(flags)
+    try:
+        for name, (x, y) in _compat_inputs():
+            got = micx.compute_score(x, y, 0.6, 15)
+            want = oracle.score(x, y, 0.6, 15, flags=flags)
+            _cmp_scores(got, want, tol=1e-10)
+            if flags & (1 | 2 | 32) and name == "tied":
+                B = oracle.grid_bound(len(x), 0.6) - (1 if flags & 16 else 0)
+                for orient in (0, 1):
+                    for ry in range(2, B // 2 + 1):
+                        g = micx.debug_item(x, y, 0.6, 15, orient, ry)
+                        w = oracle.item(x, y, 0.6, 15, orient, ry, flags=flags)
+                        assert g["yhat"] == w["yhat"] and g["K"] == w["K"], (orient, ry)
+                        assert np.array_equal(g["ends"], w["ends"]), (orient, ry)
+    finally:
+        micx.set_compat(0)
+
+
+def test_compat_in_batch(micx):
+    import torch
+    _log("case compat batch")
+    data, offx, offy, ns, alphas, cs = workloads.cfg5_stream(seed=62, npairs=12, nmin=60, nmax=900)
+    flags = 1 | 8 | 16 | 32
+    micx.set_compat(flags)
+    try:
+        got = micx.batch(torch.from_numpy(data).cuda(), offx, offy, ns, alphas, cs).cpu().numpy()
+    finally:
+        micx.set_compat(0)
+    for k in range(len(ns)):
+        n = int(ns[k])
+        w = oracle.score(data[offx[k]:offx[k] + n].astype(np.float64),
+                         data[offy[k]:offy[k] + n].astype(np.float64), float(alphas[k]), float(cs[k]),
+                         flags=flags)["stats"]
+        assert np.abs(got[k, :3] - w[:3]).max() <= TOL and abs(got[k, 3] - w[3]) < 1e-9
+
+
+def test_compat_rejects_unknown_bits(micx):
+    with pytest.raises(micx.MicxError) as e:
+        micx.set_compat(64)
+    assert e.value.code == micx.MICX_EINVAL
