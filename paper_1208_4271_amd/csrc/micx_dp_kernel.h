@@ -25,7 +25,9 @@
 //
 // Layout.  Lanes own targets t, T per lane (a chunk of 64T targets).  The
 // layers of a pass (up to NL) live in registers, as do the target's
-// cumulative counts (up to YR rows).  Sources from earlier chunks are final:
+// cumulative counts (up to YR rows).  Counts are kept as byte offsets into the
+// L table (count times sizeof(V)), so the table address of a cost term is one
+// difference of two counts.  Sources from earlier chunks are final:
 // their layer values are staged from the item's G table (global, layer-major)
 // into LDS, SB sources at a time, and read back as wavefront-uniform
 // broadcasts.  Sources inside the chunk are taken in order; the lane that
@@ -121,6 +123,13 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
     // index, its sizes and pointers in scalar registers and its branches scalar
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     V *L = (V *)smem;
+    constexpr int VB = (int)sizeof(V);
+    // Table reads by LDS address.  A target's counts are kept with the
+    // table's LDS base added, so the address of a cost term is one difference.
+    typedef __attribute__((address_space(3))) const V *lds_v;
+    const int lbase = (int)(uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char *)smem;
+    auto LA = [&](int addr) -> V { return *(lds_v)(uintptr_t)(uint32_t)addr; };
+    auto LB = [&](int b) -> V { return LA(lbase + b); };     // entry at byte offset b
     for (int j = threadIdx.x; j <= nmax; j += blockDim.x) {
         if constexpr (FX) L[j] = a.fxtab[j];
         else L[j] = a.xlogx[j];
@@ -181,33 +190,80 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
         }
 
         // ---- cumulative counts (item 10a); rows beyond yhat stay 0 ----
-        // A flag per superclump start gives each point its superclump through
-        // a ballot scan; the point's row label (stored in column order by the
-        // partition kernel) selects the count, and LDS atomics count.
+        // Every lane takes a run of consecutive points: one 16-byte load of
+        // row labels (stored in column order by the partition kernel; the
+        // first loads are issued before the table is cleared).  A flag per
+        // superclump start and a wavefront prefix sum of the lanes' flag
+        // counts give each point its superclump; LDS atomics count.
         unsigned char *F = (unsigned char *)stage;
-        const uint16_t *lb16 = (const uint16_t *)lb8;
-        for (int k = lane; k < (K + 1) * RS; k += 64) rec[k] = 0;
-        for (int p = lane; p < n; p += 64) F[p] = 0;
+        const int lbytes = l16 ? 2 * n : n;
+        constexpr int LG = 4;                       // label loads in flight per lane
+        uint4 lv[LG];
+        auto load_labels = [&](int c0) {
+#pragma unroll
+            for (int i = 0; i < LG; i++) {
+                const int off = ((c0 + i) * 64 + lane) * 16;
+                lv[i] = off < lbytes ? *(const uint4 *)(lb8 + off) : make_uint4(0, 0, 0, 0);
+            }
+        };
+        load_labels(0);
+        {
+            const uint4 z = make_uint4(0, 0, 0, 0);
+            for (int k = lane; k < (n + 15) >> 4; k += 64) ((uint4 *)F)[k] = z;
+            for (int k = lane; k < ((K + 1) * RS + 3) >> 2; k += 64) ((uint4 *)rec)[k] = z;
+        }
         wave_sync();
         for (int t = lane; t < K; t += 64) {
             const int et = ends[t];
-            rec[(t + 1) * RS] = et;
+            rec[(t + 1) * RS] = et * VB;
             if (t + 1 < K) F[et] = 1;
         }
         wave_sync();
         {
-            int carry = 0;
-#pragma unroll 4
-            for (int p0 = 0; p0 < n; p0 += 64) {
-                const int p = p0 + lane;
-                const int lab = p < n ? (l16 ? (int)lb16[p] : (int)lb8[p]) : 0;
-                const bool f = p < n && F[p] != 0;
-                const uint64_t bal = __ballot(f);
-                const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
-                                      __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-                if (p < n) atomicAdd(&rec[(carry + below + (f ? 1 : 0) + 1) * RS + 1 + lab], 1);
-                carry += __popcll(bal);
-            }
+            // chunk c of the label row: 1 KiB, 16 bytes per lane (PPL points)
+            auto count_chunk = [&](auto ppl, int c, const uint4 &lab4, int &carry) {
+                constexpr int PPL = decltype(ppl)::value;
+                const int p0 = (c * 64 + lane) * PPL;
+                uint32_t fw[PPL / 4];
+                if (p0 < n) {
+                    if constexpr (PPL == 16) {
+                        const uint4 f = *(const uint4 *)(F + p0);
+                        fw[0] = f.x; fw[1] = f.y; fw[2] = f.z; fw[3] = f.w;
+                    } else {
+                        const uint2 f = *(const uint2 *)(F + p0);
+                        fw[0] = f.x; fw[1] = f.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int w = 0; w < PPL / 4; w++) fw[w] = 0;
+                }
+                int cnt = 0;   // flags are 0 or 1: a word's byte sum is its top byte times 0x01010101
+#pragma unroll
+                for (int w = 0; w < PPL / 4; w++) cnt += (int)((fw[w] * 0x01010101u) >> 24);
+                const int incl = wave_incl_scan(cnt, lane);
+                int sc = carry + incl - cnt;            // flags before this lane's first point
+                const uint32_t lw[4] = {lab4.x, lab4.y, lab4.z, lab4.w};
+#pragma unroll
+                for (int k = 0; k < PPL; k++) {
+                    sc += (int)((fw[k >> 2] >> (8 * (k & 3))) & 1u);
+                    const int lab = PPL == 16 ? (int)((lw[k >> 2] >> (8 * (k & 3))) & 0xffu)
+                                              : (int)((lw[k >> 1] >> (16 * (k & 1))) & 0xffffu);
+                    if (p0 + k < n) atomicAdd(&rec[(sc + 1) * RS + 1 + lab], VB);
+                }
+                carry += __builtin_amdgcn_readlane(incl, 63);
+            };
+            auto count_all = [&](auto ppl) {
+                int carry = 0;
+                const int nch = (lbytes + 1023) >> 10;
+                for (int c0 = 0; c0 < nch; c0 += LG) {
+                    if (c0 > 0) load_labels(c0);
+#pragma unroll
+                    for (int i = 0; i < LG; i++)
+                        if (c0 + i < nch) count_chunk(ppl, c0 + i, lv[i], carry);
+                }
+            };
+            if (l16) count_all(std::integral_constant<int, 8>());
+            else count_all(std::integral_constant<int, 16>());
         }
         wave_sync();
         if (yh >= 8) {
@@ -247,8 +303,8 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
         // column cost h(s,t) with both records read from LDS (any row count)
         auto hcost = [&](int s, int t) -> V {
             const int *rs = rec + s * RS, *rt = rec + t * RS;
-            V acc = L[rt[0] - rs[0]];
-            for (int r = 0; r < yh; r++) acc -= L[rt[1 + r] - rs[1 + r]];
+            V acc = LB(rt[0] - rs[0]);
+            for (int r = 0; r < yh; r++) acc -= LB(rt[1 + r] - rs[1 + r]);
             return acc;
         };
 
@@ -267,16 +323,16 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
                     tt[j] = c0 + 64 * j + lane + 1;
                     const int tc = tt[j] <= K ? tt[j] : K;
                     const int *rt = rec + tc * RS;
-                    et[j] = rt[0];
-                    V h0 = L[et[j]];
+                    et[j] = rt[0] + lbase;
+                    V h0 = LA(et[j]);
                     if constexpr (YR > 0) {
 #pragma unroll
                         for (int r = 0; r < YR; r++) {
-                            Nt[j][r] = rt[1 + r];
-                            h0 -= L[Nt[j][r]];
+                            Nt[j][r] = rt[1 + r] + lbase;
+                            h0 -= LA(Nt[j][r]);
                         }
                     } else {
-                        for (int r = 0; r < yh; r++) h0 -= L[rt[1 + r]];
+                        for (int r = 0; r < yh; r++) h0 -= LB(rt[1 + r]);
                     }
                     gprev[j] = l0 == 2 ? h0 : G[(size_t)(l0 - 1) * KS + tc];
 #pragma unroll
@@ -287,13 +343,13 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
                     const int *rs = rec + s * RS;
                     const int es = rs[0];
 #pragma unroll
-                    for (int j = 0; j < T; j++) out[j] = L[et[j] - es];
+                    for (int j = 0; j < T; j++) out[j] = LA(et[j] - es);
                     if constexpr (YR > 0) {
 #pragma unroll
                         for (int r = 0; r < YR; r++) {
                             const int nsr = rs[1 + r];
 #pragma unroll
-                            for (int j = 0; j < T; j++) out[j] -= L[Nt[j][r] - nsr];
+                            for (int j = 0; j < T; j++) out[j] -= LA(Nt[j][r] - nsr);
                         }
                     } else {
 #pragma unroll
@@ -413,8 +469,12 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
         for (int d = 32; d > 0; d >>= 1) best = DV::mn(best, (V)__shfl_xor(best, d, 64));
 
         // ---- I_l = (L[n] - sum_r L[q_r] - G_l(K)) / n in FP64, normalised by ln min(l, yhat) ----
+        // H(Q) term: the rows' q ln q summed over lanes (a butterfly, so every
+        // lane holds the same sum)
         double sq = 0.0;
-        for (int r = 0; r < yh; r++) sq += a.xlogx[rec[K * RS + 1 + r]];
+        for (int r = lane; r < yh; r += 64) sq += a.xlogx[rec[K * RS + 1 + r] / VB];
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) sq += __shfl_xor(sq, d, 64);
         const double Ln = a.xlogx[n];
         for (int l = 2 + lane; l <= x; l += 64) {
             const V Gl = (l == x) ? best : G[(size_t)l * KS + K];
