@@ -33,10 +33,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MIC pairs/s at n=1340, α=0.6, c=15 (FP32+FP64 vs FP64 GPU) + max |ΔMIC|"
 
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz -- one non-packed VALU operation per lane
-# per clock (FP64 add/min and 32-bit integer add/min issue at this rate; the FP64
-# FMA peak of 78.6 TFLOP/s counts an FMA as 2).
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# VALU peaks of MI355X in algorithmic lane-operations per second (256 CUs x 4
+# SIMDs at 2.4 GHz).  FP64 add and min issue 16 lanes per SIMD per clock:
+# 39.3 T/s (the 78.6 TFLOP/s FP64 figure counts an FMA as 2).  In the 32-bit
+# form the cell update is two 32-bit adds with VGPR operands, which issue 32
+# lanes per SIMD per clock (the rate behind the 157.3 TFLOP/s FP32 figure), and
+# one v_min3_u32 that takes two minima at 16 lanes per clock: four operations
+# per lane in 8 SIMD-cycles for a wave of 64, i.e. 78.6 T/s.  The issue rates
+# are measured by paper_1208_4271_amd/calib/valu_rate.hip.
+VALU_PEAK_FP64_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+VALU_PEAK_U32_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 
 
 def parse():
@@ -121,12 +127,15 @@ def measured_traffic():
 
 
 def roofline_of(prof, kernel):
+    """The DP against the VALU peak of its form: the 32-bit peak when any row
+    count ran in 32 bits (an upper bound for a mixed call), else FP64."""
     alg_ops = 2.0 * prof["dp_cells"] + 2.0 * prof["h_terms"]
     dp_s = prof["dp_ms"] / 1e3
     achieved = alg_ops / dp_s / 1e12 if dp_s > 0 else 0.0
+    peak = VALU_PEAK_U32_TOPS if prof["dp32_classes"] > 0 else VALU_PEAK_FP64_TOPS
     return {
-        "bound": "alu", "achieved": round(achieved, 4), "peak": round(VALU_PEAK_TOPS, 4),
-        "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 5), "traffic": None,
+        "bound": "alu", "achieved": round(achieved, 4), "peak": round(peak, 4),
+        "unit": "TOP/s", "frac": round(achieved / peak, 5), "traffic": None,
         "kernel": kernel, "launches": prof["dp_launches"],
         "avg_launch_ms": round(prof["dp_ms"] / max(prof["dp_launches"], 1), 3),
         "alg_ops": alg_ops, "dp_cells": prof["dp_cells"], "h_evals": prof["h_evals"],
