@@ -33,7 +33,9 @@ EXTRA = {s: ["-fno-honor-nans"] for s in SOURCES if s.startswith("micx_dp")}
 
 
 # The DP kernels must not spill: their resource usage is read back from the
-# compiler and the build fails if any of them uses private (scratch) memory.
+# compiler and the build fails if any of them uses private (scratch) memory or
+# accumulation registers (AGPRs, where the compiler parks VGPRs it cannot fit;
+# such spills also push a kernel past its occupancy step).
 USAGE_FLAG = "-Rpass-analysis=kernel-resource-usage"
 _DP_NAME = re.compile(r"k_dpI([dj])Li(\d+)ELi(\d+)ELi(\d+)E")
 
@@ -68,7 +70,8 @@ def _compile(src, obj, verbose, defines=(), check_spills=True, device_only=False
         raise RuntimeError("hipcc failed on %s:\n%s%s" % (src, res.stdout, res.stderr))
     usage = dp_resource_usage(res.stderr) if dp else {}
     if check_spills:
-        bad = sorted(k for k, u in usage.items() if u.get("ScratchSize", 0) or u.get("VGPRs Spill", 0))
+        bad = sorted(k for k, u in usage.items()
+                     if u.get("ScratchSize", 0) or u.get("VGPRs Spill", 0) or u.get("AGPRs", 0))
         if bad:
             raise RuntimeError("DP kernels of %s spill registers (fx, NL, YR, T): %s" % (src, bad))
     return usage

@@ -164,6 +164,8 @@ int cached_occupancy(dp_kernel_t k, int threads, int lds) {
 // set-up flags) and the count records (rec_bytes).  SB and the wavefronts
 // per workgroup shrink until two workgroups fit a CU (one at the least).
 void dp_fit_lds(DpPlan &p, int nmax, size_t rec_bytes, int cus) {
+    // fewer targets per lane where the shape is not built (see dp_built)
+    while (p.T > 1 && !pick(p.fx, p.NL, p.YR, p.T, p.groups)) p.T--;
     const int vb = p.fx ? 4 : 8;
     const int PK = 16 / vb;
     const int NLP = (p.NL + PK - 1) / PK * PK;

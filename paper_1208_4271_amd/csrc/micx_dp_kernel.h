@@ -190,82 +190,112 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
         }
 
         // ---- cumulative counts (item 10a); rows beyond yhat stay 0 ----
-        // Every lane takes a run of consecutive points: one 16-byte load of
-        // row labels (stored in column order by the partition kernel; the
-        // first loads are issued before the table is cleared).  A flag per
-        // superclump start and a wavefront prefix sum of the lanes' flag
-        // counts give each point its superclump; LDS atomics count.
+        // A flag per superclump start gives each point its superclump; the
+        // point's row label (stored in column order by the partition kernel)
+        // selects the count, and LDS atomics count.
         unsigned char *F = (unsigned char *)stage;
-        const int lbytes = l16 ? 2 * n : n;
-        constexpr int LG = 4;                       // label loads in flight per lane
-        uint4 lv[LG];
-        auto load_labels = [&](int c0) {
+        if constexpr (NL < 20) {
+            // Every lane takes a run of consecutive points: one 16-byte load
+            // of labels (the first loads are issued before the table is
+            // cleared); a wavefront prefix sum of the lanes' flag counts
+            // gives each point its superclump.  (Passes of 20 layers or more
+            // keep the scan below: this one's registers would lower their
+            // occupancy, and the scan is a few percent of their time.)
+            const int lbytes = l16 ? 2 * n : n;
+            constexpr int LG = 4;                       // label loads in flight per lane
+            uint4 lv[LG];
+            auto load_labels = [&](int c0) {
 #pragma unroll
-            for (int i = 0; i < LG; i++) {
-                const int off = ((c0 + i) * 64 + lane) * 16;
-                lv[i] = off < lbytes ? *(const uint4 *)(lb8 + off) : make_uint4(0, 0, 0, 0);
+                for (int i = 0; i < LG; i++) {
+                    const int off = ((c0 + i) * 64 + lane) * 16;
+                    lv[i] = off < lbytes ? *(const uint4 *)(lb8 + off) : make_uint4(0, 0, 0, 0);
+                }
+            };
+            load_labels(0);
+            {
+                const uint4 z = make_uint4(0, 0, 0, 0);
+                for (int k = lane; k < (n + 15) >> 4; k += 64) ((uint4 *)F)[k] = z;
+                for (int k = lane; k < ((K + 1) * RS + 3) >> 2; k += 64) ((uint4 *)rec)[k] = z;
             }
-        };
-        load_labels(0);
-        {
-            const uint4 z = make_uint4(0, 0, 0, 0);
-            for (int k = lane; k < (n + 15) >> 4; k += 64) ((uint4 *)F)[k] = z;
-            for (int k = lane; k < ((K + 1) * RS + 3) >> 2; k += 64) ((uint4 *)rec)[k] = z;
-        }
-        wave_sync();
-        for (int t = lane; t < K; t += 64) {
-            const int et = ends[t];
-            rec[(t + 1) * RS] = et * VB;
-            if (t + 1 < K) F[et] = 1;
-        }
-        wave_sync();
-        {
-            // chunk c of the label row: 1 KiB, 16 bytes per lane (PPL points)
-            auto count_chunk = [&](auto ppl, int c, const uint4 &lab4, int &carry) {
-                constexpr int PPL = decltype(ppl)::value;
-                const int p0 = (c * 64 + lane) * PPL;
-                uint32_t fw[PPL / 4];
-                if (p0 < n) {
-                    if constexpr (PPL == 16) {
-                        const uint4 f = *(const uint4 *)(F + p0);
-                        fw[0] = f.x; fw[1] = f.y; fw[2] = f.z; fw[3] = f.w;
+            wave_sync();
+            for (int t = lane; t < K; t += 64) {
+                const int et = ends[t];
+                rec[(t + 1) * RS] = et * VB;
+                if (t + 1 < K) F[et] = 1;
+            }
+            wave_sync();
+            {
+                // chunk c of the label row: 1 KiB, 16 bytes per lane (PPL points)
+                auto count_chunk = [&](auto ppl, int c, const uint4 &lab4, int &carry) {
+                    constexpr int PPL = decltype(ppl)::value;
+                    const int p0 = (c * 64 + lane) * PPL;
+                    uint32_t fw[PPL / 4];
+                    if (p0 < n) {
+                        if constexpr (PPL == 16) {
+                            const uint4 f = *(const uint4 *)(F + p0);
+                            fw[0] = f.x; fw[1] = f.y; fw[2] = f.z; fw[3] = f.w;
+                        } else {
+                            const uint2 f = *(const uint2 *)(F + p0);
+                            fw[0] = f.x; fw[1] = f.y;
+                        }
                     } else {
-                        const uint2 f = *(const uint2 *)(F + p0);
-                        fw[0] = f.x; fw[1] = f.y;
+#pragma unroll
+                        for (int w = 0; w < PPL / 4; w++) fw[w] = 0;
                     }
-                } else {
+                    int cnt = 0;   // flags are 0 or 1: a word's byte sum is its top byte times 0x01010101
 #pragma unroll
-                    for (int w = 0; w < PPL / 4; w++) fw[w] = 0;
-                }
-                int cnt = 0;   // flags are 0 or 1: a word's byte sum is its top byte times 0x01010101
+                    for (int w = 0; w < PPL / 4; w++) cnt += (int)((fw[w] * 0x01010101u) >> 24);
+                    const int incl = wave_incl_scan(cnt, lane);
+                    int sc = carry + incl - cnt;            // flags before this lane's first point
+                    const uint32_t lw[4] = {lab4.x, lab4.y, lab4.z, lab4.w};
 #pragma unroll
-                for (int w = 0; w < PPL / 4; w++) cnt += (int)((fw[w] * 0x01010101u) >> 24);
-                const int incl = wave_incl_scan(cnt, lane);
-                int sc = carry + incl - cnt;            // flags before this lane's first point
-                const uint32_t lw[4] = {lab4.x, lab4.y, lab4.z, lab4.w};
+                    for (int k = 0; k < PPL; k++) {
+                        sc += (int)((fw[k >> 2] >> (8 * (k & 3))) & 1u);
+                        const int lab = PPL == 16 ? (int)((lw[k >> 2] >> (8 * (k & 3))) & 0xffu)
+                                                  : (int)((lw[k >> 1] >> (16 * (k & 1))) & 0xffffu);
+                        if (p0 + k < n) atomicAdd(&rec[(sc + 1) * RS + 1 + lab], VB);
+                    }
+                    carry += __builtin_amdgcn_readlane(incl, 63);
+                };
+                auto count_all = [&](auto ppl) {
+                    int carry = 0;
+                    const int nch = (lbytes + 1023) >> 10;
+                    for (int c0 = 0; c0 < nch; c0 += LG) {
+                        if (c0 > 0) load_labels(c0);
 #pragma unroll
-                for (int k = 0; k < PPL; k++) {
-                    sc += (int)((fw[k >> 2] >> (8 * (k & 3))) & 1u);
-                    const int lab = PPL == 16 ? (int)((lw[k >> 2] >> (8 * (k & 3))) & 0xffu)
-                                              : (int)((lw[k >> 1] >> (16 * (k & 1))) & 0xffffu);
-                    if (p0 + k < n) atomicAdd(&rec[(sc + 1) * RS + 1 + lab], VB);
-                }
-                carry += __builtin_amdgcn_readlane(incl, 63);
-            };
-            auto count_all = [&](auto ppl) {
-                int carry = 0;
-                const int nch = (lbytes + 1023) >> 10;
-                for (int c0 = 0; c0 < nch; c0 += LG) {
-                    if (c0 > 0) load_labels(c0);
-#pragma unroll
-                    for (int i = 0; i < LG; i++)
-                        if (c0 + i < nch) count_chunk(ppl, c0 + i, lv[i], carry);
-                }
-            };
-            if (l16) count_all(std::integral_constant<int, 8>());
-            else count_all(std::integral_constant<int, 16>());
+                        for (int i = 0; i < LG; i++)
+                            if (c0 + i < nch) count_chunk(ppl, c0 + i, lv[i], carry);
+                    }
+                };
+                if (l16) count_all(std::integral_constant<int, 8>());
+                else count_all(std::integral_constant<int, 16>());
+            }
+            wave_sync();
+        } else {
+            // one point per lane and step: a ballot of the flags
+            const uint16_t *lb16 = (const uint16_t *)lb8;
+            for (int k = lane; k < (K + 1) * RS; k += 64) rec[k] = 0;
+            for (int p = lane; p < n; p += 64) F[p] = 0;
+            wave_sync();
+            for (int t = lane; t < K; t += 64) {
+                const int et = ends[t];
+                rec[(t + 1) * RS] = et * VB;
+                if (t + 1 < K) F[et] = 1;
+            }
+            wave_sync();
+            int carry = 0;
+            for (int p0 = 0; p0 < n; p0 += 64) {
+                const int p = p0 + lane;
+                const int lab = p < n ? (l16 ? (int)lb16[p] : (int)lb8[p]) : 0;
+                const bool f = p < n && F[p] != 0;
+                const uint64_t bal = __ballot(f);
+                const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                      __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+                if (p < n) atomicAdd(&rec[(carry + below + (f ? 1 : 0) + 1) * RS + 1 + lab], VB);
+                carry += __popcll(bal);
+            }
+            wave_sync();
         }
-        wave_sync();
         if (yh >= 8) {
             // one row per lane, eight superclumps per step (loads issued together)
             for (int r = lane; r < yh; r += 64) {
