@@ -58,6 +58,13 @@ def dp_resource_usage(text):
     return out
 
 
+def spilling(usage):
+    """DP instances (fx, NL, YR, T) whose resource usage shows a spill:
+    scratch memory, spilled VGPRs or accumulation registers."""
+    return sorted(k for k, u in usage.items()
+                  if u.get("ScratchSize", 0) or u.get("VGPRs Spill", 0) or u.get("AGPRs", 0))
+
+
 def _compile(src, obj, verbose, defines=(), check_spills=True, device_only=False):
     dp = src.startswith("micx_dp_")
     cmd = [HIPCC] + flags() + EXTRA.get(src, []) + list(defines) + ([USAGE_FLAG] if dp else [])
@@ -70,8 +77,7 @@ def _compile(src, obj, verbose, defines=(), check_spills=True, device_only=False
         raise RuntimeError("hipcc failed on %s:\n%s%s" % (src, res.stdout, res.stderr))
     usage = dp_resource_usage(res.stderr) if dp else {}
     if check_spills:
-        bad = sorted(k for k, u in usage.items()
-                     if u.get("ScratchSize", 0) or u.get("VGPRs Spill", 0) or u.get("AGPRs", 0))
+        bad = spilling(usage)
         if bad:
             raise RuntimeError("DP kernels of %s spill registers (fx, NL, YR, T): %s" % (src, bad))
     return usage
@@ -97,6 +103,22 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
         raise RuntimeError("link failed:\n" + res.stdout + res.stderr)
     os.replace(tmp, LIBOUT)
     return LIBOUT
+
+
+CALIB_SRC = os.path.join(HERE, "calib", "valu_rate.hip")
+CALIB_BIN = os.path.join(HERE, "calib", "valu_rate")
+
+
+def build_calib(verbose: bool = False) -> str:
+    """Compile the VALU issue-rate program (a standalone executable)."""
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-O3", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", "-o", CALIB_BIN, CALIB_SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed on %s:\n%s%s" % (CALIB_SRC, res.stdout, res.stderr))
+    return CALIB_BIN
 
 
 if __name__ == "__main__":

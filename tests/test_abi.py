@@ -83,3 +83,23 @@ def test_build_reads_dp_resource_usage():
     assert set(u) == {(1, 36, 2, 2), (0, 10, 5, 1)}
     assert u[(1, 36, 2, 2)]["ScratchSize"] == 0 and u[(1, 36, 2, 2)]["VGPRs"] == 180
     assert u[(0, 10, 5, 1)]["ScratchSize"] == 152 and u[(0, 10, 5, 1)]["VGPRs Spill"] == 37
+    assert _build.spilling(u) == [(0, 10, 5, 1)]
+
+
+def test_build_flags_agpr_spills():
+    # VGPRs parked in accumulation registers count as a spill too
+    from paper_1208_4271_amd import _build
+    text = "\n".join([
+        "x.h:1:1: remark: Function Name: _ZN4micx4k_dpIdLi36ELi2ELi2ELb1EEEvNS_6DpArgsE [-Rpass-analysis]",
+        "x.h:1:1: remark:     VGPRs: 256 [-Rpass-analysis]",
+        "x.h:1:1: remark:     AGPRs: 4 [-Rpass-analysis]",
+        "x.h:1:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis]",
+        "x.h:1:1: remark:     VGPRs Spill: 0 [-Rpass-analysis]",
+        "x.h:1:1: remark: Function Name: _ZN4micx4k_dpIjLi36ELi2ELi3ELb0EEEvNS_6DpArgsE [-Rpass-analysis]",
+        "x.h:1:1: remark:     VGPRs: 226 [-Rpass-analysis]",
+        "x.h:1:1: remark:     AGPRs: 0 [-Rpass-analysis]",
+        "x.h:1:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis]",
+    ])
+    u = _build.dp_resource_usage(text)
+    assert u[(0, 36, 2, 2)]["AGPRs"] == 4
+    assert _build.spilling(u) == [(0, 36, 2, 2)]
