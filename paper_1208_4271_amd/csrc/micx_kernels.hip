@@ -44,10 +44,19 @@ __device__ __forceinline__ uint64_t order_key(double d) {
 // 2a + s >= 2 floor(R/L).  (2a + s) <= 3n and L <= n, so 32 bits hold
 // the products for n <= MICX_MAX_N; L >= 1 always (the last row never
 // closes).
+// DINT: the integer-cast target row size (MICX_COMPAT_DESIRED_INT) as a
+// compile-time choice, so the default test carries no division.
+template <bool DINT>
+__device__ __forceinline__ bool closes_row_t(int a, int s, int R, int L, bool strict) {
+    const int lhs = DINT ? 2 * a + s : (2 * a + s) * L;
+    const int rhs = DINT ? 2 * (R / L) : 2 * R;
+    return strict ? lhs > rhs : lhs >= rhs;
+}
+
 __device__ __forceinline__ bool closes_row(int a, int s, int R, int L, int compat) {
-    const int lhs = (compat & MICX_COMPAT_DESIRED_INT) ? 2 * a + s : (2 * a + s) * L;
-    const int rhs = (compat & MICX_COMPAT_DESIRED_INT) ? 2 * (R / L) : 2 * R;
-    return (compat & MICX_COMPAT_TIE_STRICT) ? lhs > rhs : lhs >= rhs;
+    const bool strict = (compat & MICX_COMPAT_TIE_STRICT) != 0;
+    return (compat & MICX_COMPAT_DESIRED_INT) ? closes_row_t<true>(a, s, R, L, strict)
+                                               : closes_row_t<false>(a, s, R, L, strict);
 }
 
 // ------------------------------------------------------------------ k_xlogx
@@ -207,7 +216,7 @@ struct PartArgs {
 // writes of neighbouring lanes fall in different banks.
 constexpr int PART_TILE = 144;
 
-template <bool L16>
+template <bool L16, bool DINT, bool STRICT>
 __device__ __forceinline__ void part_body(const PartArgs &a, int w, unsigned char *tile) {
     const int nyb = (a.NY + 63) / 64;
     const int yb = w % nyb, po = w / nyb;
@@ -245,7 +254,7 @@ __device__ __forceinline__ void part_body(const PartArgs &a, int w, unsigned cha
         const int size = ce - cstart;
         k += e ? 1 : 0;
         if (e & act & (k <= kh)) cb[k - 1] = ce;
-        const bool sup = e & (sa != 0) & closes_row(sa, size, sR, sL, a.compat);   // no short-circuit
+        const bool sup = e & (sa != 0) & closes_row_t<DINT>(sa, size, sR, sL, STRICT);   // no short-circuit
         if (sup & act) sb[sr] = sP0 + sa;
         sr += sup ? 1 : 0;
         sP0 += sup ? sa : 0;
@@ -331,10 +340,25 @@ __device__ __forceinline__ void part_body(const PartArgs &a, int w, unsigned cha
     }
 }
 
+// the compatibility variants of the row-closing test as compile-time choices
+// (a uniform branch per launch; the default test has no select or division)
+template <bool L16>
+__device__ __forceinline__ void part_dispatch(const PartArgs &a, int w, unsigned char *tile) {
+    const bool dint = (a.compat & MICX_COMPAT_DESIRED_INT) != 0;
+    const bool strict = (a.compat & MICX_COMPAT_TIE_STRICT) != 0;
+    if (dint) {
+        if (strict) part_body<L16, true, true>(a, w, tile);
+        else part_body<L16, true, false>(a, w, tile);
+    } else {
+        if (strict) part_body<L16, false, true>(a, w, tile);
+        else part_body<L16, false, false>(a, w, tile);
+    }
+}
+
 template <bool L16>
 __global__ __launch_bounds__(64) void k_part(PartArgs a) {
     __shared__ __align__(16) unsigned char tile[64 * PART_TILE];
-    part_body<L16>(a, blockIdx.x, tile);
+    part_dispatch<L16>(a, blockIdx.x, tile);
 }
 
 // ------------------------------------------------------------------ k_stats
@@ -586,8 +610,8 @@ __global__ __launch_bounds__(64) void k_part_g(const GroupDev *G, const int2 *ma
     a.khat = g.khat; a.koff = g.koff;
     a.cbuf = g.cbuf; a.sbuf = g.sbuf; a.K = g.K; a.k = g.k; a.src = g.src;
     a.lab = g.lab; a.lab_row = g.lab_row; a.compat = g.compat;
-    if (g.lab16) part_body<true>(a, m.y, tile);
-    else part_body<false>(a, m.y, tile);
+    if (g.lab16) part_dispatch<true>(a, m.y, tile);
+    else part_dispatch<false>(a, m.y, tile);
 }
 
 // 64 pairs per block: map[b].y is the group's first pair of the block
