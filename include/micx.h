@@ -156,6 +156,28 @@ int micx_pairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n,
                const int32_t *pairs_host, int64_t npairs,
                double alpha, double c, int mode, double *out_dev, void *stream);
 
+/* Pearson's correlation coefficient rho and the non-linearity index
+ * MIC - rho^2 of pairs of rows of X: the two statistics the paper's engine
+ * reports beside the four MINE statistics (Sec. 2 and Fig. 1; the
+ * Performance experiments of the supplement time all six together).
+ * X_dev: DEVICE pointer, m x n row-major, dtype MICX_F32/F64/I32, as for
+ *        micx_allpairs; m >= 2, n >= 2.
+ * pairs_host: HOST array of npairs (i, j) int32 pairs (0 <= i, j < m), or
+ *        NULL for all pairs i < j in micx_allpairs order, with npairs then
+ *        equal to m(m-1)/2 (at most 2^31 - 1 pairs).
+ * stats_dev: DEVICE pointer to the 4-double MINE records of the same pairs in
+ *        the same order (micx_allpairs or micx_pairs output), or NULL.
+ * out_dev: DEVICE pointer to npairs * 2 doubles, pair k at 2k as
+ *        (rho, MIC - rho^2).  rho is NaN when either variable is constant; the
+ *        index is NaN when rho is NaN or stats_dev is NULL.
+ * FP64: per variable the mean, then the centred sum of squares; per pair one
+ * centred dot product, rho clamped to [-1, 1].  Errors: MICX_EINVAL (null
+ * pointer, bad sizes, dtype or pair index, npairs mismatch), MICX_EDEVICE.
+ * The call returns after the stream has finished. */
+int micx_pearson(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n,
+                 const int32_t *pairs_host, int64_t npairs, const double *stats_dev,
+                 double *out_dev, void *stream);
+
 /* One independent pair of a batch: both variables are n consecutive
  * elements of the packed data buffer, at element offsets off_x and off_y;
  * alpha and c are the pair's own parameters. */

@@ -30,6 +30,8 @@ NORM_BY_Y = 8
 BOUND_STRICT = 16
 KHAT_PLUS1 = 32
 
+from .pearson import nonlinearity, pearson  # noqa: E402,F401  (Pearson's rho, MIC - rho^2)
+
 _lib = None
 
 

@@ -44,6 +44,7 @@ EXPORTS = (
     "micx_compute_score", "micx_mic", "micx_mas", "micx_mev", "micx_mcn", "micx_free_score",
     "micx_allpairs", "micx_pairs", "micx_batch", "micx_debug_item", "micx_strerror",
     "micx_set_profiling", "micx_get_profile", "micx_set_dp32_tolerance", "micx_set_compat",
+    "micx_pearson",
 )
 
 
@@ -112,6 +113,9 @@ def load_library():
     lib.micx_pairs.restype = ctypes.c_int
     lib.micx_batch.argtypes = [vp, vp, ctypes.c_int, P(_PairDesc), ctypes.c_int64, ctypes.c_int, vp, vp]
     lib.micx_batch.restype = ctypes.c_int
+    lib.micx_pearson.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_int32),
+                                 ctypes.c_int64, vp, vp, vp]
+    lib.micx_pearson.restype = ctypes.c_int
     lib.micx_debug_item.argtypes = [vp, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_int, ctypes.c_int, ip, ip, ip, ip, ip]
     lib.micx_debug_item.restype = ctypes.c_int
@@ -241,6 +245,40 @@ def pairs(X, pair_list, alpha: float = 0.6, c: float = 15.0, mode: int = MODE_FP
                                    float(alpha), float(c), int(mode),
                                    ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
     _check(rc, "micx_pairs")
+    return out
+
+
+def pearson(X, pair_list=None, stats=None, out=None, stream=None):
+    """Pearson's rho and the non-linearity index MIC - rho^2 (see micx_pearson)
+    for the listed pairs (i, j) of rows of a CUDA tensor X, or for all pairs
+    i < j in allpairs order when pair_list is None.  stats: the (npairs, 4)
+    float64 CUDA output of allpairs/pairs for the same pairs, or None.
+    Returns an (npairs, 2) float64 CUDA tensor of (rho, MIC - rho^2)."""
+    import torch
+    if not X.is_cuda or X.dim() != 2:
+        raise ValueError("X must be a 2-D CUDA tensor")
+    X = X.contiguous()
+    dt = _DTYPES.get(str(X.dtype))
+    if dt is None:
+        raise ValueError("X dtype must be float32, float64 or int32")
+    m, n = X.shape
+    if pair_list is None:
+        pl, npairs = None, m * (m - 1) // 2
+    else:
+        pl = np.ascontiguousarray(np.asarray(pair_list, dtype=np.int32).reshape(-1, 2))
+        npairs = len(pl)
+    if stats is not None:
+        if (not stats.is_cuda or stats.dtype != torch.float64 or tuple(stats.shape) != (npairs, 4)
+                or not stats.is_contiguous()):
+            raise ValueError("stats must be a contiguous (npairs, 4) float64 CUDA tensor")
+    if out is None:
+        out = torch.empty((npairs, 2), dtype=torch.float64, device=X.device)
+    pp = pl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if pl is not None else None
+    rc = load_library().micx_pearson(context(X.device.index or 0), ctypes.c_void_p(X.data_ptr()), dt,
+                                     m, n, pp, npairs,
+                                     ctypes.c_void_p(stats.data_ptr()) if stats is not None else None,
+                                     ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    _check(rc, "micx_pearson")
     return out
 
 

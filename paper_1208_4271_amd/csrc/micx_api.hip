@@ -55,6 +55,7 @@ struct micx_ctx {
     DevBuf geo;        // xcnt | khat | koff | aoff
     DevBuf cbuf, sbuf, Kb, kb, srcb, A, scratch, pairs, input, out, dense;
     DevBuf counters, fxtab, lab;
+    DevBuf moments;                    // micx_pearson: per-variable mean and 1/norm
     DevBuf bdata, boffs, bout, bidx;   // micx_batch: gathered variables, offsets, staged results
     double dp32_tol = 5e-7;   // half of the 1e-6 agreement required of the scores
     int compat = 0;           // MICX_COMPAT_* flags
@@ -407,6 +408,36 @@ extern "C" int micx_allpairs(micx_ctx *ctx, const void *X_dev, int dtype, int m,
     const int64_t npairs = (int64_t)m * (m - 1) / 2;
     RETCHK(run_pairs(ctx, rt, et, hg.g, nullptr, npairs, m, mode, out_dev, nullptr, nullptr,
                      nullptr, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MICX_OK;
+}
+
+extern "C" int micx_pearson(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n,
+                            const int32_t *pairs_host, int64_t npairs, const double *stats_dev,
+                            double *out_dev, void *stream) {
+    if (!ctx || !X_dev || !out_dev || m < 2 || n < 2 || npairs < 1) return MICX_EINVAL;
+    if (dtype != MICX_F32 && dtype != MICX_F64 && dtype != MICX_I32) return MICX_EINVAL;
+    if (npairs > INT32_MAX) return MICX_EINVAL;
+    if (!pairs_host && npairs != (int64_t)m * (m - 1) / 2) return MICX_EINVAL;
+    if (pairs_host) {
+        for (int64_t k = 0; k < 2 * npairs; k++)
+            if (pairs_host[k] < 0 || pairs_host[k] >= m) return MICX_EINVAL;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    PairSource ps;
+    ps.pairs = nullptr;
+    ps.p0 = 0;
+    ps.m = m;
+    if (pairs_host) {
+        RETCHK(ctx->pairs.ensure((size_t)npairs * 2 * sizeof(int32_t)));
+        HIPCHK(hipMemcpyAsync(ctx->pairs.p, pairs_host, (size_t)npairs * 2 * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s));
+        ps.pairs = ctx->pairs.as<int32_t>();
+    }
+    RETCHK(ctx->moments.ensure((size_t)2 * m * sizeof(double)));
+    double *mean = ctx->moments.as<double>();
+    HIPCHK(launch_pearson(X_dev, dtype, m, n, ps, (int)npairs, mean, mean + m, stats_dev, out_dev, s));
     HIPCHK(hipStreamSynchronize(s));
     return MICX_OK;
 }

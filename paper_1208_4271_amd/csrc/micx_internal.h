@@ -123,6 +123,8 @@ struct PairSource {
     int m = 0;
 };
 
+hipError_t launch_pearson(const void *X, int dtype, int m, int n, PairSource ps, int npairs,
+                          double *mean, double *inorm, const double *stats, double *out, hipStream_t s);
 hipError_t launch_rank(const void *X, int dtype, int m, int n, RankTables &rt, int *status,
                        hipStream_t s);
 hipError_t launch_equip(const RankTables &rt, EquipTables &et, hipStream_t s);

@@ -361,6 +361,79 @@ __global__ __launch_bounds__(64) void k_part(PartArgs a) {
     part_dispatch<L16>(a, blockIdx.x, tile);
 }
 
+// ---------------------------------------------------------- k_moments/k_pearson
+// Pearson's correlation coefficient beside the MINE statistics, and the
+// non-linearity index MIC - rho^2 (the companion outputs of the paper's
+// engine; Sec. 2, Fig. 1).  FP64 throughout: per variable a mean, then the
+// centred sum of squares (two passes); per pair one centred dot product.
+
+__device__ __forceinline__ double block_sum_256(double v, double *red) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    const double t = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return t;
+}
+
+// one workgroup of 256 per variable: mean, and 1/sqrt(centred sum of squares)
+// (NaN for a constant variable)
+__global__ __launch_bounds__(256) void k_moments(const void *X, int dtype, int n, double *mean,
+                                                 double *inorm) {
+    __shared__ double red[4];
+    const int v = blockIdx.x;
+    const size_t base = (size_t)v * n;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += load_value(X, dtype, base + i);
+    const double mu = block_sum_256(s, red) / (double)n;
+    double q = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const double d = load_value(X, dtype, base + i) - mu;
+        q += d * d;
+    }
+    const double ss = block_sum_256(q, red);
+    if (threadIdx.x == 0) {
+        mean[v] = mu;
+        inorm[v] = ss > 0.0 ? 1.0 / sqrt(ss) : NAN;
+    }
+}
+
+// one wavefront per pair: rho (clamped to [-1, 1]) and, with the pair's MINE
+// record, MIC - rho^2
+__global__ __launch_bounds__(256) void k_pearson(const void *X, int dtype, int n, PairSource ps,
+                                                 int npairs, const double *mean, const double *inorm,
+                                                 const double *stats, double *out) {
+    const int lane = threadIdx.x & 63;
+    const int pl = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (pl >= npairs) return;
+    int i, j;
+    pair_of(ps, pl, i, j);
+    const double mi = mean[i], mj = mean[j];
+    const size_t bi = (size_t)i * n, bj = (size_t)j * n;
+    double d = 0.0;
+    for (int k = lane; k < n; k += 64) d += (load_value(X, dtype, bi + k) - mi) * (load_value(X, dtype, bj + k) - mj);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+    if (lane == 0) {
+        double r = d * inorm[i] * inorm[j];
+        if (!isnan(r)) r = fmin(1.0, fmax(-1.0, r));
+        out[2 * (size_t)pl] = r;
+        out[2 * (size_t)pl + 1] = stats ? stats[4 * (size_t)pl] - r * r : NAN;
+    }
+}
+
+hipError_t launch_pearson(const void *X, int dtype, int m, int n, PairSource ps, int npairs,
+                          double *mean, double *inorm, const double *stats, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_moments, dim3(m), dim3(256), 0, s, X, dtype, n, mean, inorm);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pearson, dim3((npairs + 3) / 4), dim3(256), 0, s, X, dtype, n, ps, npairs,
+                       (const double *)mean, (const double *)inorm, stats, out);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ k_stats
 // Characteristic matrix and statistics of one pair per thread.
 // M_{x,y} (x bins of the first variable, y of the second) is the larger of

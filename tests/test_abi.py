@@ -5,6 +5,7 @@ import os
 import re
 
 import numpy as np
+import pytest
 
 import oracle
 import paper_1208_4271_amd as micx
@@ -103,3 +104,25 @@ def test_build_flags_agpr_spills():
     u = _build.dp_resource_usage(text)
     assert u[(0, 36, 2, 2)]["AGPRs"] == 4
     assert _build.spilling(u) == [(0, 36, 2, 2)]
+
+
+def test_cli_reads_csv_and_modes(tmp_path):
+    # the mine-style front end: CSV parsing and pair selection (no GPU needed)
+    from paper_1208_4271_amd import cli
+    p = tmp_path / "d.csv"
+    p.write_text("gA,1,2,3,4\n5,6,7,8\ngC,0.5,0.25,0.125,1e-3\n")
+    names, X = cli.read_csv(str(p))
+    assert names == ["gA", "2", "gC"] and X.shape == (3, 4) and X[2, 3] == 1e-3
+    assert cli.pair_list(3) is None
+    assert cli.pair_list(3, master=2) == [(1, 0), (1, 2)]
+    assert cli.pair_list(3, pair=(3, 1)) == [(2, 0)]
+    with pytest.raises(ValueError):
+        cli.pair_list(3, master=4)
+    with pytest.raises(ValueError):
+        cli.pair_list(3, pair=(2, 2))
+    bad = tmp_path / "bad.csv"
+    bad.write_text("a,1,2,3\nb,1,2\n")
+    with pytest.raises(ValueError):
+        cli.read_csv(str(bad))
+    args = cli.parse(["x.csv", "-a", "0.55", "-c", "10", "-m", "3", "-o", "o.tsv"])
+    assert args.alpha == 0.55 and args.clumps == 10 and args.master == 3 and args.output == "o.tsv"

@@ -420,3 +420,86 @@ def test_compat_rejects_unknown_bits(micx):
     with pytest.raises(micx.MicxError) as e:
         micx.set_compat(64)
     assert e.value.code == micx.MICX_EINVAL
+
+
+# ------------------------------------------------ Pearson's rho, MIC - rho^2
+def test_pearson_allpairs_matches_oracle(micx):
+    import torch
+    _log("case pearson allpairs cfg2")
+    X = workloads.cfg2_matrix()            # float32, 64 x 400
+    Xd = torch.from_numpy(X).cuda()
+    stats = micx.allpairs(Xd, 0.6, 15.0)
+    got = micx.pearson(Xd, stats=stats).cpu().numpy()
+    st = stats.cpu().numpy()
+    X64 = X.astype(np.float64)
+    m = X.shape[0]
+    k = 0
+    for i in range(m):
+        for j in range(i + 1, m):
+            r = oracle.pearson(X64[i], X64[j])
+            assert abs(got[k, 0] - r) <= 1e-12, (i, j, got[k, 0], r)
+            assert abs(got[k, 1] - (st[k, 0] - got[k, 0] ** 2)) <= 1e-15
+            k += 1
+    want = oracle.allpairs(X64, 0.6, 15.0)
+    idx = np.array([oracle.nonlinearity(want[q, 0], got[q, 0]) for q in range(len(want))])
+    assert np.abs(got[:, 1] - idx).max() <= 1e-6
+
+
+def test_pearson_pairs_constant_and_int32(micx):
+    import torch
+    _log("case pearson pairs, constant variable, int32")
+    rng = np.random.default_rng(71)
+    X = rng.integers(0, 50, (5, 333)).astype(np.int32)
+    X[3] = 7                                # a constant variable
+    Xd = torch.from_numpy(X).cuda()
+    pl = [(0, 1), (3, 0), (2, 2), (4, 1)]
+    got = micx.pearson(Xd, pl).cpu().numpy()
+    for k, (i, j) in enumerate(pl):
+        r = oracle.pearson(X[i].astype(np.float64), X[j].astype(np.float64))
+        if np.isnan(r):
+            assert np.isnan(got[k, 0])
+        else:
+            assert abs(got[k, 0] - r) <= 1e-12
+        assert np.isnan(got[k, 1])          # no MINE records given
+    assert abs(got[2, 0] - 1.0) <= 1e-15
+
+
+def test_pearson_errors(micx):
+    import ctypes
+    import torch
+    X = torch.zeros((4, 20), dtype=torch.float64, device="cuda")
+    out = torch.empty((6, 2), dtype=torch.float64, device="cuda")
+    lib = micx.load_library()
+    ctx = micx.context(0)
+    # npairs must be m(m-1)/2 without a pair list
+    rc = lib.micx_pearson(ctx, ctypes.c_void_p(X.data_ptr()), 1, 4, 20, None, 5, None,
+                          ctypes.c_void_p(out.data_ptr()), None)
+    assert rc == micx.MICX_EINVAL
+    with pytest.raises(micx.MicxError):
+        micx.pearson(X, [(0, 4)])
+
+
+def test_cli_end_to_end(micx, tmp_path):
+    # the mine-style front end: all pairs and master mode against the oracle
+    # (printed with 6 decimals)
+    from paper_1208_4271_amd import cli
+    _log("case cli end to end")
+    rng = np.random.default_rng(72)
+    x = rng.uniform(0, 1, 300)
+    V = np.stack([x, np.sin(6 * x) + rng.normal(0, 0.2, 300), rng.normal(size=300), x ** 2])
+    src = tmp_path / "v.csv"
+    src.write_text("".join("v%d,%s\n" % (i, ",".join(repr(float(t)) for t in row)) for i, row in enumerate(V)))
+    for extra, ij in (([], [(i, j) for i in range(4) for j in range(i + 1, 4)]),
+                      (["-m", "2"], [(1, 0), (1, 2), (1, 3)])):
+        out = tmp_path / "o.tsv"
+        assert cli.main([str(src), "-a", "0.6", "-c", "15", "--fp64", "-o", str(out)] + extra) == 0
+        lines = out.read_text().splitlines()
+        assert lines[0] == cli.HEADER and len(lines) == 1 + len(ij)
+        for line, (i, j) in zip(lines[1:], ij):
+            f = line.split("\t")
+            assert f[:2] == ["v%d" % i, "v%d" % j]
+            w = oracle.score(V[i], V[j], 0.6, 15.0)["stats"]
+            r = oracle.pearson(V[i], V[j])
+            vals = np.array([float(t) for t in f[2:]])
+            want = np.array([w[0], w[1], w[2], w[3], r, oracle.nonlinearity(w[0], r)])
+            assert np.abs(vals - want).max() <= 1.5e-6, (i, j, vals, want)

@@ -258,3 +258,35 @@ def test_independent_data_mic_falls_with_n():
     large = np.mean([oracle.score(rng.uniform(0, 1, 1500), rng.uniform(0, 1, 1500))["stats"][0]
                      for _ in range(4)])
     assert large < small
+
+
+# ------------------------------------------------ Pearson's rho, MIC - rho^2
+def test_pearson_worked_examples():
+    # hand-computed: centred sums 4 / sqrt(5 * 5) and 1 / sqrt(2 * 2)
+    assert abs(oracle.pearson([1, 2, 3, 4], [1, 3, 2, 4]) - 0.8) <= 1e-15
+    assert abs(oracle.pearson([0, 1, 2], [0, 2, 1]) - 0.5) <= 1e-15
+
+
+def test_pearson_closed_forms():
+    rng = np.random.default_rng(41)
+    x = rng.normal(size=300)
+    y = rng.normal(size=300)
+    assert abs(oracle.pearson(x, 3.0 * x - 7.0) - 1.0) <= 1e-14
+    assert abs(oracle.pearson(x, -0.5 * x + 2.0) + 1.0) <= 1e-14
+    r = oracle.pearson(x, y)
+    assert oracle.pearson(y, x) == r
+    assert abs(oracle.pearson(2.0 * x + 1.0, -3.0 * y + 5.0) + r) <= 1e-14
+    assert np.isnan(oracle.pearson(x, np.full(300, 4.25)))
+
+
+def test_nonlinearity_index():
+    # noiseless linear data: MIC = 1 (even n) and rho = 1, so the index is 0;
+    # a monotone non-linear relation keeps MIC = 1 with rho < 1
+    x = np.arange(400, dtype=np.float64) / 400.0
+    mic_lin = oracle.score(x, 2.0 * x + 1.0)["stats"][0]
+    assert abs(oracle.nonlinearity(mic_lin, oracle.pearson(x, 2.0 * x + 1.0))) <= 1e-12
+    y = np.exp(8.0 * x)
+    mic = oracle.score(x, y)["stats"][0]
+    rho = oracle.pearson(x, y)
+    assert abs(mic - 1.0) <= 1e-12 and rho < 0.9
+    assert abs(oracle.nonlinearity(mic, rho) - (1.0 - rho * rho)) <= 1e-15
