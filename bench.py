@@ -43,6 +43,7 @@ METRIC = "MIC pairs/s at n=1340, α=0.6, c=15 (FP32+FP64 vs FP64 GPU) + max |ΔM
 # are measured by paper_1208_4271_amd/calib/valu_rate.hip.
 VALU_PEAK_FP64_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 VALU_PEAK_U32_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
+LDS_PEAK_TBPS = 256 * 128 * 2.4e9 / 1e12        # 128 bytes per clock per CU
 
 
 def parse():
@@ -133,9 +134,16 @@ def roofline_of(prof, kernel):
     dp_s = prof["dp_ms"] / 1e3
     achieved = alg_ops / dp_s / 1e12 if dp_s > 0 else 0.0
     peak = VALU_PEAK_U32_TOPS if prof["dp32_classes"] > 0 else VALU_PEAK_FP64_TOPS
+    # LDS, the co-bound: every table term is one LDS read of the table's
+    # element (4 bytes in the 32-bit form, 8 in FP64) against 128 B per clock
+    # per CU
+    lds_bytes = prof["h_terms"] * (4 if prof["dp32_classes"] > 0 else 8)
+    lds_tbps = lds_bytes / dp_s / 1e12 if dp_s > 0 else 0.0
     return {
         "bound": "alu", "achieved": round(achieved, 4), "peak": round(peak, 4),
         "unit": "TOP/s", "frac": round(achieved / peak, 5), "traffic": None,
+        "lds_table_TBps": round(lds_tbps, 3), "lds_peak_TBps": round(LDS_PEAK_TBPS, 2),
+        "lds_frac": round(lds_tbps / LDS_PEAK_TBPS, 5),
         "kernel": kernel, "launches": prof["dp_launches"],
         "avg_launch_ms": round(prof["dp_ms"] / max(prof["dp_launches"], 1), 3),
         "alg_ops": alg_ops, "dp_cells": prof["dp_cells"], "h_evals": prof["h_evals"],
@@ -294,11 +302,17 @@ def main():
         ref = oracle.allpairs(X, alpha, c, pairs=np.array(sample), nthreads=threads)
         cpu_s = time.perf_counter() - t0
         idx = [pair_index(a, b, m) for a, b in sample]
+        # one core, on the first 32 pairs of the sample (beside the paper's
+        # per-pair times of its single-threaded engine)
+        t0 = time.perf_counter()
+        oracle.allpairs(X, alpha, c, pairs=np.array(sample[:32]), nthreads=1)
+        one_s = time.perf_counter() - t0
         result["cpu_baseline"] = {
             "value": round(len(sample) / cpu_s, 3), "unit": "pairs/s", "cores": threads,
             "kind": "oracle",
             "sample": "%d pairs of this workload (all planted pairs + seeded random pairs), "
                       "FP64 oracle, %.1f s" % (len(sample), cpu_s),
+            "single_core_pairs_per_s": round(32 / one_s, 3),
         }
         result["parity"] = parity_of(results[main_form][2][idx], ref)
         for form in results:
