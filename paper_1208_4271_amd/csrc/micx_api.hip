@@ -768,7 +768,11 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
         const BatchGroup &bg = groups[g0 + i];
         const Geometry &g = lay[i].hg.g;
         for (int yi = 0; yi < g.NY; yi++) {
-            DpPlan p = dp_shape(g, bg.n, yi, mode, ctx->dp32_tol);
+            // passes of at most 24 layers: the descriptor kernels then keep two
+            // (FP64) or three (32-bit) targets per lane without spilling, which
+            // shortens the stream's largest items (measured: FP64 3.40 -> 2.95 s,
+            // DP32 2.29 -> 2.13 s on the 8,192-pair stream)
+            DpPlan p = dp_shape(g, bg.n, yi, mode, ctx->dp32_tol, 24);
             // a shared table uses the smallest scale of its bucket, at most a
             // factor 2 below the class's own: keep the bound within tolerance
             if (p.fx && 2.0 * p.bound > ctx->dp32_tol) {

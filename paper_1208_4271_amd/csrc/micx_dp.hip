@@ -75,7 +75,7 @@ __global__ void k_fxtable(int n, double scale, const double *xlogx, uint32_t *ta
 // a partition into at most l <= x columns by l(yhat+1)/2, so an entry M of
 // the class is off by at most (y+1) x / (2 S n ln 2).  Classes whose bound
 // exceeds the tolerance run in FP64.
-DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol) {
+DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol, int nl_max) {
     static const int NLS[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32, 36};
     static const int YRS[] = {2, 3, 4, 5, 6, 7, 8, 10, 12, 16, 20, 24, 32, 40};
     DpPlan p;
@@ -89,7 +89,7 @@ DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol) {
     const int nf = std::max(x - 2, 1);                 // full layers (at least one shape)
     // tuning overrides: MICX_DP_NLCAP caps the layers per pass, MICX_DP_T
     // forces the targets per lane (1 or 2)
-    const int nlcap = env_int("MICX_DP_NLCAP", 36);
+    const int nlcap = env_int("MICX_DP_NLCAP", nl_max);
     p.NL = round_up_in(std::min(nf, nlcap), NLS, 17, 36);
     p.YR = round_up_in(y, YRS, 14, 0);
     if (!have_shape(p.NL, p.YR)) p.YR = 0;

@@ -131,7 +131,8 @@ hipError_t launch_equip(const RankTables &rt, EquipTables &et, hipStream_t s);
 hipError_t launch_part(const RankTables &rt, const EquipTables &et, const Geometry &g,
                        PairSource ps, int npairs, ItemBuffers &ib, hipStream_t s);
 DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol);
-DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol);   // without the LDS split
+// without the LDS split; nl_max caps the layers per pass
+DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol, int nl_max = 36);
 bool dp_fits(const Geometry &g, int n);   // every row count's DP item fits one CU's LDS
 void dp_fit_lds(DpPlan &p, int nmax, size_t rec_bytes, int cus);
 // DP over items of several groups (see DpGroup): gitems holds 3 ints per item
