@@ -164,7 +164,7 @@ def stream_leg(micx, with_oracle):
     n <= 2000 against the oracle."""
     import torch
     import workloads
-    data, offx, offy, ns, alphas, cs = workloads.cfg5_stream()
+    data, offx, offy, ns, alphas, cs = workloads.uneven_stream()
     dd = torch.from_numpy(data).cuda()
     out = torch.empty((len(ns), 4), dtype=torch.float64, device="cuda")
     micx.batch(dd, offx, offy, ns, alphas, cs, mode=micx.MODE_DP32, out=out)
@@ -243,7 +243,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     alpha, c = 0.6, 15.0
-    X, planted = workloads.cfg3_matrix()
+    X, planted = workloads.microarray_matrix()
     X = X[: args.m]
     m, n = X.shape
     npairs = m * (m - 1) // 2

@@ -57,9 +57,9 @@ def test_strerror_covers_codes():
 
 
 def test_workloads_shapes():
-    X = workloads.cfg2_matrix()
+    X = workloads.relations_matrix()
     assert X.shape == (64, 400) and X.dtype == np.float32
-    x, y = workloads.cfg1_single_pair()
+    x, y = workloads.sine_pair()
     assert len(x) == 200 and x.dtype == np.float64
 
 

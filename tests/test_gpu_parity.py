@@ -45,9 +45,9 @@ def test_cpp_example(micx):
         assert abs(v - p) <= 5e-7 + 1e-12
 
 
-def test_cfg1_single_pair_full_matrix(micx):
-    _log("case cfg1")
-    x, y = workloads.cfg1_single_pair()
+def test_sine_pair_full_matrix(micx):
+    _log("case sine_pair")
+    x, y = workloads.sine_pair()
     _cmp_scores(micx.compute_score(x, y, 0.6, 15), oracle.score(x, y, 0.6, 15), tol=1e-10)
 
 
@@ -61,7 +61,7 @@ def test_boundary_cases(micx, name):
 
 def _integer_stage_cases():
     rng = np.random.default_rng(11)
-    cases = [("cfg1",) + workloads.cfg1_single_pair() + (0.6, 15.0)]
+    cases = [("sine_pair",) + workloads.sine_pair() + (0.6, 15.0)]
     a, b = workloads.fig2_points()
     cases.append(("fig2", a, b, 1.0, 15.0))
     n = 500
@@ -89,10 +89,10 @@ def test_integer_stages_bit_exact(micx, case):
             assert np.array_equal(g["ends"], w["ends"]), (orient, ry)
 
 
-def test_cfg2_allpairs(micx):
+def test_relations_allpairs(micx):
     import torch
-    _log("case cfg2 allpairs")
-    X = workloads.cfg2_matrix()
+    _log("case relations allpairs")
+    X = workloads.relations_matrix()
     got = micx.allpairs(torch.from_numpy(X).cuda(), 0.6, 15).cpu().numpy()
     want = oracle.allpairs(X.astype(np.float64), 0.6, 15)
     assert got.shape == want.shape
@@ -100,10 +100,10 @@ def test_cfg2_allpairs(micx):
     assert (np.abs(got[:, 3] - want[:, 3]) < 1e-9).all()
 
 
-def test_cfg3_subset_allpairs(micx):
+def test_microarray_subset_allpairs(micx):
     import torch
-    _log("case cfg3 subset")
-    X, planted = workloads.cfg3_matrix()
+    _log("case microarray subset")
+    X, planted = workloads.microarray_matrix()
     rows = sorted(set([0, 1, 2, 3, 4, 5] + [int(planted[k, 0]) for k in range(6)] +
                       [int(planted[k, 1]) for k in range(6)]))
     Xs = X[rows]
@@ -113,10 +113,10 @@ def test_cfg3_subset_allpairs(micx):
     assert (np.abs(got[:, 3] - want[:, 3]) < 1e-9).all()
 
 
-def test_cfg4_int32_pairs(micx):
+def test_counts_int32_pairs(micx):
     import torch
-    _log("case cfg4 int32 subset")
-    C = workloads.cfg4_matrix(m=40)
+    _log("case counts int32 subset")
+    C = workloads.counts_matrix(m=40)
     got = micx.allpairs(torch.from_numpy(C).cuda(), 0.6, 15).cpu().numpy()
     want = oracle.allpairs(C.astype(np.float64), 0.6, 15)
     assert np.abs(got[:, :3] - want[:, :3]).max() <= TOL
@@ -126,7 +126,7 @@ def test_cfg4_int32_pairs(micx):
 def test_pair_list_matches_allpairs(micx):
     import torch
     _log("case pair list")
-    X = workloads.cfg2_matrix()[:12]
+    X = workloads.relations_matrix()[:12]
     Xd = torch.from_numpy(X).cuda()
     allp = micx.allpairs(Xd, 0.6, 15).cpu().numpy()
     m = X.shape[0]
@@ -186,19 +186,19 @@ def test_dp32_cpp_example(micx):
         assert abs(v - p) <= 5e-7 + bound
 
 
-def test_dp32_cfg1_matrix_within_bound(micx):
-    _log("case dp32 cfg1")
-    x, y = workloads.cfg1_single_pair()
+def test_dp32_sine_pair_matrix_within_bound(micx):
+    _log("case dp32 sine_pair")
+    x, y = workloads.sine_pair()
     got = micx.compute_score(x, y, 0.6, 15, mode=micx.MODE_DP32)
     bound, nfx, _ = _bound(micx)
     assert nfx > 0
     _cmp_scores(got, oracle.score(x, y, 0.6, 15), tol=bound + 1e-12)
 
 
-def test_dp32_cfg2_allpairs(micx):
+def test_dp32_relations_allpairs(micx):
     import torch
-    _log("case dp32 cfg2 allpairs")
-    X = workloads.cfg2_matrix()
+    _log("case dp32 relations allpairs")
+    X = workloads.relations_matrix()
     got = micx.allpairs(torch.from_numpy(X).cuda(), 0.6, 15, mode=micx.MODE_DP32).cpu().numpy()
     bound, nfx, nf64 = _bound(micx)
     assert nfx > 0
@@ -206,7 +206,7 @@ def test_dp32_cfg2_allpairs(micx):
     d = np.abs(got[:, :3] - want[:, :3]).max()
     assert d <= min(TOL, bound + 1e-12), (d, bound)
     mism = int((np.abs(got[:, 3] - want[:, 3]) > 1e-9).sum())
-    _log("dp32 cfg2: max|d|=%.3g bound=%.3g mcn mismatches=%d of %d" % (d, bound, mism, len(got)))
+    _log("dp32 relations: max|d|=%.3g bound=%.3g mcn mismatches=%d of %d" % (d, bound, mism, len(got)))
     assert mism <= len(got) // 200
 
 
@@ -215,7 +215,7 @@ def test_dp32_tolerance_falls_back_to_fp64(micx):
     # matches the FP64 form bit for bit.
     import torch
     _log("case dp32 tolerance fallback")
-    X = torch.from_numpy(workloads.cfg2_matrix()[:10]).cuda()
+    X = torch.from_numpy(workloads.relations_matrix()[:10]).cuda()
     micx.set_dp32_tolerance(1e-30)
     try:
         a = micx.allpairs(X, 0.6, 15, mode=micx.MODE_DP32).cpu().numpy()
@@ -245,7 +245,7 @@ def test_alternating_forms_full_matrices(micx):
 
 # ------------------------------------------------------------ batch stream
 def _stream_case(seed, npairs, nmin, nmax):
-    data, offx, offy, ns, alphas, cs = workloads.cfg5_stream(seed=seed, npairs=npairs, nmin=nmin,
+    data, offx, offy, ns, alphas, cs = workloads.uneven_stream(seed=seed, npairs=npairs, nmin=nmin,
                                                              nmax=nmax)
     return data, offx, offy, ns, alphas, cs
 
@@ -351,7 +351,7 @@ def test_master_variable_mode(micx):
     # one variable against all others equals the matching rows of all pairs
     import torch
     _log("case master variable")
-    X = workloads.cfg2_matrix()[:14]
+    X = workloads.relations_matrix()[:14]
     Xd = torch.from_numpy(X).cuda()
     allp = micx.allpairs(Xd, 0.6, 15).cpu().numpy()
     m = X.shape[0]
@@ -374,7 +374,7 @@ def _compat_inputs():
     # three row values: yhat stays below the requested row count (normalisation variant)
     three = (rng.uniform(0, 1, 400), np.floor(rng.uniform(0, 3, 400)))
     return [("tied", tied), ("three", three), ("cpp", workloads.cpp_example()),
-            ("cfg1", workloads.cfg1_single_pair())]
+            ("sine_pair", workloads.sine_pair())]
 
 
 @pytest.mark.parametrize("flags", _COMPAT_CASES)
@@ -401,7 +401,7 @@ def test_compat_variants_match_oracle(micx, flags):
 def test_compat_in_batch(micx):
     import torch
     _log("case compat batch")
-    data, offx, offy, ns, alphas, cs = workloads.cfg5_stream(seed=62, npairs=12, nmin=60, nmax=900)
+    data, offx, offy, ns, alphas, cs = workloads.uneven_stream(seed=62, npairs=12, nmin=60, nmax=900)
     flags = 1 | 8 | 16 | 32
     micx.set_compat(flags)
     try:
@@ -425,8 +425,8 @@ def test_compat_rejects_unknown_bits(micx):
 # ------------------------------------------------ Pearson's rho, MIC - rho^2
 def test_pearson_allpairs_matches_oracle(micx):
     import torch
-    _log("case pearson allpairs cfg2")
-    X = workloads.cfg2_matrix()            # float32, 64 x 400
+    _log("case pearson allpairs relations")
+    X = workloads.relations_matrix()            # float32, 64 x 400
     Xd = torch.from_numpy(X).cuda()
     stats = micx.allpairs(Xd, 0.6, 15.0)
     got = micx.pearson(Xd, stats=stats).cpu().numpy()

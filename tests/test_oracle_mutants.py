@@ -82,7 +82,7 @@ def _battery() -> bool:
     r = oracle.score(xs, ys, 0.6, 15)
     ok &= abs(r["Axy"][2, 2] - 1.0) < 1e-12
     # superclumps never exceed khat (App. A items 6-7)
-    x1, y1 = workloads.cfg1_single_pair()
+    x1, y1 = workloads.sine_pair()
     B1 = oracle.grid_bound(len(x1), 0.6)
     for ry in range(2, B1 // 2 + 1):
         it = oracle.item(x1, y1, 0.6, 15, 0, ry)

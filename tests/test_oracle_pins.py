@@ -238,7 +238,7 @@ def test_constant_variable_scores_zero():
 
 
 def test_superclumps_respect_khat():
-    x, y = workloads.cfg1_single_pair()
+    x, y = workloads.sine_pair()
     B = oracle.grid_bound(len(x), 0.6)
     for orient in (0, 1):
         for ry in range(2, B // 2 + 1):

@@ -4,6 +4,6 @@ This package holds input generators only -- no step of the MINE method.  Both
 the GPU library's tests and the FP64 oracle draw their inputs from here.
 """
 from .gen import (  # noqa: F401
-    cfg1_single_pair, cfg2_matrix, cfg3_matrix, cfg4_matrix, cfg5_stream,
+    sine_pair, relations_matrix, microarray_matrix, counts_matrix, uneven_stream,
     cpp_example, fig2_points, boundary_cases, RELATIONS,
 )

@@ -11,7 +11,7 @@ from __future__ import annotations
 
 import numpy as np
 
-# Relationship types applied to a base column (config 2 and 5 recipes).
+# Relationship types applied to a base column (the mixed-relations matrix and the uneven stream).
 RELATIONS = ("linear", "parabola", "cubic", "exponential", "sine1", "sine8", "circle", "step")
 
 
@@ -40,7 +40,7 @@ def _relation(kind: str, u: np.ndarray, rng: np.random.Generator) -> np.ndarray:
     return f
 
 
-def cfg1_single_pair(seed: int = 1, n: int = 200):
+def sine_pair(seed: int = 1, n: int = 200):
     """Single pair, float64: x ~ U[0,1], y = sin(4 pi x) + N(0, 0.1^2)."""
     rng = np.random.default_rng(seed)
     x = rng.uniform(0.0, 1.0, n)
@@ -48,7 +48,7 @@ def cfg1_single_pair(seed: int = 1, n: int = 200):
     return x.astype(np.float64), y.astype(np.float64)
 
 
-def cfg2_matrix(seed: int = 2, m: int = 64, n: int = 400) -> np.ndarray:
+def relations_matrix(seed: int = 2, m: int = 64, n: int = 400) -> np.ndarray:
     """m x n float32: 16 uniform base columns, 32 noisy functions of them
     (8 relation types x 4 noise levels sigma in {0, 1/3, 2/3, 1}), 16 N(0,1)
     columns.  Row-major, one variable per row."""
@@ -71,7 +71,7 @@ def cfg2_matrix(seed: int = 2, m: int = 64, n: int = 400) -> np.ndarray:
     return X.astype(np.float32)
 
 
-def cfg3_matrix(seed: int = 3, m: int = 1000, n: int = 1340, planted: int = 50):
+def microarray_matrix(seed: int = 3, m: int = 1000, n: int = 1340, planted: int = 50):
     """Microarray-shaped m x n float64: exp(N(6, 1.5^2)) rounded to 2 decimals
     (ties), with `planted` disjoint dependent pairs (i, j): column j is a noisy
     function of standardised log column i.  Returns (X, planted_list) where
@@ -93,7 +93,7 @@ def cfg3_matrix(seed: int = 3, m: int = 1000, n: int = 1340, planted: int = 50):
     return X.astype(np.float64), np.array(plist, dtype=np.float64)
 
 
-def cfg4_matrix(seed: int = 4, m: int = 2000, n: int = 1340) -> np.ndarray:
+def counts_matrix(seed: int = 4, m: int = 2000, n: int = 1340) -> np.ndarray:
     """RNA-seq-shaped m x n int32 counts: per feature a mean mu log-uniform in
     [0.5, 5000], negative binomial with dispersion 0.2 (size 5), then
     structural zeros with probability pi ~ U[0.3, 0.6] per feature."""
@@ -108,7 +108,7 @@ def cfg4_matrix(seed: int = 4, m: int = 2000, n: int = 1340) -> np.ndarray:
     return C.astype(np.int32)
 
 
-def cfg5_stream(seed: int = 5, npairs: int = 8192, nmin: int = 50, nmax: int = 8000):
+def uneven_stream(seed: int = 5, npairs: int = 8192, nmin: int = 50, nmax: int = 8000):
     """Uneven stream of independent pairs.  Returns (data float32 packed,
     offsets_x, offsets_y, ns, alphas, cs).  n is log-uniform in [nmin, nmax];
     the relation is one of the 8 types or independent, with noise sigma ~ U[0,1];
