@@ -503,3 +503,28 @@ def test_cli_end_to_end(micx, tmp_path):
             vals = np.array([float(t) for t in f[2:]])
             want = np.array([w[0], w[1], w[2], w[3], r, oracle.nonlinearity(w[0], r)])
             assert np.abs(vals - want).max() <= 1.5e-6, (i, j, vals, want)
+
+
+def test_microarray_full_size_sampled(micx):
+    # the benchmark workload at full size (1000 x 1340, all 499,500 pairs) in
+    # both forms; pairs sampled for the oracle: the planted ones + 128 seeded
+    import torch
+    _log("case microarray full size, sampled pairs")
+    X, planted = workloads.microarray_matrix()
+    m = X.shape[0]
+    rng = np.random.default_rng(91)
+    pl = {(int(min(a, b)), int(max(a, b))) for a, b in planted[:, :2]}
+    while len(pl) < len(planted) + 128:
+        a, b = rng.integers(0, m, 2)
+        if a != b:
+            pl.add((int(min(a, b)), int(max(a, b))))
+    pl = sorted(pl)
+    idx = np.array([i * m - i * (i + 1) // 2 + (j - i - 1) for i, j in pl])
+    want = oracle.allpairs(X, 0.6, 15.0, pairs=np.array(pl))
+    Xd = torch.from_numpy(X).cuda()
+    got64 = micx.allpairs(Xd, 0.6, 15.0, micx.MODE_FP64).cpu().numpy()[idx]
+    assert np.abs(got64[:, :3] - want[:, :3]).max() <= TOL
+    assert (np.abs(got64[:, 3] - want[:, 3]) < 1e-9).all()
+    got32 = micx.allpairs(Xd, 0.6, 15.0, micx.MODE_DP32).cpu().numpy()[idx]
+    bound = micx.get_profile()["dp32_bound"]
+    assert np.abs(got32[:, :3] - want[:, :3]).max() <= max(bound, 1e-12) + 1e-12
