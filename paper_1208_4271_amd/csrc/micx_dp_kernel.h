@@ -31,7 +31,8 @@
 // their layer values are staged from the item's G table (global, layer-major)
 // into LDS, SB sources at a time, and read back as wavefront-uniform
 // broadcasts.  Sources inside the chunk are taken in order; the lane that
-// owns a source publishes its layer values through LDS.
+// owns a source broadcasts its layer values through scalar registers
+// (readlane).
 #pragma once
 
 #include <stdlib.h>
