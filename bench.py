@@ -157,11 +157,11 @@ def parity_of(got, ref):
             "max_dMEV": float(d[:, 2].max()), "mcn_mismatch": int((d[:, 3] > 1e-9).sum())}
 
 
-def stream_leg(micx, with_oracle):
+def stream_leg(micx):
     """The uneven stream (8,192 independent pairs, n log-uniform in [50, 8000],
     alpha in {0.55, 0.6, 0.75}, c in {5, 15}) through micx_batch: one warm-up,
-    then one timed call per form; parity on a seeded sample of pairs with
-    n <= 2000 against the oracle."""
+    then one timed call per form.  Returns (leg, results per form, inputs);
+    the CPU-oracle leg adds parity on a seeded sample (stream_parity)."""
     import torch
     import workloads
     data, offx, offy, ns, alphas, cs = workloads.uneven_stream()
@@ -181,22 +181,26 @@ def stream_leg(micx, with_oracle):
         hosts[form] = out.cpu().numpy()
         leg[form] = {"value": round(len(ns) / dt, 2), "unit": "pairs/s", "ms": round(dt * 1e3, 1)}
         print("bench: stream %s done" % form, file=sys.stderr, flush=True)
-    if with_oracle:
-        import oracle
-        rng = np.random.default_rng(777)
-        cand = np.flatnonzero(ns <= 2000)
-        sample = np.sort(rng.choice(cand, size=min(64, len(cand)), replace=False))
-        ref = []
-        for k in sample:
-            n = int(ns[k])
-            x = data[offx[k]:offx[k] + n].astype(np.float64)
-            y = data[offy[k]:offy[k] + n].astype(np.float64)
-            ref.append(oracle.score(x, y, float(alphas[k]), float(cs[k]))["stats"])
-        ref = np.array(ref)
-        for form in hosts:
-            leg[form]["parity"] = parity_of(hosts[form][sample], ref)
-        leg["parity_sample"] = "%d seeded pairs with n <= 2000" % len(sample)
-    return leg
+    return leg, hosts, (data, offx, offy, ns, alphas, cs)
+
+
+def stream_parity(oracle, leg, hosts, inputs):
+    """Part of the CPU-oracle leg: the stream's results on a seeded sample of
+    pairs with n <= 2000 against the FP64 oracle."""
+    data, offx, offy, ns, alphas, cs = inputs
+    rng = np.random.default_rng(777)
+    cand = np.flatnonzero(ns <= 2000)
+    sample = np.sort(rng.choice(cand, size=min(64, len(cand)), replace=False))
+    ref = []
+    for k in sample:
+        n = int(ns[k])
+        x = data[offx[k]:offx[k] + n].astype(np.float64)
+        y = data[offy[k]:offy[k] + n].astype(np.float64)
+        ref.append(oracle.score(x, y, float(alphas[k]), float(cs[k]))["stats"])
+    ref = np.array(ref)
+    for form in hosts:
+        leg[form]["parity"] = parity_of(hosts[form][sample], ref)
+    leg["parity_sample"] = "%d seeded pairs with n <= 2000" % len(sample)
 
 
 def sweep_leg(micx):
@@ -287,6 +291,11 @@ def main():
         "forms": forms,
     }
 
+    stream = None
+    if not args.no_stream and args.m == 1000:
+        stream = stream_leg(micx)
+        result["batch_stream"] = stream[0]
+    # the CPU-oracle leg: baseline timing and every parity figure
     if args.cpu_sample > 0:
         import oracle
         rng = np.random.default_rng(12345)
@@ -317,8 +326,8 @@ def main():
         result["parity"] = parity_of(results[main_form][2][idx], ref)
         for form in results:
             forms[form]["parity"] = parity_of(results[form][2][idx], ref)
-    if not args.no_stream and args.m == 1000:
-        result["batch_stream"] = stream_leg(micx, args.cpu_sample > 0)
+        if stream is not None:
+            stream_parity(oracle, *stream)
     if args.sweep:
         result["sweep"] = sweep_leg(micx)
     if args.copy_calibration > 0:
