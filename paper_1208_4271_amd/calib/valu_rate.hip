@@ -1,16 +1,18 @@
 // valu_rate.hip -- issue rate of the VALU instructions the DP kernels use, on
 // the GPU it runs on.  Each case runs 16 independent register chains of one
 // instruction (inline assembly of ALU instructions only, so the count is
-// exact) over 8 waves per SIMD, and reports SIMD-cycles per wave64
+// exact) over W waves per SIMD (first argument, default 8), and reports
+// SIMD-cycles per wave64
 // instruction at the clock the first wave measures (shader clock against the
 // 100 MHz real-time counter).  The peaks in bench.py's roofline rest on these
 // rates.
 //
 //   hipcc --offload-arch=gfx950 -O3 -Xclang -target-feature -Xclang -packed-fp32-ops \
-//         -o valu_rate paper_1208_4271_amd/calib/valu_rate.hip && ./valu_rate
+//         -o valu_rate paper_1208_4271_amd/calib/valu_rate.hip && ./valu_rate [W]
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 
 #define NCASE 12
 
@@ -60,8 +62,13 @@ __global__ __launch_bounds__(256) void k_rate(uint32_t *out, unsigned long long 
 
 typedef void (*kern_t)(uint32_t *, unsigned long long *, int, uint32_t);
 
-int main() {
-    const int blocks = 256 * 8, threads = 256, iters = 10000;
+int main(int argc, char **argv) {
+    const int wps = argc > 1 ? atoi(argv[1]) : 8;   // waves per SIMD (4 waves per workgroup)
+    if (wps < 1 || wps > 8) {
+        fprintf(stderr, "waves per SIMD must be 1..8\n");
+        return 1;
+    }
+    const int blocks = 256 * wps, threads = 256, iters = 10000;
     const double winstr = (double)blocks * (threads / 64) * iters * 32;   // wave-instructions per launch
     uint32_t *out = nullptr;
     unsigned long long *clk = nullptr;
@@ -77,6 +84,7 @@ int main() {
                                 "v_add_f32 v,v", "v_fma_f32", "v_add_f64", "v_min_f64"};
     const kern_t ks[NCASE] = {k_rate<0>, k_rate<1>, k_rate<2>, k_rate<3>, k_rate<4>, k_rate<5>,
                               k_rate<6>, k_rate<7>, k_rate<8>, k_rate<9>, k_rate<10>, k_rate<11>};
+    printf("waves per SIMD: %d\n", wps);
     printf("%-28s %9s %10s %8s %14s\n", "instruction", "ms", "T lane/s", "MHz", "cycles/instr");
     for (int kind = 0; kind < NCASE; kind++) {
         for (int rep = 0; rep < 2; rep++) {   // the first launch warms up
