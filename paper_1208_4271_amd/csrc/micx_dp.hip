@@ -173,6 +173,10 @@ void dp_fit_lds(DpPlan &p, int nmax, size_t rec_bytes, int cus) {
     const int lds_rec = align16(rec_bytes);
     const int budget = 160 * 1024;
     p.WPB = 4;
+    // workgroups per CU the staging split aims for: four for one-target
+    // passes of 14 layers or more (their registers allow four waves per SIMD;
+    // measured 7% faster than two), else two (tuning override MICX_DP_WGS)
+    const int wgs = std::max(1, env_int("MICX_DP_WGS", (p.T == 1 && p.NL >= 14) ? 4 : 2));
     for (p.SB = 64;; p.SB >>= 1) {
         const int lds_stage = align16(std::max((size_t)p.SB * NLP * vb, (size_t)nmax));
         const int wave = align16((size_t)lds_stage + lds_rec);
@@ -180,7 +184,7 @@ void dp_fit_lds(DpPlan &p, int nmax, size_t rec_bytes, int cus) {
         p.lds_stage = lds_stage;
         p.lds_wave = wave;
         p.lds = lds_L + p.WPB * wave;
-        if (p.lds * 2 <= budget || p.SB == 8) break;     // two workgroups per CU
+        if (p.lds * wgs <= budget || p.SB == 8) break;
     }
     while (p.lds > budget && p.WPB > 1) {
         p.WPB--;
