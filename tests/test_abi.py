@@ -126,3 +126,13 @@ def test_cli_reads_csv_and_modes(tmp_path):
         cli.read_csv(str(bad))
     args = cli.parse(["x.csv", "-a", "0.55", "-c", "10", "-m", "3", "-o", "o.tsv"])
     assert args.alpha == 0.55 and args.clumps == 10 and args.master == 3 and args.output == "o.tsv"
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the path runs on one GPU; bench.py says so and exits before any GPU work
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
