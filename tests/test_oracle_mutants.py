@@ -37,6 +37,16 @@ MUTANTS = {
     "norm_by_requested": ("(l < yhat ? l : yhat)", "(l < ry ? l : ry)"),
     # one superclump more than khat (the MINE.jar behaviour of App. A item 7)
     "khat_plus_one": ("int k = (int) floor(c * (double) cx);", "int k = (int) floor(c * (double) cx) + 1;"),
+    # Algorithm 2 read as consecutive clumps grouped by count, not by points
+    "superclump_equal_count": (
+        "int K = oracle_equipartition(d, n, limit, flags & (ORC_TIE_STRICT | ORC_DESIRED_INT), p);",
+        "int per = (k + limit - 1) / limit; for (int i = 0; i < n; i++) p[i] = (int) d[i] / per;"
+        " int K = p[n - 1] + 1;"),
+    # the superclump step alone closes rows on '>' (the row step keeps '>=')
+    "superclump_strict_tie": ("flags & (ORC_TIE_STRICT | ORC_DESIRED_INT), p);",
+                              "(flags & ORC_DESIRED_INT) | ORC_TIE_STRICT, p);"),
+    # no lower bound of one superclump when c x < 1
+    "khat_no_floor_guard": ("return k < 1 ? 1 : k;", "return k;"),
 }
 
 
@@ -89,6 +99,16 @@ def _battery() -> bool:
         ok &= it["K"] <= 15 * (B1 // ry)
     it = oracle.item(x1, y1, 0.6, 1.0, 0, 2)
     ok &= it["K"] <= (B1 // 2)
+    # Algorithm 2 worked by hand (tests/golden/superclumps_alg2.txt)
+    from test_oracle_pins import clump_input, superclump_ends, superclump_goldens
+    for _, khat, sizes, ends in superclump_goldens():
+        a, q = clump_input(sizes)
+        p, K, k = oracle.superclumps(a, q, khat)
+        ok &= k == len(sizes) and K == len(ends) and superclump_ends(p) == ends
+    # a bound below one column: one superclump
+    for ry in range(2, B1 // 2 + 1):
+        if math.floor(0.3 * (B1 // ry)) < 1:
+            ok &= oracle.item(x1, y1, 0.6, 0.3, 0, ry)["K"] == 1
     return bool(ok)
 
 
@@ -108,6 +128,7 @@ def test_unmodified_oracle_passes_battery():
 _CHILD = """
 import importlib.util, sys
 sys.path.insert(0, {root!r})
+sys.path.insert(0, {tests!r})
 import oracle
 spec = importlib.util.spec_from_file_location("mut", {here!r})
 mod = importlib.util.module_from_spec(spec)
@@ -127,6 +148,7 @@ def test_mutant_is_caught(tmp_path, name):
     assert src.count(old) == 1
     so = _build_variant(tmp_path, name, src.replace(old, new))
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    code = _CHILD.format(root=root, here=os.path.abspath(__file__), so=so)
+    code = _CHILD.format(root=root, tests=os.path.join(root, "tests"), here=os.path.abspath(__file__),
+                         so=so)
     res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert res.returncode != 0, "pins did not catch mutant " + name

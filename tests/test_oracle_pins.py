@@ -237,6 +237,65 @@ def test_constant_variable_scores_zero():
     assert st[0] == 0.0 and st[1] == 0.0 and st[2] == 0.0 and st[3] == 2.0
 
 
+# ------------------------------------------- GetSuperclumpsPartition (Alg. 2) --
+def superclump_goldens():
+    """Hand-worked cases of Algorithm 2 (tests/golden/superclumps_alg2.txt):
+    (name, khat, clump sizes, superclump ends)."""
+    out = []
+    for r in _read_golden("superclumps_alg2.txt"):
+        out.append((r[0], int(r[1]), [int(v) for v in r[2].split(",")],
+                    [int(v) for v in r[3].split(",")]))
+    return out
+
+
+def clump_input(sizes):
+    """Points in column order (distinct first coordinates) whose row labels
+    alternate 0, 1, 0, ... from one clump to the next, so that
+    GetClumpsPartition returns exactly clumps of the given sizes."""
+    a = np.arange(sum(sizes), dtype=np.float64)
+    q = np.repeat(np.arange(len(sizes)) % 2, sizes).astype(np.int32)
+    return a, q
+
+
+def superclump_ends(p):
+    n = len(p)
+    return [i + 1 for i in range(n) if i == n - 1 or p[i + 1] != p[i]]
+
+
+@pytest.mark.parametrize("case", superclump_goldens(), ids=lambda c: c[0])
+def test_superclumps_hand_worked(case):
+    # Algorithm 2 with Appendix A items 3 and 7: the merge is EquipartitionYAxis
+    # over the points with each clump a tie group, closing rows on equality
+    name, khat, sizes, ends = case
+    a, q = clump_input(sizes)
+    p, K, k = oracle.superclumps(a, q, khat)
+    assert k == len(sizes)
+    assert K == len(ends) <= khat
+    assert superclump_ends(p) == ends
+
+
+def test_superclump_bound_below_one_column():
+    # c < 1/2 with two columns gives floor(c x) = 0: the bound is taken as one
+    # superclump, so the single column carries no information and every
+    # entry of such a row count is exactly 0
+    x, y = workloads.sine_pair()
+    c = 0.3
+    B = oracle.grid_bound(len(x), 0.6)
+    r = oracle.score(x, y, 0.6, c)
+    seen = 0
+    for orient, A in ((0, r["Axy"]), (1, r["Ayx"])):
+        for ry in range(2, B // 2 + 1):
+            cx = B // ry
+            it = oracle.item(x, y, 0.6, c, orient, ry)
+            kh = max(1, math.floor(c * cx))
+            assert it["K"] <= kh
+            if kh == 1:
+                seen += 1
+                assert it["K"] == 1 and list(it["ends"]) == [len(x)]
+                assert (A[ry - 2, : cx - 1] == 0.0).all()
+    assert seen > 0
+
+
 def test_superclumps_respect_khat():
     x, y = workloads.sine_pair()
     B = oracle.grid_bound(len(x), 0.6)
