@@ -184,23 +184,41 @@ def stream_leg(micx):
     return leg, hosts, (data, offx, offy, ns, alphas, cs)
 
 
-def stream_parity(oracle, leg, hosts, inputs):
-    """Part of the CPU-oracle leg: the stream's results on a seeded sample of
-    pairs with n <= 2000 against the FP64 oracle."""
+def stream_parity(oracle, leg, hosts, inputs, threads):
+    """Part of the CPU-oracle leg: the stream's results against the FP64
+    oracle on a seeded sample -- 64 pairs with n <= 2000, plus the pair of
+    largest DP cost (n near 8000 at alpha 0.75) and three more seeded pairs
+    with n > 4000 -- run on `threads` host threads."""
+    from concurrent.futures import ThreadPoolExecutor
     data, offx, offy, ns, alphas, cs = inputs
     rng = np.random.default_rng(777)
-    cand = np.flatnonzero(ns <= 2000)
-    sample = np.sort(rng.choice(cand, size=min(64, len(cand)), replace=False))
-    ref = []
-    for k in sample:
+    small = np.flatnonzero(ns <= 2000)
+    sample = list(rng.choice(small, size=min(64, len(small)), replace=False))
+    big = np.flatnonzero(ns > 4000)
+    cost = ns.astype(np.float64) ** (3 * alphas) * cs ** 2
+    heaviest = int(big[np.argmax(cost[big])])
+    others = [int(k) for k in rng.permutation(big) if int(k) != heaviest][:3]
+    sample = np.array(sorted(set(int(k) for k in sample) | {heaviest} | set(others)))
+
+    def one(k):
         n = int(ns[k])
         x = data[offx[k]:offx[k] + n].astype(np.float64)
         y = data[offy[k]:offy[k] + n].astype(np.float64)
-        ref.append(oracle.score(x, y, float(alphas[k]), float(cs[k]))["stats"])
-    ref = np.array(ref)
+        return oracle.score(x, y, float(alphas[k]), float(cs[k]))["stats"]
+
+    t0 = time.perf_counter()
+    # largest first, so the heaviest pair starts at once
+    order = sorted(sample, key=lambda k: -cost[k])
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        got = dict(zip(order, ex.map(one, order)))
+    ref = np.array([got[k] for k in sample])
     for form in hosts:
         leg[form]["parity"] = parity_of(hosts[form][sample], ref)
-    leg["parity_sample"] = "%d seeded pairs with n <= 2000" % len(sample)
+    leg["parity_sample"] = ("%d seeded pairs: %d with n <= 2000, %d with n > 4000 (largest n %d, "
+                            "alpha %.2f); oracle %.1f s on %d threads" %
+                            (len(sample), int((ns[sample] <= 2000).sum()), int((ns[sample] > 4000).sum()),
+                             int(ns[sample].max()), float(alphas[heaviest]), time.perf_counter() - t0,
+                             threads))
 
 
 def sweep_leg(micx):
@@ -270,6 +288,11 @@ def main():
                        "roofline_frac": roofline_of(prof, "k_dp")["frac"],
                        "dp32_classes": prof["dp32_classes"], "fp64_classes": prof["fp64_classes"],
                        "dp32_bound": prof["dp32_bound"]}
+        if prof["dp32_classes"] > 0:
+            # pairs whose MCN the 32-bit entries left open, and their FP64 re-run
+            forms[form]["recheck"] = {"pairs": prof["recheck_pairs"], "items": prof["recheck_items"],
+                                      "flag_rate": round(prof["recheck_pairs"] / npairs, 7),
+                                      "ms": round(prof["recheck_ms"], 3)}
 
     main_form = order[0]
     ms, prof, host = results[main_form]
@@ -327,7 +350,7 @@ def main():
         for form in results:
             forms[form]["parity"] = parity_of(results[form][2][idx], ref)
         if stream is not None:
-            stream_parity(oracle, *stream)
+            stream_parity(oracle, *stream, threads)
     if args.sweep:
         result["sweep"] = sweep_leg(micx)
     if args.copy_calibration > 0:

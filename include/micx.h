@@ -236,6 +236,9 @@ typedef struct {
     int dp32_classes;     /* row counts run in 32-bit fixed point (MICX_MODE_DP32) */
     int fp64_classes;     /* row counts run in FP64 */
     double dp32_bound;    /* largest |dM| bound among the fixed-point row counts */
+    int64_t recheck_pairs; /* MICX_MODE_DP32: pairs whose MCN the 32-bit entries left open */
+    int64_t recheck_items; /* items of those pairs re-run in FP64 */
+    double recheck_ms;    /* duration of the FP64 re-runs and the statistics after them */
 } micx_profile;
 
 int micx_set_profiling(micx_ctx *ctx, int enable);

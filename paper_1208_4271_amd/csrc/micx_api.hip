@@ -61,6 +61,8 @@ struct micx_ctx {
     int compat = 0;           // MICX_COMPAT_* flags
     int profiling = 0;
     micx_profile prof = {};
+    DevBuf rcwords, rclist, rcpairs;   // near-tie recheck: counters and item flags, item lists, pairs
+    DevBuf rcmeta;                     // near-tie recheck of a batch pass: key offsets, key of each class
     DevBuf arena, gitems;              // micx_batch: per-pass group buffers, DP item lists
     std::vector<hipStream_t> dstreams; // micx_batch: DP launches of different shapes run side by side
 };
@@ -121,7 +123,8 @@ extern "C" void micx_ctx_destroy(micx_ctx *c) {
                      &c->xlogx, &c->status, &c->geo, &c->cbuf, &c->sbuf, &c->Kb, &c->kb,
                      &c->srcb, &c->A, &c->scratch, &c->pairs, &c->input, &c->out, &c->dense,
                      &c->counters, &c->fxtab, &c->lab,
-                     &c->bdata, &c->boffs, &c->bout, &c->bidx};
+                     &c->bdata, &c->boffs, &c->bout, &c->bidx,
+                     &c->rcwords, &c->rclist, &c->rcpairs, &c->rcmeta, &c->moments};
     for (DevBuf *b : all) b->release();
     c->arena.release();
     c->gitems.release();
@@ -294,12 +297,43 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
     std::vector<DpPlan> plans(g.NY);
     size_t scratch = 0;
     int nfx = 0;
+    double bound = 0.0;
+    auto grid_bytes = [&](const DpPlan &p) {
+        const size_t waves = (size_t)std::min<int64_t>(p.max_waves, 2 * (int64_t)pb);
+        return ((waves + p.WPB - 1) / p.WPB) * p.WPB * p.slot_bytes;
+    };
     for (int yi = 0; yi < g.NY; yi++) {
         plans[yi] = dp_plan(g, rt.n, yi, ctx->cus, mode, ctx->dp32_tol);
-        const size_t waves = (size_t)std::min<int64_t>(plans[yi].max_waves, 2 * (int64_t)pb);
-        const size_t w = ((waves + plans[yi].WPB - 1) / plans[yi].WPB) * plans[yi].WPB;
-        scratch = std::max(scratch, w * plans[yi].slot_bytes);
-        nfx += plans[yi].fx ? 1 : 0;
+        scratch = std::max(scratch, grid_bytes(plans[yi]));
+        if (plans[yi].fx) {
+            nfx++;
+            bound = std::max(bound, plans[yi].bound);
+        }
+    }
+    // near-tie recheck of the 32-bit form: FP64 plans of every row count, the
+    // item flags, per-row-count item lists and the flagged pairs (Recheck)
+    const bool recheck = nfx > 0;
+    std::vector<DpPlan> plans64;
+    Recheck rc;
+    size_t rc_words = 0;
+    if (recheck) {
+        plans64.resize(g.NY);
+        for (int yi = 0; yi < g.NY; yi++) {
+            plans64[yi] = dp_plan(g, rt.n, yi, ctx->cus, MICX_MODE_FP64, 0.0);
+            scratch = std::max(scratch, grid_bytes(plans64[yi]));
+        }
+        rc.band = 2.0 * bound + 1e-12;
+        rc.nyw = (g.NY + 31) / 32;
+        rc.icap = 2 * pb;
+        rc_words = (size_t)g.NY + 1 + (size_t)rc.icap * rc.nyw;
+        RETCHK(ctx->rcwords.ensure(rc_words * sizeof(unsigned)));
+        RETCHK(ctx->rclist.ensure((size_t)g.NY * rc.icap * sizeof(int)));
+        RETCHK(ctx->rcpairs.ensure((size_t)pb * sizeof(int)));
+        rc.icount = ctx->rcwords.as<int>();
+        rc.pcount = rc.icount + g.NY;
+        rc.iflag = (unsigned *)(rc.pcount + 1);
+        rc.ilist = ctx->rclist.as<int>();
+        rc.plist = ctx->rcpairs.as<int>();
     }
     RETCHK(ctx->scratch.ensure(scratch));
     // fixed-point cost tables, one per row count that runs in 32 bits
@@ -311,7 +345,7 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
                 HIPCHK(launch_fxtable(rt.n, plans[yi], ctx->xlogx.as<double>(),
                                       ctx->fxtab.as<uint32_t>() + yi * tabn, s));
     }
-    std::vector<hipEvent_t> ev;
+    std::vector<hipEvent_t> ev, ev_rc;
     unsigned long long *counters = nullptr;
     ctx->prof = micx_profile{};
     if (ctx->profiling) {
@@ -330,6 +364,7 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
             ps.pairs = nullptr;
             ps.p0 = p0;
         }
+        if (recheck) HIPCHK(launch_zero(ctx->rcwords.p, rc_words, s));
         HIPCHK(launch_part(rt, et, g, ps, np, ib, s));
         if (counters) HIPCHK(launch_work(et, g, ps, np, ib, counters, s));
         for (int yi = 0; yi < g.NY; yi++) {
@@ -346,7 +381,33 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
                              ctx->scratch.p, yi, plans[yi], s));
             if (ctx->profiling) HIPCHK(hipEventRecord(ev.back(), s));
         }
-        HIPCHK(launch_stats(g, np, ib, out_dev + 4 * p0, M, Axy, Ayx, s));
+        HIPCHK(launch_stats(g, np, ib, out_dev + 4 * p0, M, Axy, Ayx, s, recheck ? &rc : nullptr));
+        if (recheck) {
+            // FP64 re-run of the queued items of every row count, then the
+            // flagged pairs' statistics again from the updated entries
+            if (ctx->profiling) {
+                hipEvent_t a;
+                HIPCHK(hipEventCreate(&a));
+                ev_rc.push_back(a);
+                HIPCHK(hipEventRecord(a, s));
+            }
+            for (int yi = 0; yi < g.NY; yi++)
+                HIPCHK(launch_dp(rt, et, g, ps, np, ib, ctx->xlogx.as<double>(), nullptr,
+                                 ctx->scratch.p, yi, plans64[yi], s, rc.ilist + (size_t)yi * rc.icap,
+                                 rc.icount + yi, 2 * np));
+            HIPCHK(launch_stats(g, np, ib, out_dev + 4 * p0, M, Axy, Ayx, s, nullptr, rc.plist, rc.pcount));
+            if (ctx->profiling) {
+                hipEvent_t b;
+                HIPCHK(hipEventCreate(&b));
+                ev_rc.push_back(b);
+                HIPCHK(hipEventRecord(b, s));
+                std::vector<int> h(g.NY + 1);
+                HIPCHK(hipMemcpyAsync(h.data(), rc.icount, h.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                for (int yi = 0; yi < g.NY; yi++) ctx->prof.recheck_items += h[yi];
+                ctx->prof.recheck_pairs += h[g.NY];
+            }
+        }
     }
     if (ctx->profiling) {
         HIPCHK(hipStreamSynchronize(s));
@@ -357,6 +418,14 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
             ms += t;
         }
         for (hipEvent_t e : ev) hipEventDestroy(e);
+        double rms = 0.0;
+        for (size_t k = 0; k + 1 < ev_rc.size(); k += 2) {
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, ev_rc[k], ev_rc[k + 1]));
+            rms += t;
+        }
+        for (hipEvent_t e : ev_rc) hipEventDestroy(e);
+        ctx->prof.recheck_ms = rms;
         unsigned long long h[4];
         HIPCHK(hipMemcpy(h, counters, sizeof(h), hipMemcpyDeviceToHost));
         ctx->prof.items = (int64_t)h[0];
@@ -542,6 +611,9 @@ void add_profile(micx_profile &t, const micx_profile &p) {
     t.dp32_classes += p.dp32_classes;
     t.fp64_classes += p.fp64_classes;
     t.dp32_bound = std::max(t.dp32_bound, p.dp32_bound);
+    t.recheck_pairs += p.recheck_pairs;
+    t.recheck_items += p.recheck_items;
+    t.recheck_ms += p.recheck_ms;
 }
 
 // DP launch key of a batch: kernel shape, plus the fixed-point scale bucket
@@ -564,6 +636,103 @@ struct DpBucket {
 };
 
 constexpr size_t kArenaBytes = (size_t)16 << 30;  // per pass over the stream (of 288 GB)
+
+// Launch keys of a batch pass for one numeric form: every (group, row count)
+// class goes to the launch of its kernel shape (and fixed-point scale
+// bucket); a key whose largest table and largest count records together
+// exceed the LDS is split, largest n first, into launches that fit (every
+// class fits on its own).
+void make_buckets(micx_ctx *ctx, const std::vector<BatchGroup> &groups, size_t g0,
+                  const std::vector<GroupLayout> &lay, int mode, std::map<DpKey, DpBucket> &buckets) {
+    struct DpClass {
+        DpPlan p;
+        int gi, yi, n;
+        size_t rec, slot;
+        double cost;
+    };
+    std::map<DpKey, std::vector<DpClass>> byShape;
+    for (size_t i = 0; i < lay.size(); i++) {
+        const BatchGroup &bg = groups[g0 + i];
+        const Geometry &g = lay[i].hg.g;
+        for (int yi = 0; yi < g.NY; yi++) {
+            // passes of at most 24 layers: the descriptor kernels then keep two
+            // (FP64) or three (32-bit) targets per lane without spilling, which
+            // shortens the stream's largest items (measured: FP64 3.40 -> 2.95 s,
+            // DP32 2.29 -> 2.13 s on the 8,192-pair stream)
+            DpPlan p = dp_shape(g, bg.n, yi, mode, ctx->dp32_tol, 24);
+            // a shared table uses the smallest scale of its bucket, at most a
+            // factor 2 below the class's own: keep the bound within tolerance
+            if (p.fx && 2.0 * p.bound > ctx->dp32_tol) {
+                p.fx = false;
+                if (p.T == 3) p.T = 2;   // three targets per lane exist in 32 bits only
+            }
+            DpKey key{p.fx ? 1 : 0, p.NL, p.YR, p.T, p.fx ? (int)floor(log2(p.scale)) : 0, -1};
+            byShape[key].push_back({p, (int)i, yi, bg.n, (size_t)p.KS * p.RS * 4,
+                                    (size_t)p.x * p.KS * (p.fx ? 4 : 8), (double)p.x * p.KS * p.KS});
+        }
+    }
+    for (auto &kv : byShape) {
+        std::vector<DpClass> &cl = kv.second;
+        std::sort(cl.begin(), cl.end(), [](const DpClass &u, const DpClass &v) { return u.n > v.n; });
+        const int vb = kv.first.fx ? 4 : 8;
+        const int NLP = (kv.first.NL + 16 / vb - 1) / (16 / vb) * (16 / vb);
+        auto need = [&](int nmax, size_t rec) {
+            return (size_t)align16b((size_t)(nmax + 1) * vb) + align16b(std::max((size_t)8 * NLP * vb, (size_t)nmax)) +
+                   align16b(rec);
+        };
+        int part = -1, nmax = 0;
+        size_t rec = 0;
+        for (const DpClass &c : cl) {
+            if (part < 0 || need(nmax, std::max(rec, c.rec)) > 160 * 1024) {
+                part++;
+                nmax = c.n;
+                rec = 0;
+            }
+            rec = std::max(rec, c.rec);
+            DpKey key = kv.first;
+            key.grp = part;
+            DpBucket &b = buckets[key];
+            if (b.classes.empty()) b.plan = c.p;
+            b.nmax = std::max(b.nmax, c.n);
+            b.rec = std::max(b.rec, c.rec);
+            b.slot = std::max(b.slot, c.slot);
+            if (c.p.fx) b.scale = b.scale == 0.0 ? c.p.scale : std::min(b.scale, c.p.scale);
+            b.classes.push_back({c.cost, {c.gi, c.yi}});
+        }
+    }
+    for (auto &kv : buckets) {
+        DpBucket &b = kv.second;
+        std::sort(b.classes.begin(), b.classes.end(),
+                  [](const std::pair<double, std::pair<int, int>> &u,
+                     const std::pair<double, std::pair<int, int>> &v) { return u.first > v.first; });
+        DpPlan &p = b.plan;
+        p.scale = b.scale;
+        p.slot_bytes = b.slot;
+        p.groups = true;
+        dp_fit_lds(p, b.nmax, b.rec, ctx->cus);
+    }
+}
+
+// Scratch (G tables) of a set of DP launches spread round-robin over the DP
+// streams: per stream, the largest need among the launches it runs.
+size_t stream_scratch(const std::vector<std::pair<const DpPlan *, size_t>> &launches, int nstreams,
+                      std::vector<size_t> &off) {
+    std::vector<size_t> need(nstreams, 0);
+    for (size_t k = 0; k < launches.size(); k++) {
+        const DpPlan &p = *launches[k].first;
+        const size_t waves = std::min<size_t>(launches[k].second, (size_t)p.max_waves);
+        const size_t w = (waves + p.WPB - 1) / p.WPB * p.WPB;
+        need[k % nstreams] = std::max(need[k % nstreams], w * p.slot_bytes);
+    }
+    size_t scr = 0;
+    off.assign(nstreams, 0);
+    for (int k = 0; k < nstreams; k++) {
+        off[k] = scr;
+        scr += align256(need[k]);
+    }
+    return scr;
+}
+
 constexpr int kDpStreams = 4;
 
 // Runs groups[g0, g1) of a batch: per-group ranks, equipartitions and
@@ -757,66 +926,8 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
     if (hstatus & 1) return MICX_ENONFINITE;
     if (hstatus) return MICX_EDEVICE;
     // DP keys: every (group, row count) class goes to the launch of its shape
-    struct DpClass {
-        DpPlan p;
-        int gi, yi, n;
-        size_t rec, slot;
-        double cost;
-    };
-    std::map<DpKey, std::vector<DpClass>> byShape;
-    for (size_t i = 0; i < ng; i++) {
-        const BatchGroup &bg = groups[g0 + i];
-        const Geometry &g = lay[i].hg.g;
-        for (int yi = 0; yi < g.NY; yi++) {
-            // passes of at most 24 layers: the descriptor kernels then keep two
-            // (FP64) or three (32-bit) targets per lane without spilling, which
-            // shortens the stream's largest items (measured: FP64 3.40 -> 2.95 s,
-            // DP32 2.29 -> 2.13 s on the 8,192-pair stream)
-            DpPlan p = dp_shape(g, bg.n, yi, mode, ctx->dp32_tol, 24);
-            // a shared table uses the smallest scale of its bucket, at most a
-            // factor 2 below the class's own: keep the bound within tolerance
-            if (p.fx && 2.0 * p.bound > ctx->dp32_tol) {
-                p.fx = false;
-                if (p.T == 3) p.T = 2;   // three targets per lane exist in 32 bits only
-            }
-            DpKey key{p.fx ? 1 : 0, p.NL, p.YR, p.T, p.fx ? (int)floor(log2(p.scale)) : 0, -1};
-            byShape[key].push_back({p, (int)i, yi, bg.n, (size_t)p.KS * p.RS * 4,
-                                    (size_t)p.x * p.KS * (p.fx ? 4 : 8), (double)p.x * p.KS * p.KS});
-        }
-    }
-    // one launch per key, unless its largest table and its largest count
-    // records together exceed the LDS: then it is split, largest n first,
-    // into launches that fit (every class fits on its own)
     std::map<DpKey, DpBucket> buckets;
-    for (auto &kv : byShape) {
-        std::vector<DpClass> &cl = kv.second;
-        std::sort(cl.begin(), cl.end(), [](const DpClass &u, const DpClass &v) { return u.n > v.n; });
-        const int vb = kv.first.fx ? 4 : 8;
-        const int NLP = (kv.first.NL + 16 / vb - 1) / (16 / vb) * (16 / vb);
-        auto need = [&](int nmax, size_t rec) {
-            return (size_t)align16b((size_t)(nmax + 1) * vb) + align16b(std::max((size_t)8 * NLP * vb, (size_t)nmax)) +
-                   align16b(rec);
-        };
-        int part = -1, nmax = 0;
-        size_t rec = 0;
-        for (const DpClass &c : cl) {
-            if (part < 0 || need(nmax, std::max(rec, c.rec)) > 160 * 1024) {
-                part++;
-                nmax = c.n;
-                rec = 0;
-            }
-            rec = std::max(rec, c.rec);
-            DpKey key = kv.first;
-            key.grp = part;
-            DpBucket &b = buckets[key];
-            if (b.classes.empty()) b.plan = c.p;
-            b.nmax = std::max(b.nmax, c.n);
-            b.rec = std::max(b.rec, c.rec);
-            b.slot = std::max(b.slot, c.slot);
-            if (c.p.fx) b.scale = b.scale == 0.0 ? c.p.scale : std::min(b.scale, c.p.scale);
-            b.classes.push_back({c.cost, {c.gi, c.yi}});
-        }
-    }
+    make_buckets(ctx, groups, g0, lay, mode, buckets);
     // keys run largest first (their longest items start at once), round-robin
     // over the DP streams
     std::vector<std::pair<const DpKey, DpBucket> *> keys;
@@ -824,9 +935,6 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
     size_t nitems = 0, tabs = 0;
     for (auto *kp : keys) {
         DpBucket &b = kp->second;
-        std::sort(b.classes.begin(), b.classes.end(),
-                  [](const std::pair<double, std::pair<int, int>> &u,
-                     const std::pair<double, std::pair<int, int>> &v) { return u.first > v.first; });
         for (auto &c : b.classes) {
             const int gi = c.second.first, yi = c.second.second;
             const int npo = (int)(2 * groups[g0 + gi].idx.size());
@@ -837,12 +945,7 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
             }
         }
         nitems += b.items.size() / 3;
-        DpPlan &p = b.plan;
-        p.scale = b.scale;
-        p.slot_bytes = b.slot;
-        p.groups = true;
-        dp_fit_lds(p, b.nmax, b.rec, ctx->cus);
-        if (p.fx) tabs++;
+        if (b.plan.fx) tabs++;
     }
     std::sort(keys.begin(), keys.end(), [](const std::pair<const DpKey, DpBucket> *u,
                                            const std::pair<const DpKey, DpBucket> *v) {
@@ -856,23 +959,92 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
     for (auto *kp : keys) allitems.insert(allitems.end(), kp->second.items.begin(), kp->second.items.end());
     HIPCHK(hipMemcpyAsync(ctx->gitems.p, allitems.data(), allitems.size() * sizeof(int),
                           hipMemcpyHostToDevice, s));
-    // scratch per DP stream: the largest need among the keys it runs
-    std::vector<size_t> need(kDpStreams, 0);
-    {
-        int k = 0;
-        for (auto *kp : keys) {
-            const DpBucket &b = kp->second;
-            const size_t waves = std::min<size_t>(b.items.size() / 3, (size_t)b.plan.max_waves);
-            const size_t w = (waves + b.plan.WPB - 1) / b.plan.WPB * b.plan.WPB;
-            need[k % kDpStreams] = std::max(need[k % kDpStreams], w * b.plan.slot_bytes);
-            k++;
+    // near-tie recheck of the 32-bit form: FP64 launch keys over every class
+    // of the pass, each with a device list of the items queued for it
+    // (capacity: all items of its classes), per-item flag bits and the
+    // flagged pairs (StreamRecheck)
+    double bound = 0.0;
+    for (auto &kv : buckets) {
+        const DpBucket &b = kv.second;
+        if (!b.plan.fx) continue;
+        for (auto &c : b.classes) {
+            const GroupLayout &L = lay[c.second.first];
+            const int y = c.second.second + 2, x = L.hg.xcnt[c.second.second];
+            bound = std::max(bound, 0.5 * (double)(y + 1) * (double)x /
+                                        (b.plan.scale * (double)groups[g0 + c.second.first].n * log(2.0)));
         }
     }
-    size_t scr = 0;
-    std::vector<size_t> scr_off(kDpStreams);
-    for (int k = 0; k < kDpStreams; k++) {
-        scr_off[k] = scr;
-        scr += align256(need[k]);
+    const bool recheck = bound > 0.0;
+    std::map<DpKey, DpBucket> rbuckets;
+    std::vector<std::pair<const DpKey, DpBucket> *> rkeys;
+    std::vector<int> rcap, rkoff, keyof;
+    StreamRecheck srq;
+    size_t rc_words = 0;
+    int ptotal = 0;
+    if (recheck) {
+        make_buckets(ctx, groups, g0, lay, MICX_MODE_FP64, rbuckets);
+        for (auto &kv : rbuckets) rkeys.push_back(&kv);
+        std::vector<size_t> kbase(ng, 0);
+        size_t nk = 0;
+        for (size_t i = 0; i < ng; i++) {
+            kbase[i] = nk;
+            nk += lay[i].hg.g.NY;
+        }
+        keyof.assign(nk, -1);
+        int koff = 0;
+        for (size_t k = 0; k < rkeys.size(); k++) {
+            int cap = 0;
+            for (auto &c : rkeys[k]->second.classes) {
+                keyof[kbase[c.second.first] + c.second.second] = (int)k;
+                cap += (int)(2 * groups[g0 + c.second.first].idx.size());
+            }
+            rcap.push_back(cap);
+            rkoff.push_back(koff);
+            koff += cap;
+        }
+        size_t fw = 0;
+        std::vector<size_t> fbase(ng);
+        for (size_t i = 0; i < ng; i++) {
+            fbase[i] = fw;
+            ptotal += (int)groups[g0 + i].idx.size();
+            fw += 2 * groups[g0 + i].idx.size() * (size_t)((lay[i].hg.g.NY + 31) / 32);
+        }
+        rc_words = rkeys.size() + 1 + fw;
+        RETCHK(ctx->rcwords.ensure(rc_words * sizeof(unsigned)));
+        RETCHK(ctx->rclist.ensure(std::max<size_t>((size_t)koff * 3, 1) * sizeof(int)));
+        RETCHK(ctx->rcpairs.ensure((size_t)2 * ptotal * sizeof(int)));
+        RETCHK(ctx->rcmeta.ensure((rkeys.size() + nk) * sizeof(int)));
+        int *meta = ctx->rcmeta.as<int>();
+        std::vector<int> hmeta(rkoff);
+        hmeta.insert(hmeta.end(), keyof.begin(), keyof.end());
+        HIPCHK(hipMemcpyAsync(meta, hmeta.data(), hmeta.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        srq.band = 2.0 * bound + 1e-12;
+        srq.kcount = ctx->rcwords.as<int>();
+        srq.pcount = srq.kcount + rkeys.size();
+        srq.klist = ctx->rclist.as<int>();
+        srq.koff = meta;
+        srq.plist = ctx->rcpairs.as<int>();
+        unsigned *flags = (unsigned *)(srq.pcount + 1);
+        for (size_t i = 0; i < ng; i++) {
+            gdev[i].iflag = flags + fbase[i];
+            gdev[i].nyw = (lay[i].hg.g.NY + 31) / 32;
+            gdev[i].keyof = meta + rkeys.size() + kbase[i];
+        }
+        HIPCHK(hipMemcpyAsync(ar + gdev_off, gdev.data(), ng * sizeof(GroupDev), hipMemcpyHostToDevice, s));
+        HIPCHK(launch_zero(ctx->rcwords.p, rc_words, s));
+        // the host tables above are read by the copies: keep them until done
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    // scratch per DP stream: the largest need among the keys it runs (main
+    // and recheck launches run one after the other and share it)
+    std::vector<size_t> scr_off, rscr_off;
+    size_t scr;
+    {
+        std::vector<std::pair<const DpPlan *, size_t>> ml, rl;
+        for (auto *kp : keys) ml.push_back({&kp->second.plan, kp->second.items.size() / 3});
+        scr = stream_scratch(ml, kDpStreams, scr_off);
+        for (size_t k = 0; k < rkeys.size(); k++) rl.push_back({&rkeys[k]->second.plan, (size_t)rcap[k]});
+        scr = std::max(scr, stream_scratch(rl, kDpStreams, rscr_off));
     }
     RETCHK(ctx->scratch.ensure(std::max<size_t>(scr, 1)));
     RETCHK(fork());
@@ -910,9 +1082,43 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
     }
     // statistics into the staging rows, once every DP key is done
     RETCHK(join());
-    HIPCHK(launch_stats_g(gd, (const int2 *)(ar + mstats_off), (int)mstats.size(), s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(launch_stats_g(gd, (const int2 *)(ar + mstats_off), (int)mstats.size(), s,
+                          recheck ? &srq : nullptr));
     micx_profile pp{};
+    if (recheck) {
+        // FP64 re-run of the queued items, key by key, then the flagged pairs'
+        // statistics again
+        hipEvent_t r0 = nullptr, r1 = nullptr;
+        if (ctx->profiling) {
+            HIPCHK(hipEventCreate(&r0));
+            HIPCHK(hipEventCreate(&r1));
+            HIPCHK(hipEventRecord(r0, s));
+        }
+        RETCHK(fork());
+        for (size_t k = 0; k < rkeys.size(); k++) {
+            const DpBucket &b = rkeys[k]->second;
+            HIPCHK(launch_dp_items((const DpGroup *)(ar + tab_off), srq.klist + 3 * (size_t)rkoff[k], rcap[k],
+                                   b.nmax, ctx->xlogx.as<double>(), nullptr,
+                                   ctx->scratch.as<unsigned char>() + rscr_off[k % kDpStreams], b.plan,
+                                   ctx->compat, ctx->dstreams[k % kDpStreams], srq.kcount + k));
+        }
+        RETCHK(join());
+        HIPCHK(launch_stats_g_list(gd, srq.plist, srq.pcount, ptotal, s));
+        if (ctx->profiling) {
+            HIPCHK(hipEventRecord(r1, s));
+            std::vector<int> h(rkeys.size() + 1);
+            HIPCHK(hipMemcpyAsync(h.data(), srq.kcount, h.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (size_t k = 0; k < rkeys.size(); k++) pp.recheck_items += h[k];
+            pp.recheck_pairs = h[rkeys.size()];
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, r0, r1));
+            pp.recheck_ms = ms;
+            hipEventDestroy(r0);
+            hipEventDestroy(r1);
+        }
+    }
+    HIPCHK(hipStreamSynchronize(s));
     if (ctx->profiling) {
         for (size_t k = 0; k + 1 < ev.size(); k += 2) {
             float ms = 0.f;

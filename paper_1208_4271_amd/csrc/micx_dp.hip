@@ -208,7 +208,7 @@ hipError_t launch_fxtable(int n, const DpPlan &p, const double *xlogx, uint32_t 
 hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry &g,
                      PairSource ps, int npairs, const ItemBuffers &ib, const double *xlogx,
                      const uint32_t *fxtab, void *scratch, int yi, const DpPlan &p,
-                     hipStream_t s) {
+                     hipStream_t s, const int *ilist, const int *icount, int cap) {
     DpArgs a;
     a.n = rt.n; a.NY = g.NY; a.KSUM = g.KSUM; a.ASUM = g.ASUM;
     a.yi = yi; a.x = p.x; a.RS = p.RS; a.KS = p.KS;
@@ -221,6 +221,8 @@ hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry
     a.scratch = scratch; a.slot_bytes = p.slot_bytes;
     a.lds_L = p.lds_L; a.lds_stage = p.lds_stage; a.lds_wave = p.lds_wave;
     a.groups = nullptr; a.gitems = nullptr; a.compat = g.compat;
+    a.ilist = ilist; a.icount = icount;
+    if (ilist) a.nitems = std::min(a.nitems, cap);
     dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T);
     if (!k) return hipErrorInvalidValue;
     // the attribute is the whole LDS budget, the same for every caller (plans
@@ -238,7 +240,7 @@ hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry
 
 hipError_t launch_dp_items(const DpGroup *groups, const int *gitems, int nitems, int nmax,
                            const double *xlogx, const uint32_t *fxtab, void *scratch,
-                           const DpPlan &p, int compat, hipStream_t s) {
+                           const DpPlan &p, int compat, hipStream_t s, const int *icount) {
     DpArgs a = {};
     a.compat = compat;
     a.n = nmax;
@@ -249,6 +251,7 @@ hipError_t launch_dp_items(const DpGroup *groups, const int *gitems, int nitems,
     a.xlogx = xlogx; a.fxtab = fxtab; a.inv_scale = p.fx ? 1.0 / p.scale : 0.0;
     a.scratch = scratch; a.slot_bytes = p.slot_bytes;
     a.lds_L = p.lds_L; a.lds_stage = p.lds_stage; a.lds_wave = p.lds_wave;
+    a.ilist = nullptr; a.icount = icount;
     dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T, true);
     if (!k) return hipErrorInvalidValue;
     if (p.lds > 160 * 1024) return hipErrorInvalidValue;

@@ -67,6 +67,10 @@ struct DpArgs {
     const int *gitems;
     int compat;                  // MICX_COMPAT_* flags (MICX_COMPAT_NORM_BY_Y acts here)
     int lds_L, lds_stage, lds_wave;
+    // the FP64 recheck of near-tied items: a list of the class's items
+    // (pair*2+orientation; the GR instances take gitems) and its length, both
+    // in device memory, or null: every item
+    const int *ilist, *icount;
 };
 
 template <class V> struct DpVal;
@@ -143,7 +147,9 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
     const int gw = blockIdx.x * wpb + wv, nw = gridDim.x * wpb;
     V *G = (V *)((unsigned char *)a.scratch + (size_t)gw * a.slot_bytes);
 
-    for (int wi = gw; wi < a.nitems; wi += nw) {
+    int nitems = a.nitems;
+    if (a.icount) nitems = min(nitems, __builtin_amdgcn_readfirstlane(*a.icount));
+    for (int wi = gw; wi < nitems; wi += nw) {
         // the item: its sample count n, columns x, G-table and count-record
         // strides, superclump count K, rows yhat and buffers
         int n, x, KS, RS, K, yh, ycls;
@@ -171,7 +177,8 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
             l16 = gr.lab16 != 0;
             Aout = gr.A + (size_t)po * gr.ASUM + gr.aoff[yi];
         } else {
-            const int po = wi, yi = a.yi, NY = a.NY;
+            const int po = a.ilist ? __builtin_amdgcn_readfirstlane(a.ilist[wi]) : wi;
+            const int yi = a.yi, NY = a.NY;
             const int o = po & 1, pl = po >> 1;
             int pi, pj;
             pair_of(a.ps, pl, pi, pj);

@@ -19,7 +19,7 @@ template <class V, int NL, int YR, int T, bool GR>
 constexpr bool dp_built() {
     if (T == 1) return true;
     if (NL < 20) return false;
-    if (std::is_same<V, double>::value) return T == 2 && (GR ? NL <= 24 : !(NL >= 36 && YR >= 5));
+    if (std::is_same<V, double>::value) return T == 2 && (GR ? NL <= 24 : !(NL >= 36 && YR >= 4));
     if (T == 2) return true;
     return GR ? (NL <= 24 || (NL <= 28 && YR <= 3)) : true;
 }

@@ -73,6 +73,24 @@ struct ItemBuffers {
     double *A = nullptr;   // normalised scores, ASUM per (pair, orientation)
 };
 
+// Near-tie recheck of the 32-bit form.  Its entries are within a bound of
+// the FP64 ones, which keeps MIC, MAS and MEV within tolerance but can change
+// which cell MCN selects when cells lie within that bound of MIC (exact ties
+// above all, which rounding at different fixed-point scales splits).  The
+// statistics kernel flags such a pair and queues the items behind every cell
+// within `band` of its MIC, per row count, for an FP64 re-run of their DP;
+// the flagged pairs' statistics are then computed again.
+struct Recheck {
+    double band = 0.0;          // twice the largest entry bound plus the MCN slack; 0: no flags
+    unsigned *iflag = nullptr;  // [pair*2+orientation][nyw]: one bit per row count, item queued
+    int nyw = 0;                // 32-bit words per (pair, orientation)
+    int *ilist = nullptr;       // [y-2][icap]: queued items (pair*2+orientation) per row count
+    int icap = 0;               // capacity per row count (2 * pairs of the batch)
+    int *icount = nullptr;      // [y-2]: items queued per row count
+    int *plist = nullptr;       // flagged pairs (batch-local index)
+    int *pcount = nullptr;      // number of flagged pairs
+};
+
 // One group of a batch stream on the device (pairs sharing n, alpha and c):
 // its geometry and item buffers, for DP launches that mix groups.  The
 // group's variables are rows 2i and 2i+1 for its pair i.
@@ -103,6 +121,25 @@ struct GroupDev {
     const int32_t *pairs = nullptr;  // (2i, 2i+1) per pair
     double *out = nullptr;           // 4 doubles per pair
     int compat = 0;                  // MICX_COMPAT_* flags
+    // near-tie recheck (see Recheck): one bit per (pair*2+orientation, y-2)
+    // item, nyw words per (pair, orientation), and the FP64 recheck launch of
+    // each row count (keyof[y-2])
+    unsigned *iflag = nullptr;
+    int nyw = 0;
+    const int *keyof = nullptr;
+};
+
+// Near-tie recheck of a batch stream pass: per FP64 launch key k, the queued
+// items (3 ints each: group, y-2, pair*2+orientation) at klist + 3*koff[k],
+// kcount[k] of them; the flagged pairs as (group, pair) at plist, pcount of
+// them.  band as in Recheck.
+struct StreamRecheck {
+    double band = 0.0;
+    int *klist = nullptr;
+    const int *koff = nullptr;
+    int *kcount = nullptr;
+    int *plist = nullptr;
+    int *pcount = nullptr;
 };
 
 // Fused per-group stages: map[b] = (group, index of the block inside the
@@ -113,7 +150,11 @@ hipError_t launch_rank_g(const GroupDev *G, const int2 *map, int blocks, int nma
                          int *status, hipStream_t s);
 hipError_t launch_equip_g(const GroupDev *G, const int2 *map, int blocks, int nmax, hipStream_t s);
 hipError_t launch_part_g(const GroupDev *G, const int2 *map, int blocks, hipStream_t s);
-hipError_t launch_stats_g(const GroupDev *G, const int2 *map, int blocks, hipStream_t s);
+hipError_t launch_stats_g(const GroupDev *G, const int2 *map, int blocks, hipStream_t s,
+                          const StreamRecheck *flag = nullptr, const int *status = nullptr);
+// statistics again for the flagged pairs of a pass (after the FP64 recheck)
+hipError_t launch_stats_g_list(const GroupDev *G, const int *plist, const int *pcount, int cap,
+                               hipStream_t s);
 
 // Pair source for a batch: either an explicit list (pairs != null) or the
 // row-major upper triangle starting at global pair index p0.
@@ -139,17 +180,30 @@ void dp_fit_lds(DpPlan &p, int nmax, size_t rec_bytes, int cus);
 // (group, y-2, pair*2+orientation); the plan's shape, scale and LDS split
 // cover every item; scratch holds min(nitems, p.max_waves) G tables of
 // p.slot_bytes.
+// icount (device, may be null): only the first min(nitems, *icount) items.
 hipError_t launch_dp_items(const DpGroup *groups, const int *gitems, int nitems, int nmax,
                            const double *xlogx, const uint32_t *fxtab, void *scratch,
-                           const DpPlan &p, int compat, hipStream_t s);
+                           const DpPlan &p, int compat, hipStream_t s, const int *icount = nullptr);
 hipError_t launch_fxtable(int n, const DpPlan &p, const double *xlogx, uint32_t *tab,
                           hipStream_t s);
+// ilist/icount (device, may be null): run only the items ilist[0..*icount)
+// (pair*2+orientation) of the class, at most `cap` of them.
 hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry &g,
                      PairSource ps, int npairs, const ItemBuffers &ib, const double *xlogx,
                      const uint32_t *fxtab, void *scratch, int yi, const DpPlan &p,
-                     hipStream_t s);
+                     hipStream_t s, const int *ilist = nullptr, const int *icount = nullptr,
+                     int cap = 0);
+// Statistics of a batch.  flag (may be null): queue near-tied pairs and
+// their items for the FP64 recheck.  plist/pcount (device, may be null): only
+// the pairs plist[0..*pcount).  status (device, may be null): nothing is
+// written while the call's status word is set.
 hipError_t launch_stats(const Geometry &g, int npairs, const ItemBuffers &ib, double *out,
-                        double *M, double *Axy, double *Ayx, hipStream_t s);
+                        double *M, double *Axy, double *Ayx, hipStream_t s,
+                        const Recheck *flag = nullptr, const int *plist = nullptr,
+                        const int *pcount = nullptr, const int *status = nullptr);
+// Clears nwords 32-bit words (a kernel, so that captured graphs hold no
+// memset nodes).
+hipError_t launch_zero(void *p, size_t nwords, hipStream_t s);
 hipError_t launch_xlogx(int n, double *xlogx, hipStream_t s);
 hipError_t launch_gather(const void *src, int esize, const int64_t *offs, int nv, int n, void *dst,
                          hipStream_t s);

@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "micx_device.h"
 
 namespace micx {
@@ -446,7 +448,40 @@ struct StatsArgs {
     const int *aoff;
     const double *A;
     double *out, *M, *Axy, *Ayx;
+    Recheck rc;                  // near-tie flags (rc.band > 0) of the 32-bit form
+    const int *plist, *pcount;   // only these batch-local pairs (the recheck pass), or null
+    const int *status;           // nothing is written while *status != 0, or null
+    // batch streams: flags go to the pass's FP64 launch keys instead (then
+    // srq->band > 0 and rc.band = 0)
+    const StreamRecheck *srq;
+    const GroupDev *grp;
+    int gi;
 };
+
+// Queues item (po, yi) for the FP64 recheck, once.
+__device__ __forceinline__ void queue_item(const Recheck &rc, int po, int yi) {
+    const unsigned bit = 1u << (yi & 31);
+    const unsigned old = atomicOr(rc.iflag + (size_t)po * rc.nyw + (yi >> 5), bit);
+    if (!(old & bit)) {
+        const int slot = atomicAdd(rc.icount + yi, 1);
+        rc.ilist[(size_t)yi * rc.icap + slot] = po;
+    }
+}
+
+// The same for an item of group gi of a batch stream pass: its descriptor
+// goes to the FP64 launch key of its row count.
+__device__ __forceinline__ void queue_item_g(const StreamRecheck &q, const GroupDev &g, int gi, int po,
+                                             int yi) {
+    const unsigned bit = 1u << (yi & 31);
+    const unsigned old = atomicOr(g.iflag + (size_t)po * g.nyw + (yi >> 5), bit);
+    if (!(old & bit)) {
+        const int k = g.keyof[yi];
+        int *d = q.klist + 3 * ((size_t)q.koff[k] + atomicAdd(q.kcount + k, 1));
+        d[0] = gi;
+        d[1] = yi;
+        d[2] = po;
+    }
+}
 
 __device__ __forceinline__ void stats_body(const StatsArgs &a, int pl) {
     const double *A0 = a.A + (size_t)(2 * pl) * a.ASUM;
@@ -471,6 +506,46 @@ __device__ __forceinline__ void stats_body(const StatsArgs &a, int pl) {
             if (xx == 2 || yy == 2) mev = fmax(mev, v);
             if (v >= mic - 1e-12) mcn = fmin(mcn, log2((double)(xx * yy)));
         }
+    // Near-tie flag (32-bit form).  Every entry is within bound d of its FP64
+    // value, so a cell whose FP64 value reaches MIC - 1e-12 has a 32-bit
+    // value of at least MIC - band (band = 2d + 1e-12).  When those cells do
+    // not all share one product xy, MCN is not settled by the 32-bit values:
+    // the pair is flagged and the items behind each such cell (both
+    // orientations) are queued for an FP64 re-run.  Cells below the band stay
+    // below MIC - 1e-12 in FP64 as well.
+    const double band = a.srq ? a.srq->band : a.rc.band;
+    if (band > 0.0) {
+        const double lo = mic - band;
+        int pmin = 0x7fffffff, pmax = 0;
+        for (int yy = 2; yy <= Bh; yy++)
+            for (int xx = 2; xx * yy <= a.B; xx++)
+                if (Mxy(xx, yy) >= lo) {
+                    pmin = min(pmin, xx * yy);
+                    pmax = max(pmax, xx * yy);
+                }
+        if (pmin != pmax) {
+            if (a.srq) {
+                const int slot = atomicAdd(a.srq->pcount, 1);
+                a.srq->plist[2 * slot] = a.gi;
+                a.srq->plist[2 * slot + 1] = pl;
+            } else {
+                a.rc.plist[atomicAdd(a.rc.pcount, 1)] = pl;
+            }
+            const bool ci = (a.compat & MICX_COMPAT_COMBINE_INDEX) != 0;
+            for (int yy = 2; yy <= Bh; yy++)
+                for (int xx = 2; xx * yy <= a.B; xx++)
+                    if (Mxy(xx, yy) >= lo) {
+                        const int y1 = (ci ? yy : xx) - 2;
+                        if (a.srq) {
+                            queue_item_g(*a.srq, *a.grp, a.gi, 2 * pl, yy - 2);
+                            queue_item_g(*a.srq, *a.grp, a.gi, 2 * pl + 1, y1);
+                        } else {
+                            queue_item(a.rc, 2 * pl, yy - 2);
+                            queue_item(a.rc, 2 * pl + 1, y1);
+                        }
+                    }
+        }
+    }
     double *o = a.out + (size_t)4 * pl;
     o[0] = mic; o[1] = mas; o[2] = mev; o[3] = mcn;
     if (a.M) {
@@ -487,8 +562,19 @@ __device__ __forceinline__ void stats_body(const StatsArgs &a, int pl) {
 }
 
 __global__ void k_stats(StatsArgs a) {
-    const int pl = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pl < a.npairs) stats_body(a, pl);
+    if (a.status && *a.status) return;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a.plist) {
+        if (k < min(*a.pcount, a.npairs)) stats_body(a, a.plist[k]);
+    } else if (k < a.npairs) {
+        stats_body(a, k);
+    }
+}
+
+__global__ void k_zero(unsigned *p, size_t nwords) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
 }
 
 // ------------------------------------------------------------------- k_work
@@ -585,11 +671,22 @@ hipError_t launch_part(const RankTables &rt, const EquipTables &et, const Geomet
 }
 
 hipError_t launch_stats(const Geometry &g, int npairs, const ItemBuffers &ib, double *out,
-                        double *M, double *Axy, double *Ayx, hipStream_t s) {
+                        double *M, double *Axy, double *Ayx, hipStream_t s, const Recheck *flag,
+                        const int *plist, const int *pcount, const int *status) {
     StatsArgs a;
     a.npairs = npairs; a.B = g.B; a.NY = g.NY; a.W = g.W; a.ASUM = g.ASUM;
     a.aoff = g.aoff; a.A = ib.A; a.out = out; a.M = M; a.Axy = Axy; a.Ayx = Ayx; a.compat = g.compat;
+    a.rc = flag ? *flag : Recheck();
+    a.plist = plist; a.pcount = pcount; a.status = status;
+    a.srq = nullptr; a.grp = nullptr; a.gi = 0;
     hipLaunchKernelGGL(k_stats, dim3((npairs + 127) / 128), dim3(128), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *p, size_t nwords, hipStream_t s) {
+    if (nwords == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((nwords + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, (unsigned *)p, nwords);
     return hipGetLastError();
 }
 
@@ -687,17 +784,34 @@ __global__ __launch_bounds__(64) void k_part_g(const GroupDev *G, const int2 *ma
     else part_dispatch<false>(a, m.y, tile);
 }
 
-// 64 pairs per block: map[b].y is the group's first pair of the block
-__global__ void k_stats_g(const GroupDev *G, const int2 *map) {
-    const int2 m = map[blockIdx.x];
-    const GroupDev &g = G[m.x];
-    const int pl = m.y + threadIdx.x;
-    if (pl >= g.npairs) return;
+__device__ __forceinline__ void stats_g_pair(const GroupDev *G, int gi, int pl, const StreamRecheck *q) {
+    const GroupDev &g = G[gi];
     StatsArgs a;
     a.npairs = g.npairs; a.B = g.B; a.NY = g.NY; a.W = g.W; a.ASUM = g.ASUM;
     a.aoff = g.aoff; a.A = g.A; a.out = g.out; a.M = nullptr; a.Axy = nullptr; a.Ayx = nullptr;
     a.compat = g.compat;
+    a.rc = Recheck();
+    a.plist = nullptr; a.pcount = nullptr; a.status = nullptr;
+    a.srq = q && q->band > 0.0 ? q : nullptr;
+    a.grp = &g;
+    a.gi = gi;
     stats_body(a, pl);
+}
+
+// 64 pairs per block: map[b].y is the group's first pair of the block
+__global__ void k_stats_g(const GroupDev *G, const int2 *map, StreamRecheck q, const int *status) {
+    if (status && *status) return;
+    const int2 m = map[blockIdx.x];
+    const int pl = m.y + threadIdx.x;
+    if (pl >= G[m.x].npairs) return;
+    stats_g_pair(G, m.x, pl, &q);
+}
+
+// the flagged pairs of a pass, (group, pair) each
+__global__ void k_stats_g_list(const GroupDev *G, const int *plist, const int *pcount, int cap) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= min(*pcount, cap)) return;
+    stats_g_pair(G, plist[2 * k], plist[2 * k + 1], nullptr);
 }
 
 hipError_t launch_gather_g(const void *data, int esize, const GroupDev *G, const int2 *map, int blocks,
@@ -729,8 +843,17 @@ hipError_t launch_part_g(const GroupDev *G, const int2 *map, int blocks, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_stats_g(const GroupDev *G, const int2 *map, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_stats_g, dim3(blocks), dim3(64), 0, s, G, map);
+hipError_t launch_stats_g(const GroupDev *G, const int2 *map, int blocks, hipStream_t s,
+                          const StreamRecheck *flag, const int *status) {
+    const StreamRecheck q = flag ? *flag : StreamRecheck();
+    hipLaunchKernelGGL(k_stats_g, dim3(blocks), dim3(64), 0, s, G, map, q, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats_g_list(const GroupDev *G, const int *plist, const int *pcount, int cap,
+                               hipStream_t s) {
+    if (cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stats_g_list, dim3((cap + 127) / 128), dim3(128), 0, s, G, plist, pcount, cap);
     return hipGetLastError();
 }
 
