@@ -254,6 +254,37 @@ int micx_set_dp32_tolerance(micx_ctx *ctx, double tol);
  * Returns MICX_EINVAL for unknown bits. */
 int micx_set_compat(micx_ctx *ctx, int flags);
 
+/* Size of the device array behind micx_score_noalloc (per device, held
+ * until the process ends). */
+#define MICX_NOALLOC_BYTES (32u << 20)
+
+/* micx_compute_score for callers that cannot allocate (code under HIP graph
+ * capture, serving loops or harnesses that forbid allocation): the same
+ * score of one pair, with inputs and outputs in device memory, and no
+ * allocation of any kind -- every intermediate buffer lives in one
+ * file-scope device array of MICX_NOALLOC_BYTES (32 MiB) per device.
+ * x_dev, y_dev: DEVICE pointers to n elements each of type dtype
+ *        (MICX_F32/F64/I32), read only.
+ * stats_dev: DEVICE pointer to 4 doubles: MIC, MAS, MEV, MCN.
+ * mats_dev: DEVICE pointer to 3*W*W doubles (M, then Axy, then Ayx, each laid
+ *        out as in micx_score, W = floor(B/2) - 1), or NULL.
+ * status_dev: DEVICE pointer to one int that receives the call's device-side
+ *        result once its work completes (MICX_OK, or MICX_ENONFINITE for a
+ *        NaN or infinity in the input, in which case stats_dev and mats_dev
+ *        are left untouched), or NULL.
+ * stream: hipStream_t (as void*) or NULL.  The work is queued on it and the
+ *        call returns without waiting.  All calls on one device share its
+ *        array, which keeps the last call's contents (each call clears what
+ *        it needs first): calls that overlap on one device race, so order
+ *        them (one stream, or events).
+ * Errors found before any work is queued: MICX_EINVAL (null pointer, bad
+ * alpha/c/mode/dtype, n < 2), MICX_ESMALLN, MICX_ETOOBIG (n > MICX_MAX_N, or
+ * a problem whose buffers exceed MICX_NOALLOC_BYTES -- alpha = 0.6 fits up
+ * to n = MICX_MAX_N), MICX_EDEVICE. */
+int micx_score_noalloc(micx_ctx *ctx, const void *x_dev, const void *y_dev, int dtype, int n,
+                       double alpha, double c, int mode, double *stats_dev, double *mats_dev,
+                       int *status_dev, void *stream);
+
 /* Message for a return code (static string). */
 const char *micx_strerror(int code);
 

@@ -44,8 +44,11 @@ EXPORTS = (
     "micx_compute_score", "micx_mic", "micx_mas", "micx_mev", "micx_mcn", "micx_free_score",
     "micx_allpairs", "micx_pairs", "micx_batch", "micx_debug_item", "micx_strerror",
     "micx_set_profiling", "micx_get_profile", "micx_set_dp32_tolerance", "micx_set_compat",
-    "micx_pearson",
+    "micx_pearson", "micx_score_noalloc",
 )
+
+# Size of the device array behind micx_score_noalloc (include/micx.h).
+NOALLOC_BYTES = 32 << 20
 
 
 class MicxError(RuntimeError):
@@ -117,6 +120,9 @@ def load_library():
     lib.micx_pearson.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_int32),
                                  ctypes.c_int64, vp, vp, vp]
     lib.micx_pearson.restype = ctypes.c_int
+    lib.micx_score_noalloc.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_int, vp, vp, vp, vp]
+    lib.micx_score_noalloc.restype = ctypes.c_int
     lib.micx_debug_item.argtypes = [vp, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_int, ctypes.c_int, ip, ip, ip, ip, ip]
     lib.micx_debug_item.restype = ctypes.c_int
@@ -323,6 +329,26 @@ def master(X, i: int, alpha: float = 0.6, c: float = 15.0, mode: int = MODE_FP64
     if not 0 <= i < m:
         raise ValueError("master variable out of range")
     return pairs(X, [(i, j) for j in range(m) if j != i], alpha, c, mode, out, stream)
+
+
+def score_noalloc(x, y, alpha: float, c: float, mode: int, stats, mats=None, status=None,
+                  stream=None):
+    """micx_score_noalloc: the score of one pair of 1-D CUDA tensors x, y
+    (float32/float64/int32, same length) into caller-owned CUDA tensors:
+    stats (4 float64), mats (3*W*W float64: M, Axy, Ayx) or None, status
+    (1 int32: the device-side result) or None.  Queued on the stream; no
+    allocation.  Returns the host-side return code (raises on error)."""
+    if x.dtype != y.dtype or x.numel() != y.numel() or not (x.is_cuda and y.is_cuda):
+        raise ValueError("x and y must be CUDA tensors of one dtype and length")
+    dt = _DTYPES.get(str(x.dtype))
+    if dt is None:
+        raise ValueError("dtype must be float32, float64 or int32")
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    rc = load_library().micx_score_noalloc(context(x.device.index or 0), ptr(x), ptr(y), dt, x.numel(),
+                                           float(alpha), float(c), int(mode), ptr(stats), ptr(mats),
+                                           ptr(status), _stream_ptr(stream))
+    _check(rc, "micx_score_noalloc")
+    return rc
 
 
 def debug_item(x, y, alpha: float, c: float, orient: int, ry: int, device: int = 0):

@@ -112,9 +112,24 @@ extern "C" int micx_ctx_create(micx_ctx **ctx, int device) {
         return MICX_EDEVICE;
     }
     c->cus = device_cus(device);
+    // the no-allocation entry point's array: its address on this device
+    const int rc = noalloc_init(device);
+    if (rc != MICX_OK) {
+        delete c;
+        return rc;
+    }
     *ctx = c;
     return MICX_OK;
 }
+
+namespace micx {
+void ctx_params(const micx_ctx *ctx, int *device, int *cus, int *compat, double *tol) {
+    *device = ctx->device;
+    *cus = ctx->cus;
+    *compat = ctx->compat;
+    *tol = ctx->dp32_tol;
+}
+}  // namespace micx
 
 extern "C" void micx_ctx_destroy(micx_ctx *c) {
     if (!c) return;

@@ -3,9 +3,7 @@
 // tables of the 32-bit form.
 #include <math.h>
 
-#include <map>
 #include <mutex>
-#include <tuple>
 
 #include "micx_dp_kernel.h"
 
@@ -136,28 +134,74 @@ DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol) 
 
 namespace {
 
-// Resident workgroups per CU for (kernel, workgroup size, LDS bytes), asked
-// of the runtime once and remembered.
-int cached_occupancy(dp_kernel_t k, int threads, int lds) {
-    static std::mutex mu;
-    static std::map<std::tuple<const void *, int, int>, int> memo;
-    const auto key = std::make_tuple((const void *)k, threads, lds);
-    {
-        std::lock_guard<std::mutex> lock(mu);
-        auto it = memo.find(key);
-        if (it != memo.end()) return it->second;
-    }
-    int occ = 0;
-    if (hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) !=
-            hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k, threads, lds) != hipSuccess)
-        occ = 0;
-    std::lock_guard<std::mutex> lock(mu);
-    memo[key] = occ;
-    return occ;
+// Fixed-size open-addressing memo: no heap allocation on any call path (the
+// no-allocation entry point plans launches through here too).
+struct OccEntry {
+    const void *k;
+    int device, threads, lds, occ;
+};
+constexpr int kOccSlots = 4096;
+OccEntry g_occ[kOccSlots];
+std::mutex g_occ_mu;
+
+size_t occ_hash(const void *k, int device, int threads, int lds) {
+    size_t h = (size_t)(uintptr_t)k * 0x9e3779b97f4a7c15ull;
+    h ^= ((size_t)device * 0x85ebca6bu) ^ ((size_t)threads << 20) ^ (size_t)lds * 0xc2b2ae35u;
+    return (h ^ (h >> 29)) & (kOccSlots - 1);
 }
 
+// Resident workgroups per CU for (kernel, workgroup size, LDS bytes) on the
+// current device, asked of the runtime once and remembered.
+int cached_occupancy(dp_kernel_t k, int threads, int lds) {
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lock(g_occ_mu);
+    size_t h = occ_hash((const void *)k, device, threads, lds);
+    for (int probe = 0; probe < kOccSlots; probe++, h = (h + 1) & (kOccSlots - 1)) {
+        OccEntry &e = g_occ[h];
+        if (e.k == (const void *)k && e.device == device && e.threads == threads && e.lds == lds) return e.occ;
+        if (e.k == nullptr) {
+            int occ = 0;
+            if (ensure_lds_attr((const void *)k) != hipSuccess ||
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k, threads, lds) != hipSuccess)
+                occ = 0;
+            e = OccEntry{(const void *)k, device, threads, lds, occ};
+            return occ;
+        }
+    }
+    return 0;   // table full: no occupancy figure (the LDS cap alone applies)
+}
+
+// Kernels whose dynamic-LDS limit is set, per device (same memo scheme).
+struct AttrEntry {
+    const void *k;
+    int device;
+};
+AttrEntry g_attr[kOccSlots];
+std::mutex g_attr_mu;
+
 }  // namespace
+
+// Sets a kernel's dynamic-LDS limit to the whole 160 KB budget, once per
+// kernel and device (the same value for every caller, so launches of one
+// kernel from several threads agree).
+hipError_t ensure_lds_attr(const void *k) {
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_attr_mu);
+    size_t h = occ_hash(k, device, 0, 0);
+    for (int probe = 0; probe < kOccSlots; probe++, h = (h + 1) & (kOccSlots - 1)) {
+        AttrEntry &a = g_attr[h];
+        if (a.k == k && a.device == device) return hipSuccess;
+        if (a.k == nullptr) {
+            e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            if (e == hipSuccess) a = AttrEntry{k, device};
+            return e;
+        }
+    }
+    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
 
 // LDS split of a DP launch: the L table (nmax+1 values), then per wavefront
 // a staging buffer (SB sources x NLP layers, at least nmax bytes for the
@@ -225,11 +269,8 @@ hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry
     if (ilist) a.nitems = std::min(a.nitems, cap);
     dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T);
     if (!k) return hipErrorInvalidValue;
-    // the attribute is the whole LDS budget, the same for every caller (plans
-    // of different sizes may launch one kernel from several threads)
     if (p.lds > 160 * 1024) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024);
+    hipError_t e = ensure_lds_attr((const void *)k);
     if (e != hipSuccess) return e;
     const int waves_needed = a.nitems;
     const int waves = std::min(waves_needed, p.max_waves);
@@ -255,8 +296,7 @@ hipError_t launch_dp_items(const DpGroup *groups, const int *gitems, int nitems,
     dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T, true);
     if (!k) return hipErrorInvalidValue;
     if (p.lds > 160 * 1024) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024);
+    hipError_t e = ensure_lds_attr((const void *)k);
     if (e != hipSuccess) return e;
     const int waves = std::min(nitems, p.max_waves);
     const int blocks = (waves + p.WPB - 1) / p.WPB;

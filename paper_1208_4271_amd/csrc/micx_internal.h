@@ -215,5 +215,13 @@ hipError_t launch_work(const EquipTables &et, const Geometry &g, PairSource ps, 
                        const ItemBuffers &ib, unsigned long long *counters, hipStream_t s);
 
 int device_cus(int device);
+// Sets a kernel's dynamic-LDS limit to the whole 160 KB, once per kernel and
+// device.
+hipError_t ensure_lds_attr(const void *k);
+
+// A context's device, compute units, compatibility flags and DP32 tolerance.
+void ctx_params(const micx_ctx *ctx, int *device, int *cus, int *compat, double *tol);
+// Resolves the no-allocation scratch array's address on `device` (current).
+int noalloc_init(int device);
 
 }  // namespace micx

@@ -638,10 +638,8 @@ hipError_t launch_rank(const void *X, int dtype, int m, int n, RankTables &rt, i
     while (N2 < n) N2 <<= 1;
     const size_t lds = (size_t)N2 * (8 + 4 + 4);
     const int threads = N2 >= 1024 ? 1024 : (N2 < 64 ? 64 : N2);
-    // the attribute is the whole LDS budget, the same for every caller
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void *)k_rank,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipError_t e = ensure_lds_attr((const void *)k_rank);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rank, dim3(m), dim3(threads), lds, s, X, dtype, m, n, N2, rt.perm,
                        rt.gsize, rt.grank, status);
@@ -826,8 +824,7 @@ hipError_t launch_rank_g(const GroupDev *G, const int2 *map, int blocks, int nma
     while (N2 < nmax) N2 <<= 1;
     const size_t lds = (size_t)N2 * (8 + 4 + 4);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void *)k_rank_g,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipError_t e = ensure_lds_attr((const void *)k_rank_g);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rank_g, dim3(blocks), dim3(1024), lds, s, G, map, dtype, status);
     return hipGetLastError();
