@@ -58,9 +58,11 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="pairs timed on the CPU oracle (0 disables the baseline)")
     ap.add_argument("--cpu-threads", type=int, default=0)
-    ap.add_argument("--sweep", action="store_true",
-                    help="also run the grid-bound scaling sweep (uniform random data, "
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the grid-bound scaling sweep (uniform random data, "
                          "alpha in {0.5, 0.6, 0.7}, growing n)")
+    ap.add_argument("--no-counts", action="store_true",
+                    help="skip the RNA-seq-shaped counts workload (2000 x 1340 int32)")
     ap.add_argument("--no-stream", action="store_true",
                     help="skip the uneven pair-stream leg (micx_batch, 8,192 pairs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -69,32 +71,66 @@ def parse():
     return ap.parse_args()
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def pair_index(i, j, m):
     return i * m - i * (i + 1) // 2 + (j - i - 1)
 
 
 def run_form(micx, Xd, out, stream, mode, alpha, c, steps, warmup, label):
-    """Time `steps` micx_allpairs calls of one numeric form, then one
-    instrumented call.  Returns (ms_per_step, profile, host copy of the output)."""
+    """Time one numeric form of micx_allpairs.  The first call runs eagerly
+    (and sizes the workspace), the second captures the call into a HIP graph,
+    every later one replays it: those two are timed on their own, then
+    max(warmup - 2, 0) untimed replays, then `steps` timed replays (each
+    bracketed by device synchronisation), then one instrumented eager call.
+    Returns (ms_per_step, per-step times, first/capture times, profile, host
+    copy of the output)."""
     import torch
-    for w in range(warmup):
-        micx.allpairs(Xd, alpha, c, mode, out=out, stream=stream)
+
+    def one():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        micx.allpairs(Xd, alpha, c, mode, out=out, stream=stream, wait=False)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3
+
+    first_ms = one()
+    print("bench: %s first (eager) call done" % label, file=sys.stderr, flush=True)
+    capture_ms = one()
+    print("bench: %s capture call done" % label, file=sys.stderr, flush=True)
+    for w in range(max(warmup - 2, 0)):
+        one()
         print("bench: %s warmup %d done" % (label, w), file=sys.stderr, flush=True)
+    times = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
-        micx.allpairs(Xd, alpha, c, mode, out=out, stream=stream)
+        ts = time.perf_counter()
+        micx.allpairs(Xd, alpha, c, mode, out=out, stream=stream, wait=False)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - ts) * 1e3)
         print("bench: %s step %d done" % (label, s), file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / max(steps, 1)
-    # one more call with the library's instrumentation on: DP kernel time from
-    # HIP events recorded on the launch stream, algorithmic work from the items
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
+    rc = micx.status()
+    if rc != micx.MICX_OK:
+        raise RuntimeError("allpairs device status %d" % rc)
+    # one more call with the library's instrumentation on (eager): DP kernel
+    # time from HIP events recorded on the launch stream, algorithmic work
+    # from the items
     micx.set_profiling(True)
     micx.allpairs(Xd, alpha, c, mode, out=out, stream=stream)
     prof = micx.get_profile()
     micx.set_profiling(False)
-    return ms_per_step, prof, out.cpu().numpy()
+    return ms_per_step, times, (first_ms, capture_ms), prof, out.cpu().numpy()
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dp_u32_allpairs_m1000_n1340_dp32_traffic.md")
@@ -157,11 +193,12 @@ def parity_of(got, ref):
             "max_dMEV": float(d[:, 2].max()), "mcn_mismatch": int((d[:, 3] > 1e-9).sum())}
 
 
-def stream_leg(micx):
+def stream_leg(micx, steps=3):
     """The uneven stream (8,192 independent pairs, n log-uniform in [50, 8000],
     alpha in {0.55, 0.6, 0.75}, c in {5, 15}) through micx_batch: one warm-up,
-    then one timed call per form.  Returns (leg, results per form, inputs);
-    the CPU-oracle leg adds parity on a seeded sample (stream_parity)."""
+    then `steps` timed calls per form (median reported), then one
+    instrumented call.  Returns (leg, results per form, inputs); the
+    CPU-oracle leg adds parity on a seeded sample (stream_parity)."""
     import torch
     import workloads
     data, offx, offy, ns, alphas, cs = workloads.uneven_stream()
@@ -173,13 +210,25 @@ def stream_leg(micx):
            "data": "synthetic"}
     hosts = {}
     for form, mode in (("dp32", micx.MODE_DP32), ("fp64", micx.MODE_FP64)):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        micx.batch(dd, offx, offy, ns, alphas, cs, mode=mode, out=out)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        times = []
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            micx.batch(dd, offx, offy, ns, alphas, cs, mode=mode, out=out)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
         hosts[form] = out.cpu().numpy()
-        leg[form] = {"value": round(len(ns) / dt, 2), "unit": "pairs/s", "ms": round(dt * 1e3, 1)}
+        dt = float(np.median(times))
+        leg[form] = {"value": round(len(ns) / dt, 2), "unit": "pairs/s", "median_ms": round(dt * 1e3, 1),
+                     "ms": [round(t * 1e3, 1) for t in times]}
+        micx.set_profiling(True)
+        micx.batch(dd, offx, offy, ns, alphas, cs, mode=mode, out=out)
+        prof = micx.get_profile()
+        micx.set_profiling(False)
+        leg[form]["dp_launches"] = prof["dp_launches"]
+        if prof["dp32_classes"] > 0:
+            leg[form]["recheck"] = {"pairs": prof["recheck_pairs"], "items": prof["recheck_items"],
+                                    "ms": round(prof["recheck_ms"], 2)}
         print("bench: stream %s done" % form, file=sys.stderr, flush=True)
     return leg, hosts, (data, offx, offy, ns, alphas, cs)
 
@@ -225,22 +274,28 @@ def sweep_leg(micx):
     """The paper's timing experiment over the grid bound B = n^alpha (Sec. 2C):
     independent uniform variables, alpha in {0.5, 0.6, 0.7}, n from 250 to
     8000.  Per point: all pairs of 64 variables (2,016 pairs) in the DP32
-    form after one warm-up call.  The cost model of the DP is about
-    c^2 B^3 per pair, so the time per pair should grow like n^(3 alpha); the
-    fitted exponent is reported beside it."""
+    form, timed on a replay of the captured call (after the eager first call
+    and the capture).  The cost model of the DP is about c^2 B^3 per pair, so
+    the time per pair should grow like n^(3 alpha); the fitted exponent is
+    reported beside it, and so is the paper's claim that alpha = 0.6 takes
+    under 15% of the time of alpha = 0.7."""
     import torch
     out = []
+    ms = {}
     for alpha in (0.5, 0.6, 0.7):
         pts = []
         for n in (250, 500, 1000, 2000, 4000, 8000):
             rng = np.random.default_rng(2000 + n)
             X = torch.from_numpy(rng.uniform(0.0, 1.0, (64, n)).astype(np.float32)).cuda()
-            micx.allpairs(X, alpha, 15.0, micx.MODE_DP32)
+            res = torch.empty((2016, 4), dtype=torch.float64, device="cuda")
+            for _ in range(2):
+                micx.allpairs(X, alpha, 15.0, micx.MODE_DP32, out=res)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            micx.allpairs(X, alpha, 15.0, micx.MODE_DP32)
+            micx.allpairs(X, alpha, 15.0, micx.MODE_DP32, out=res)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
+            ms[(alpha, n)] = dt * 1e3
             pts.append({"n": n, "B": micx.grid_bound(n, alpha), "ms": round(dt * 1e3, 2),
                         "pairs_per_s": round(2016 / dt, 1)})
             print("bench: sweep alpha=%.1f n=%d done" % (alpha, n), file=sys.stderr, flush=True)
@@ -250,7 +305,60 @@ def sweep_leg(micx):
         slope = float(np.polyfit(ln, lt, 1)[0])
         out.append({"alpha": alpha, "points": pts, "fitted_exponent_n_ge_1000": round(slope, 3),
                     "model_exponent": round(3 * alpha, 2)})
-    return out
+    ratio = {str(n): round(ms[(0.6, n)] / ms[(0.7, n)], 4) for n in (250, 500, 1000, 2000, 4000, 8000)}
+    return {"points_by_alpha": out, "time_ratio_alpha_0.6_over_0.7": ratio,
+            "paper_claim_under_0.15_holds_at_n": [int(n) for n, r in ratio.items() if r < 0.15],
+            "data": "synthetic: 64 independent U[0,1] variables per point (2,016 pairs)"}
+
+
+def counts_leg(micx, steps):
+    """The RNA-seq-shaped workload at full size: m = 2000 x n = 1340 int32
+    negative-binomial counts with 30-60% zeros (1,999,000 pairs), both forms,
+    timed like the main workload (eager call, capture, `steps` replays).
+    Returns (leg, host outputs per form, matrix)."""
+    import torch
+    import workloads
+    C = workloads.counts_matrix()
+    m = C.shape[0]
+    npairs = m * (m - 1) // 2
+    Cd = torch.from_numpy(C).cuda()
+    out = torch.empty((npairs, 4), dtype=torch.float64, device="cuda")
+    leg = {"workload": "RNA-seq-shaped all-pairs: m=%d x n=%d int32 counts, 30-60%% zeros" % C.shape,
+           "pairs": npairs, "data": "synthetic"}
+    hosts = {}
+    for form, mode in (("dp32", micx.MODE_DP32), ("fp64", micx.MODE_FP64)):
+        ms, times, (first_ms, capture_ms), prof, host = run_form(micx, Cd, out, None, mode, 0.6, 15.0,
+                                                                  steps, 2, "counts " + form)
+        hosts[form] = host
+        leg[form] = {"value": round(npairs / (ms / 1e3), 2), "unit": "pairs/s", "ms_per_step": round(ms, 1),
+                     "first_call_ms": round(first_ms, 1), "capture_call_ms": round(capture_ms, 1),
+                     "roofline_frac": roofline_of(prof, "k_dp")["frac"]}
+        if prof["dp32_classes"] > 0:
+            leg[form]["recheck"] = {"pairs": prof["recheck_pairs"], "items": prof["recheck_items"],
+                                    "flag_rate": round(prof["recheck_pairs"] / npairs, 6),
+                                    "ms": round(prof["recheck_ms"], 2)}
+    return leg, hosts, C
+
+
+def counts_parity(oracle, leg, hosts, C, threads):
+    """Part of the CPU-oracle leg: 256 seeded pairs plus the 8 most
+    zero-heavy pairs of the counts workload against the FP64 oracle."""
+    m = C.shape[0]
+    zf = (C == 0).mean(axis=1)
+    order = np.argsort(-zf, kind="stable")
+    pl = {(int(min(order[2 * i], order[2 * i + 1])), int(max(order[2 * i], order[2 * i + 1])))
+          for i in range(8)}
+    rng = np.random.default_rng(93)
+    while len(pl) < 264:
+        a, b = rng.integers(0, m, 2)
+        if a != b:
+            pl.add((int(min(a, b)), int(max(a, b))))
+    pl = sorted(pl)
+    ref = oracle.allpairs(C.astype(np.float64), 0.6, 15.0, pairs=np.array(pl), nthreads=threads)
+    idx = [pair_index(a, b, m) for a, b in pl]
+    for form in hosts:
+        leg[form]["parity"] = parity_of(hosts[form][idx], ref)
+    leg["parity_sample"] = "%d pairs: 8 most zero-heavy + 256 seeded" % len(pl)
 
 
 def main():
@@ -282,9 +390,12 @@ def main():
     results = {}
     for form in order:
         mode = micx.MODE_DP32 if form == "dp32" else micx.MODE_FP64
-        ms, prof, host = run_form(micx, Xd, out, stream, mode, alpha, c, args.steps, args.warmup, form)
+        ms, times, (first_ms, capture_ms), prof, host = run_form(micx, Xd, out, stream, mode, alpha, c,
+                                                                  args.steps, args.warmup, form)
         results[form] = (ms, prof, host)
         forms[form] = {"value": round(npairs / (ms / 1e3), 2), "ms_per_step": round(ms, 3),
+                       "median_replay_ms": round(float(np.median(times)), 3),
+                       "first_call_ms": round(first_ms, 3), "capture_call_ms": round(capture_ms, 3),
                        "roofline_frac": roofline_of(prof, "k_dp")["frac"],
                        "dp32_classes": prof["dp32_classes"], "fp64_classes": prof["fp64_classes"],
                        "dp32_bound": prof["dp32_bound"]}
@@ -318,6 +429,10 @@ def main():
     if not args.no_stream and args.m == 1000:
         stream = stream_leg(micx)
         result["batch_stream"] = stream[0]
+    counts = None
+    if not args.no_counts and args.m == 1000:
+        counts = counts_leg(micx, 2)
+        result["counts_workload"] = counts[0]
     # the CPU-oracle leg: baseline timing and every parity figure
     if args.cpu_sample > 0:
         import oracle
@@ -329,6 +444,8 @@ def main():
         jj = rng.integers(0, m, 4 * k + 8)
         extra = [(int(min(a, b)), int(max(a, b))) for a, b in zip(ii, jj) if a != b]
         sample = list(dict.fromkeys(pl + extra))[: args.cpu_sample]
+        # the GPU machine allots 16 host cores to each GPU, whatever os.cpu_count()
+        # reports there: the oracle's pool is sized to that share
         threads = args.cpu_threads or min(os.cpu_count() or 1, 16)
         t0 = time.perf_counter()
         ref = oracle.allpairs(X, alpha, c, pairs=np.array(sample), nthreads=threads)
@@ -345,13 +462,18 @@ def main():
             "sample": "%d pairs of this workload (all planted pairs + seeded random pairs), "
                       "FP64 oracle, %.1f s" % (len(sample), cpu_s),
             "single_core_pairs_per_s": round(32 / one_s, 3),
+            "extrapolated_full_run_s": round(npairs * cpu_s / len(sample), 1),
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "cores_note": "threads capped at the 16 host cores the GPU box allots per GPU",
         }
         result["parity"] = parity_of(results[main_form][2][idx], ref)
         for form in results:
             forms[form]["parity"] = parity_of(results[form][2][idx], ref)
         if stream is not None:
             stream_parity(oracle, *stream, threads)
-    if args.sweep:
+        if counts is not None:
+            counts_parity(oracle, *counts, threads)
+    if not args.no_sweep and args.m == 1000:
         result["sweep"] = sweep_leg(micx)
     if args.copy_calibration > 0:
         nb = args.copy_calibration << 20

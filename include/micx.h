@@ -89,8 +89,27 @@ extern "C" {
 #define MICX_COMPAT_BOUND_STRICT  16
 #define MICX_COMPAT_KHAT_PLUS1    32
 
-/* Opaque context: device, workspace, cached tables. */
+/* Opaque context: device, workspace, cached tables and launch graphs. */
 typedef struct micx_ctx micx_ctx;
+
+/* The dataset of one pair (the paper's dataset structure): n samples of two
+ * variables, HOST arrays of n doubles owned by the caller. */
+typedef struct {
+    int n;
+    const double *x;
+    const double *y;
+} micx_problem;
+
+/* The parameters of the method (the paper's parameter structure, Sec. 2):
+ * alpha sets the grid bound B = n^alpha (Sec. 2C), c the superclump bound
+ * khat = c x (Algorithm 2).  Defaults 0.6 and 15 (the paper's usage
+ * example). */
+typedef struct {
+    double alpha;
+    double c;
+} micx_param;
+#define MICX_ALPHA_DEFAULT 0.6
+#define MICX_C_DEFAULT 15.0
 
 /* Score of one pair: the characteristic matrix (the paper's score structure). */
 typedef struct {
@@ -109,20 +128,22 @@ int micx_ctx_create(micx_ctx **ctx, int device);
 /* Release a context and its workspace.  NULL is ignored. */
 void micx_ctx_destroy(micx_ctx *ctx);
 
-/* Parameter check (the paper's MINE(alpha, c) rejects bad values with a
- * message).  Returns NULL when 0 < alpha <= 1 and c > 0, else a static
- * message. */
-const char *micx_check_param(double alpha, double c);
+/* Parameter check (the paper's engine validates its parameter structure and
+ * reports a message, Sec. 2 and the usage example).  Returns NULL when
+ * param is non-null, 0 < alpha <= 1 and c > 0, else a static message. */
+const char *micx_check_param(const micx_param *param);
 
 /* Grid bound floor(pow(n, alpha)) in FP64 (Sec. 2C; Appendix A item 1). */
 int micx_grid_bound(int n, double alpha);
 
-/* Score of one pair (the paper's mine_compute_score).
- * x, y: HOST arrays of n doubles.  mode: MICX_MODE_*.
+/* Score of one pair: the paper's score function on its dataset and
+ * parameter structures (Sec. 2; Appendix A items 1-10 for what it computes).
+ * problem: the pair (host arrays).  mode: MICX_MODE_*.
  * *out receives a newly allocated score owned by the caller; release it
- * with micx_free_score().  Synchronous. */
-int micx_compute_score(micx_ctx *ctx, const double *x, const double *y, int n,
-                       double alpha, double c, int mode, micx_score **out);
+ * with micx_free_score().  Synchronous: returns once the score is on the
+ * host, with MICX_ENONFINITE for NaN or infinite input. */
+int micx_compute_score(micx_ctx *ctx, const micx_problem *problem, const micx_param *param, int mode,
+                       micx_score **out);
 
 /* The four statistics of a score (the paper's four statistic functions). */
 double micx_mic(const micx_score *s);
@@ -133,28 +154,48 @@ double micx_mcn(const micx_score *s, double eps);
 /* Free a score returned by micx_compute_score().  NULL is ignored. */
 void micx_free_score(micx_score *s);
 
-/* All pairs of rows of X.
+/* All pairs of rows of X: the all-pairs mode of the paper's engine (Sec. 2;
+ * the mine application's default mode), each pair scored as by
+ * micx_compute_score.
  * X_dev: DEVICE pointer to an m x n row-major matrix (one variable per row,
  *        n samples contiguous) of element type dtype (MICX_F32/F64/I32);
- *        owned by the caller, read only.
+ *        owned by the caller, read only until the work completes.
  * out_dev: DEVICE pointer to m(m-1)/2 * 4 doubles owned by the caller; pair
  *        (i < j) is written at index p = i*m - i*(i+1)/2 + (j-i-1) as
  *        (MIC, MAS, MEV, MCN), with the first variable i and the second j.
- * stream: hipStream_t (as void*), or NULL for the null stream.  Kernels are
- *        queued on it; the call returns after the work completes (it reads
- *        back the device status word).
- * mode: MICX_MODE_*. */
-int micx_allpairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n,
-                  double alpha, double c, int mode, double *out_dev, void *stream);
+ * stream: hipStream_t (as void*), or NULL for the null stream.
+ * mode: MICX_MODE_*.
+ * Asynchronous: the work is queued on stream and the call returns without
+ * waiting for it.  Argument errors are returned at once; errors the device
+ * finds (NaN or infinity in X) are returned by micx_status(), and out_dev
+ * is then left untouched.  With launch graphs on (micx_set_graphs, the
+ * default), the second call with the same arguments captures the work into
+ * a HIP graph and later ones replay it. */
+int micx_allpairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n, const micx_param *param,
+                  int mode, double *out_dev, void *stream);
 
-/* Listed pairs of rows of X (the paper's "master variable" and single-pair
- * modes are lists of this kind).
+/* Waits for the work of the last pair call on ctx (micx_allpairs,
+ * micx_pairs, micx_batch, micx_pearson) and returns its device-side result:
+ * MICX_OK, MICX_ENONFINITE (NaN or infinity in the input; outputs untouched)
+ * or MICX_EDEVICE.  A call's result holds until the next call. */
+int micx_status(micx_ctx *ctx);
+
+/* Launch graphs for micx_allpairs (1 = on, the default; 0 = every call
+ * launches its kernels one by one).  Cached graphs are dropped when the
+ * context's workspace grows. */
+int micx_set_graphs(micx_ctx *ctx, int enable);
+
+/* Listed pairs of rows of X: the paper's "master variable" (one variable
+ * against all others) and single-pair modes of its mine application
+ * (Sec. 2) are lists of this kind.
  * pairs_host: HOST array of npairs (i, j) int32 index pairs, 0 <= i, j < m,
- *        i != j; out_dev: DEVICE pointer to npairs * 4 doubles, pair k
- *        written at 4k as (MIC, MAS, MEV, MCN) with i the first variable. */
+ *        i != j (copied before the call returns); out_dev: DEVICE pointer to
+ *        npairs * 4 doubles, pair k written at 4k as (MIC, MAS, MEV, MCN)
+ *        with i the first variable.
+ * Asynchronous, as micx_allpairs (results of the device: micx_status). */
 int micx_pairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n,
-               const int32_t *pairs_host, int64_t npairs,
-               double alpha, double c, int mode, double *out_dev, void *stream);
+               const int32_t *pairs_host, int64_t npairs, const micx_param *param, int mode,
+               double *out_dev, void *stream);
 
 /* Pearson's correlation coefficient rho and the non-linearity index
  * MIC - rho^2 of pairs of rows of X: the two statistics the paper's engine
@@ -173,7 +214,8 @@ int micx_pairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n,
  * FP64: per variable the mean, then the centred sum of squares; per pair one
  * centred dot product, rho clamped to [-1, 1].  Errors: MICX_EINVAL (null
  * pointer, bad sizes, dtype or pair index, npairs mismatch), MICX_EDEVICE.
- * The call returns after the stream has finished. */
+ * Asynchronous, as micx_allpairs (pairs_host is copied before the call
+ * returns). */
 int micx_pearson(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n,
                  const int32_t *pairs_host, int64_t npairs, const double *stats_dev,
                  double *out_dev, void *stream);
@@ -191,7 +233,9 @@ typedef struct {
 } micx_pair_desc;
 
 /* A stream of independent pairs of uneven n and uneven (alpha, c), each
- * scored as by micx_compute_score on its own two variables.
+ * scored as by micx_compute_score on its own two variables (the pair-level
+ * parallelism of the paper's multi-core and MPI drivers, Sec. 2A-2B, on one
+ * device).
  * data_dev: DEVICE pointer to the packed variables, element type dtype
  *        (MICX_F32/F64/I32), owned by the caller, read only.
  * pairs_host: HOST array of npairs descriptors.  Every descriptor is checked
@@ -201,21 +245,37 @@ typedef struct {
  * out_dev: DEVICE pointer to npairs * 4 doubles owned by the caller; pair k
  *        is written at 4k as (MIC, MAS, MEV, MCN), x the first variable.
  *        On any error out_dev is left untouched.
- * Pairs that share (n, alpha, c) run together.  Synchronous on stream. */
+ * Pairs that share (n, alpha, c) run together.  Asynchronous, as
+ * micx_allpairs (pairs_host is read before the call returns; device-side
+ * results: micx_status). */
 int micx_batch(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pair_desc *pairs_host,
                int64_t npairs, int mode, double *out_dev, void *stream);
 
-/* Integer stages of one item, read back for bit-exact tests.
- * x, y: HOST arrays of n doubles.  orient 0: columns from x, rows from y;
+/* Integer stages of one item, read back for bit-exact tests:
+ * EquipartitionYAxis (App. A items 3-4), GetClumpsPartition (Algorithm 1)
+ * and GetSuperclumpsPartition (Algorithm 2).
+ * problem: the pair (host arrays).  orient 0: columns from x, rows from y;
  * orient 1: swapped.  ry: requested row count, 2 <= ry <= floor(B/2).
  * Outputs (host): *yhat rows produced; row_starts[0..yhat] positions (in
  * the row variable's sorted order) where each row starts, then n (caller
  * provides ry+1 ints); *k clumps; *K (super)clumps; ends[0..K-1] number of
  * points, in the column variable's order, up to and including each
- * (super)clump (caller provides n ints). */
-int micx_debug_item(micx_ctx *ctx, const double *x, const double *y, int n,
-                    double alpha, double c, int orient, int ry,
-                    int *yhat, int *row_starts, int *k, int *K, int *ends);
+ * (super)clump (caller provides n ints).  Synchronous. */
+int micx_debug_item(micx_ctx *ctx, const micx_problem *problem, const micx_param *param, int orient,
+                    int ry, int *yhat, int *row_starts, int *k, int *K, int *ends);
+
+/* The ranks and the DP's cumulative count table of one item, read back for
+ * bit-exact tests (App. A item 10a).
+ * group_start_x, group_start_y: HOST arrays of n ints: for every sample, the
+ *        position in its variable's sorted order where its tie group starts
+ *        (the number of smaller values), as the rank kernel stores it.
+ * counts: HOST array of (n+1)*ry ints (or NULL): counts[t*yhat + r] = points
+ *        of the first t (super)clumps, in the column variable's order, that
+ *        lie in row r, for t = 0..K and r = 0..yhat-1 -- the table the DP
+ *        kernel builds in LDS, written out by a debug instance of it.
+ * Same item selection as micx_debug_item.  Synchronous. */
+int micx_debug_tables(micx_ctx *ctx, const micx_problem *problem, const micx_param *param, int orient,
+                      int ry, int *group_start_x, int *group_start_y, int *counts);
 
 /* Instrumentation of the pair calls (micx_allpairs, micx_pairs, micx_batch).
  * With profiling enabled, each call records HIP events on its stream around
@@ -282,7 +342,7 @@ int micx_set_compat(micx_ctx *ctx, int flags);
  * a problem whose buffers exceed MICX_NOALLOC_BYTES -- alpha = 0.6 fits up
  * to n = MICX_MAX_N), MICX_EDEVICE. */
 int micx_score_noalloc(micx_ctx *ctx, const void *x_dev, const void *y_dev, int dtype, int n,
-                       double alpha, double c, int mode, double *stats_dev, double *mats_dev,
+                       const micx_param *param, int mode, double *stats_dev, double *mats_dev,
                        int *status_dev, void *stream);
 
 /* Message for a return code (static string). */

@@ -100,6 +100,11 @@ def _configure(lib):
     lib.oracle_item.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ip, ip, ip, ip]
     lib.oracle_item.restype = ctypes.c_int
+    lib.oracle_counts.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_int, ctypes.c_int, ctypes.c_int, ip]
+    lib.oracle_counts.restype = ctypes.c_int
+    lib.oracle_group_starts.argtypes = [dp, ctypes.c_int, ip]
+    lib.oracle_group_starts.restype = None
     lib.oracle_allpairs.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_int, P(ctypes.c_longlong),
                                     ctypes.c_longlong, ctypes.c_int, dp]
@@ -220,6 +225,29 @@ def item(x, y, alpha: float, c: float, orient: int, ry: int, flags: int = 0):
         raise ValueError("oracle_item: bad arguments")
     return {"yhat": yhat.value, "row_starts": rs[: yhat.value + 1].copy(), "k": k.value,
             "K": K.value, "ends": ends[: K.value].copy()}
+
+
+def counts(x, y, alpha: float, c: float, orient: int, ry: int, flags: int = 0):
+    """Cumulative count table of one item (App. A item 10a): int array
+    (K+1, yhat), row t = points of the first t superclumps per row."""
+    x, y = _f64(x), _f64(y)
+    n = len(x)
+    N = np.zeros((n + 1) * ry, dtype=np.int32)
+    K = _load().oracle_counts(_dptr(x), _dptr(y), n, float(alpha), float(c), int(flags), int(orient),
+                              int(ry), _iptr(N))
+    if K < 0:
+        raise ValueError("oracle_counts: bad arguments")
+    yh = item(x, y, alpha, c, orient, ry, flags)["yhat"]
+    return N[: (K + 1) * yh].reshape(K + 1, yh).copy()
+
+
+def group_starts(v):
+    """Sorted position where each sample's tie group starts (count of
+    smaller values)."""
+    v = _f64(v)
+    out = np.zeros(len(v), dtype=np.int32)
+    _load().oracle_group_starts(_dptr(v), len(v), _iptr(out))
+    return out
 
 
 def allpairs(X, alpha: float = 0.6, c: float = 15.0, pairs=None, nthreads: int | None = None,

@@ -476,6 +476,62 @@ int oracle_item(const double *x, const double *y, int n, double alpha, double c,
 }
 
 /* ---------------------------------------------------------------------- */
+/* Cumulative count table of one item (App. A item 10a):                   */
+/* N[t*yhat + r] = number of points among the first e_t in column-variable */
+/* order (the first t superclumps) that lie in row r, t = 0..K,            */
+/* r = 0..yhat-1.  Same item as oracle_item; N holds (n+1)*ry ints at      */
+/* most.  Returns K, or -1 on bad arguments.                               */
+/* ---------------------------------------------------------------------- */
+int oracle_counts(const double *x, const double *y, int n, double alpha, double c, int flags,
+                  int orient, int ry, int *N)
+{
+    int B = oracle_grid_bound(n, alpha);
+    int lim = cell_limit(B, flags);
+    if (n < 2 || ry < 2 || ry > lim / 2) return -1;
+    const double *u = orient ? y : x, *v = orient ? x : y;
+    int cx = lim / ry;
+    int *ou = (int *) malloc(sizeof(int) * (size_t) n);
+    int *ov = (int *) malloc(sizeof(int) * (size_t) n);
+    double *us = (double *) malloc(sizeof(double) * (size_t) n);
+    double *vs = (double *) malloc(sizeof(double) * (size_t) n);
+    int *qv = (int *) malloc(sizeof(int) * (size_t) n);
+    int *rowpt = (int *) malloc(sizeof(int) * (size_t) n);
+    int *qu = (int *) malloc(sizeof(int) * (size_t) n);
+    int *col = (int *) malloc(sizeof(int) * (size_t) n);
+    argsort(u, n, ou);
+    argsort(v, n, ov);
+    for (int i = 0; i < n; i++) { us[i] = u[ou[i]]; vs[i] = v[ov[i]]; }
+    int yh = oracle_equipartition(vs, n, ry, flags, qv);
+    for (int i = 0; i < n; i++) rowpt[ov[i]] = qv[i];
+    for (int i = 0; i < n; i++) qu[i] = rowpt[ou[i]];
+    int K = oracle_superclumps(us, qu, n, khat_of(c, cx), flags, col, NULL);
+    /* row t+1 of the table adds superclump t's points to row t */
+    for (int r = 0; r < yh; r++) N[r] = 0;
+    for (int t = 0; t < K; t++) {
+        for (int r = 0; r < yh; r++) N[(size_t) (t + 1) * yh + r] = N[(size_t) t * yh + r];
+        for (int i = 0; i < n; i++)
+            if (col[i] == t) N[(size_t) (t + 1) * yh + qu[i]]++;
+    }
+    free(col); free(qu); free(rowpt); free(qv); free(vs); free(us); free(ov); free(ou);
+    return K;
+}
+
+/* Tie-group start of every sample: out[j] = number of samples whose value */
+/* is smaller than v[j], i.e. the sorted position where v[j]'s tie group   */
+/* begins (the rank information the method uses: order and ties).         */
+void oracle_group_starts(const double *v, int n, int *out)
+{
+    int *o = (int *) malloc(sizeof(int) * (size_t) (n > 0 ? n : 1));
+    argsort(v, n, o);
+    int start = 0;
+    for (int i = 0; i < n; i++) {
+        if (i > 0 && v[o[i]] != v[o[i - 1]]) start = i;
+        out[o[i]] = start;
+    }
+    free(o);
+}
+
+/* ---------------------------------------------------------------------- */
 /* Many pairs on CPU threads (one pair per task).  X is m x n row-major    */
 /* (variable-contiguous).  pairs: npairs (i, j) index pairs as 2*npairs    */
 /* int64, or NULL for all i < j in the order (0,1), (0,2), ..., (m-2,m-1). */

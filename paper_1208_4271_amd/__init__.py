@@ -44,7 +44,7 @@ EXPORTS = (
     "micx_compute_score", "micx_mic", "micx_mas", "micx_mev", "micx_mcn", "micx_free_score",
     "micx_allpairs", "micx_pairs", "micx_batch", "micx_debug_item", "micx_strerror",
     "micx_set_profiling", "micx_get_profile", "micx_set_dp32_tolerance", "micx_set_compat",
-    "micx_pearson", "micx_score_noalloc",
+    "micx_pearson", "micx_score_noalloc", "micx_status", "micx_set_graphs", "micx_debug_tables",
 )
 
 # Size of the device array behind micx_score_noalloc (include/micx.h).
@@ -61,6 +61,19 @@ class _Score(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("B", ctypes.c_int), ("W", ctypes.c_int),
                 ("M", ctypes.POINTER(ctypes.c_double)), ("Axy", ctypes.POINTER(ctypes.c_double)),
                 ("Ayx", ctypes.POINTER(ctypes.c_double)), ("stats", ctypes.c_double * 4)]
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("x", ctypes.POINTER(ctypes.c_double)),
+                ("y", ctypes.POINTER(ctypes.c_double))]
+
+
+class _Param(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("c", ctypes.c_double)]
+
+
+def _param(alpha, c):
+    return _Param(float(alpha), float(c))
 
 
 class _PairDesc(ctypes.Structure):
@@ -95,12 +108,11 @@ def load_library():
     lib.micx_ctx_create.restype = ctypes.c_int
     lib.micx_ctx_destroy.argtypes = [vp]
     lib.micx_ctx_destroy.restype = None
-    lib.micx_check_param.argtypes = [ctypes.c_double, ctypes.c_double]
+    lib.micx_check_param.argtypes = [P(_Param)]
     lib.micx_check_param.restype = ctypes.c_char_p
     lib.micx_grid_bound.argtypes = [ctypes.c_int, ctypes.c_double]
     lib.micx_grid_bound.restype = ctypes.c_int
-    lib.micx_compute_score.argtypes = [vp, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                       ctypes.c_int, P(P(_Score))]
+    lib.micx_compute_score.argtypes = [vp, P(_Problem), P(_Param), ctypes.c_int, P(P(_Score))]
     lib.micx_compute_score.restype = ctypes.c_int
     for f in ("micx_mic", "micx_mas", "micx_mev"):
         getattr(lib, f).argtypes = [P(_Score)]
@@ -109,23 +121,29 @@ def load_library():
     lib.micx_mcn.restype = ctypes.c_double
     lib.micx_free_score.argtypes = [P(_Score)]
     lib.micx_free_score.restype = None
-    lib.micx_allpairs.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                  ctypes.c_double, ctypes.c_int, vp, vp]
+    lib.micx_allpairs.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(_Param),
+                                  ctypes.c_int, vp, vp]
     lib.micx_allpairs.restype = ctypes.c_int
+    lib.micx_status.argtypes = [vp]
+    lib.micx_status.restype = ctypes.c_int
+    lib.micx_set_graphs.argtypes = [vp, ctypes.c_int]
+    lib.micx_set_graphs.restype = ctypes.c_int
     lib.micx_pairs.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_int32),
-                               ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int, vp, vp]
+                               ctypes.c_int64, P(_Param), ctypes.c_int, vp, vp]
     lib.micx_pairs.restype = ctypes.c_int
     lib.micx_batch.argtypes = [vp, vp, ctypes.c_int, P(_PairDesc), ctypes.c_int64, ctypes.c_int, vp, vp]
     lib.micx_batch.restype = ctypes.c_int
     lib.micx_pearson.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_int32),
                                  ctypes.c_int64, vp, vp, vp]
     lib.micx_pearson.restype = ctypes.c_int
-    lib.micx_score_noalloc.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                       ctypes.c_double, ctypes.c_int, vp, vp, vp, vp]
+    lib.micx_score_noalloc.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, P(_Param),
+                                       ctypes.c_int, vp, vp, vp, vp]
     lib.micx_score_noalloc.restype = ctypes.c_int
-    lib.micx_debug_item.argtypes = [vp, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                    ctypes.c_int, ctypes.c_int, ip, ip, ip, ip, ip]
+    lib.micx_debug_item.argtypes = [vp, P(_Problem), P(_Param), ctypes.c_int, ctypes.c_int,
+                                    ip, ip, ip, ip, ip]
     lib.micx_debug_item.restype = ctypes.c_int
+    lib.micx_debug_tables.argtypes = [vp, P(_Problem), P(_Param), ctypes.c_int, ctypes.c_int, ip, ip, ip]
+    lib.micx_debug_tables.restype = ctypes.c_int
     lib.micx_set_profiling.argtypes = [vp, ctypes.c_int]
     lib.micx_set_profiling.restype = ctypes.c_int
     lib.micx_get_profile.argtypes = [vp, P(_Profile)]
@@ -159,8 +177,20 @@ def context(device: int = 0):
 
 
 def check_param(alpha: float, c: float):
-    msg = load_library().micx_check_param(float(alpha), float(c))
+    p = _param(alpha, c)
+    msg = load_library().micx_check_param(ctypes.byref(p))
     return None if msg is None else msg.decode()
+
+
+def status(device: int = 0) -> int:
+    """micx_status: waits for the last pair call's work and returns its
+    device-side result code."""
+    return load_library().micx_status(context(device))
+
+
+def set_graphs(enable: bool = True, device: int = 0):
+    """Launch graphs for allpairs (captured on the second identical call)."""
+    _check(load_library().micx_set_graphs(context(device), 1 if enable else 0), "micx_set_graphs")
 
 
 def grid_bound(n: int, alpha: float) -> int:
@@ -176,16 +206,19 @@ def _dptr(a):
 
 
 def compute_score(x, y, alpha: float = 0.6, c: float = 15.0, mode: int = MODE_FP64,
-                  device: int = 0):
+                  device: int = 0, mcn_eps=()):
     """Score of one pair (host arrays).  Returns dict: stats (MIC, MAS, MEV,
-    MCN), M, Axy, Ayx (W x W, [rows-2, cols-2], NaN outside the grid bound), B."""
+    MCN), M, Axy, Ayx (W x W, [rows-2, cols-2], NaN outside the grid bound), B,
+    and mcn: {eps: micx_mcn(score, eps)} for every eps in mcn_eps."""
     lib = load_library()
     x, y = _f64(x), _f64(y)
     if len(x) != len(y):
         raise ValueError("x and y differ in length")
     out = ctypes.POINTER(_Score)()
-    _check(lib.micx_compute_score(context(device), _dptr(x), _dptr(y), len(x), float(alpha),
-                                  float(c), int(mode), ctypes.byref(out)), "micx_compute_score")
+    prob = _Problem(len(x), _dptr(x), _dptr(y))
+    par = _param(alpha, c)
+    _check(lib.micx_compute_score(context(device), ctypes.byref(prob), ctypes.byref(par), int(mode),
+                                  ctypes.byref(out)), "micx_compute_score")
     try:
         s = out.contents
         W = s.W
@@ -194,7 +227,8 @@ def compute_score(x, y, alpha: float = 0.6, c: float = 15.0, mode: int = MODE_FP
         Ayx = np.ctypeslib.as_array(s.Ayx, shape=(W * W,)).reshape(W, W).copy()
         stats = np.array([lib.micx_mic(out), lib.micx_mas(out), lib.micx_mev(out),
                           lib.micx_mcn(out, 0.0)])
-        return {"stats": stats, "M": M, "Axy": Axy, "Ayx": Ayx, "B": s.B, "W": W}
+        mcn = {float(e): lib.micx_mcn(out, float(e)) for e in mcn_eps}
+        return {"stats": stats, "M": M, "Axy": Axy, "Ayx": Ayx, "B": s.B, "W": W, "mcn": mcn}
     finally:
         lib.micx_free_score(out)
 
@@ -210,11 +244,13 @@ def _stream_ptr(stream):
 
 
 def allpairs(X, alpha: float = 0.6, c: float = 15.0, mode: int = MODE_FP64, out=None,
-             stream=None):
+             stream=None, wait: bool = True):
     """All pairs of rows of a CUDA tensor X (m x n, float32/float64/int32).
 
     Returns a (m(m-1)/2, 4) float64 CUDA tensor of (MIC, MAS, MEV, MCN) in
-    row-major upper-triangle order (0,1), (0,2), ..., (m-2, m-1)."""
+    row-major upper-triangle order (0,1), (0,2), ..., (m-2, m-1).  The work
+    is queued on the stream; with wait=True the call then waits for it and
+    raises on a device-side error (micx_status)."""
     import torch
     if not X.is_cuda or X.dim() != 2:
         raise ValueError("X must be a 2-D CUDA tensor")
@@ -226,15 +262,19 @@ def allpairs(X, alpha: float = 0.6, c: float = 15.0, mode: int = MODE_FP64, out=
     npairs = m * (m - 1) // 2
     if out is None:
         out = torch.empty((npairs, 4), dtype=torch.float64, device=X.device)
-    rc = load_library().micx_allpairs(context(X.device.index or 0), ctypes.c_void_p(X.data_ptr()),
-                                      dt, m, n, float(alpha), float(c), int(mode),
-                                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    par = _param(alpha, c)
+    dev = X.device.index or 0
+    rc = load_library().micx_allpairs(context(dev), ctypes.c_void_p(X.data_ptr()), dt, m, n,
+                                      ctypes.byref(par), int(mode), ctypes.c_void_p(out.data_ptr()),
+                                      _stream_ptr(stream))
     _check(rc, "micx_allpairs")
+    if wait:
+        _check(status(dev), "micx_allpairs")
     return out
 
 
 def pairs(X, pair_list, alpha: float = 0.6, c: float = 15.0, mode: int = MODE_FP64, out=None,
-          stream=None):
+          stream=None, wait: bool = True):
     """Listed pairs (i, j) of rows of a CUDA tensor X.  Returns (npairs, 4)."""
     import torch
     if not X.is_cuda or X.dim() != 2:
@@ -247,11 +287,15 @@ def pairs(X, pair_list, alpha: float = 0.6, c: float = 15.0, mode: int = MODE_FP
     pl = np.ascontiguousarray(np.asarray(pair_list, dtype=np.int32).reshape(-1, 2))
     if out is None:
         out = torch.empty((len(pl), 4), dtype=torch.float64, device=X.device)
-    rc = load_library().micx_pairs(context(X.device.index or 0), ctypes.c_void_p(X.data_ptr()), dt,
+    par = _param(alpha, c)
+    dev = X.device.index or 0
+    rc = load_library().micx_pairs(context(dev), ctypes.c_void_p(X.data_ptr()), dt,
                                    m, n, pl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(pl),
-                                   float(alpha), float(c), int(mode),
+                                   ctypes.byref(par), int(mode),
                                    ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
     _check(rc, "micx_pairs")
+    if wait:
+        _check(status(dev), "micx_pairs")
     return out
 
 
@@ -281,15 +325,18 @@ def pearson(X, pair_list=None, stats=None, out=None, stream=None):
     if out is None:
         out = torch.empty((npairs, 2), dtype=torch.float64, device=X.device)
     pp = pl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if pl is not None else None
-    rc = load_library().micx_pearson(context(X.device.index or 0), ctypes.c_void_p(X.data_ptr()), dt,
+    dev = X.device.index or 0
+    rc = load_library().micx_pearson(context(dev), ctypes.c_void_p(X.data_ptr()), dt,
                                      m, n, pp, npairs,
                                      ctypes.c_void_p(stats.data_ptr()) if stats is not None else None,
                                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
     _check(rc, "micx_pearson")
+    _check(status(dev), "micx_pearson")
     return out
 
 
-def batch(data, off_x, off_y, ns, alphas, cs, mode: int = MODE_FP64, out=None, stream=None):
+def batch(data, off_x, off_y, ns, alphas, cs, mode: int = MODE_FP64, out=None, stream=None,
+          wait: bool = True):
     """Independent pairs of uneven n and (alpha, c) from a packed 1-D CUDA
     tensor `data` (float32/float64/int32): pair k is data[off_x[k]:+ns[k]]
     against data[off_y[k]:+ns[k]] with parameters (alphas[k], cs[k]).
@@ -313,10 +360,13 @@ def batch(data, off_x, off_y, ns, alphas, cs, mode: int = MODE_FP64, out=None, s
         descs[k] = _PairDesc(int(off_x[k]), int(off_y[k]), int(ns[k]), 0, float(alphas[k]), float(cs[k]))
     if out is None:
         out = torch.empty((npairs, 4), dtype=torch.float64, device=data.device)
-    rc = load_library().micx_batch(context(data.device.index or 0), ctypes.c_void_p(data.data_ptr()),
+    dev = data.device.index or 0
+    rc = load_library().micx_batch(context(dev), ctypes.c_void_p(data.data_ptr()),
                                    dt, descs, npairs, int(mode), ctypes.c_void_p(out.data_ptr()),
                                    _stream_ptr(stream))
     _check(rc, "micx_batch")
+    if wait:
+        _check(status(dev), "micx_batch")
     return out
 
 
@@ -344,8 +394,9 @@ def score_noalloc(x, y, alpha: float, c: float, mode: int, stats, mats=None, sta
     if dt is None:
         raise ValueError("dtype must be float32, float64 or int32")
     ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    par = _param(alpha, c)
     rc = load_library().micx_score_noalloc(context(x.device.index or 0), ptr(x), ptr(y), dt, x.numel(),
-                                           float(alpha), float(c), int(mode), ptr(stats), ptr(mats),
+                                           ctypes.byref(par), int(mode), ptr(stats), ptr(mats),
                                            ptr(status), _stream_ptr(stream))
     _check(rc, "micx_score_noalloc")
     return rc
@@ -359,12 +410,35 @@ def debug_item(x, y, alpha: float, c: float, orient: int, ry: int, device: int =
     rs = np.zeros(ry + 1, dtype=np.int32)
     ends = np.zeros(n, dtype=np.int32)
     ip = ctypes.POINTER(ctypes.c_int)
-    _check(load_library().micx_debug_item(context(device), _dptr(x), _dptr(y), n, float(alpha),
-                                          float(c), int(orient), int(ry), ctypes.byref(yhat),
+    prob = _Problem(n, _dptr(x), _dptr(y))
+    par = _param(alpha, c)
+    _check(load_library().micx_debug_item(context(device), ctypes.byref(prob), ctypes.byref(par),
+                                          int(orient), int(ry), ctypes.byref(yhat),
                                           rs.ctypes.data_as(ip), ctypes.byref(k), ctypes.byref(K),
                                           ends.ctypes.data_as(ip)), "micx_debug_item")
     return {"yhat": yhat.value, "row_starts": rs[: yhat.value + 1].copy(), "k": k.value,
             "K": K.value, "ends": ends[: K.value].copy()}
+
+
+def debug_tables(x, y, alpha: float, c: float, orient: int, ry: int, device: int = 0):
+    """Tie-group starts of both variables and the DP's cumulative count table
+    of one item (see micx_debug_tables): dict with group_start_x,
+    group_start_y (n ints) and counts ((K+1) x yhat)."""
+    x, y = _f64(x), _f64(y)
+    n = len(x)
+    it = debug_item(x, y, alpha, c, orient, ry, device)
+    gx = np.zeros(n, dtype=np.int32)
+    gy = np.zeros(n, dtype=np.int32)
+    N = np.zeros((n + 1) * ry, dtype=np.int32)
+    ip = ctypes.POINTER(ctypes.c_int)
+    prob = _Problem(n, _dptr(x), _dptr(y))
+    par = _param(alpha, c)
+    _check(load_library().micx_debug_tables(context(device), ctypes.byref(prob), ctypes.byref(par),
+                                            int(orient), int(ry), gx.ctypes.data_as(ip),
+                                            gy.ctypes.data_as(ip), N.ctypes.data_as(ip)),
+           "micx_debug_tables")
+    K, yh = it["K"], it["yhat"]
+    return {"group_start_x": gx, "group_start_y": gy, "counts": N[: (K + 1) * yh].reshape(K + 1, yh).copy()}
 
 
 def set_profiling(enable: bool = True, device: int = 0):

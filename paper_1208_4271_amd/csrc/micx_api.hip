@@ -22,12 +22,15 @@ using namespace micx;
 
 namespace {
 
-// Grow-only device buffer.
+// Grow-only device buffer.  Every reallocation bumps the context's
+// generation counter: launch graphs captured before it hold stale pointers.
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
+    unsigned *gen = nullptr;
     int ensure(size_t bytes) {
         if (bytes <= cap) return MICX_OK;
+        if (gen) (*gen)++;
         if (p) hipFree(p);
         p = nullptr;
         cap = 0;
@@ -46,11 +49,24 @@ struct DevBuf {
     template <class T> T *as() const { return (T *)p; }
 };
 
+// Arguments of an all-pairs call, the key of its captured graph.
+struct GraphKey {
+    const void *X = nullptr;
+    int dtype = -1, m = 0, n = 0, mode = -1, compat = 0;
+    double alpha = 0.0, c = 0.0, tol = 0.0;
+    double *out = nullptr;
+    bool operator==(const GraphKey &o) const {
+        return X == o.X && dtype == o.dtype && m == o.m && n == o.n && mode == o.mode &&
+               compat == o.compat && alpha == o.alpha && c == o.c && tol == o.tol && out == o.out;
+    }
+};
+
 }  // namespace
 
 struct micx_ctx {
     int device = 0;
     int cus = 256;
+    unsigned gen = 0;         // workspace generation (see DevBuf)
     DevBuf perm, gsize, grank, rowof, yhat, rowstart, xlogx, status;
     DevBuf geo;        // xcnt | khat | koff | aoff
     DevBuf cbuf, sbuf, Kb, kb, srcb, A, scratch, pairs, input, out, dense;
@@ -64,7 +80,29 @@ struct micx_ctx {
     DevBuf rcwords, rclist, rcpairs;   // near-tie recheck: counters and item flags, item lists, pairs
     DevBuf rcmeta;                     // near-tie recheck of a batch pass: key offsets, key of each class
     DevBuf arena, gitems;              // micx_batch: per-pass group buffers, DP item lists
+    DevBuf dbg;                        // micx_debug_tables: the DP's count table
     std::vector<hipStream_t> dstreams; // micx_batch: DP launches of different shapes run side by side
+    // pinned host memory: the device status word of the last call, and a
+    // staging ring for host-to-device copies of asynchronous calls
+    int *hstatus = nullptr;
+    hipStream_t last = nullptr;        // stream of the last pair call (micx_status waits on it)
+    unsigned char *stage = nullptr;
+    size_t stage_cap = 0, stage_off = 0;
+    std::vector<hipStream_t> stage_streams;   // streams with copies out of the ring since its reset
+    // launch graph of micx_allpairs: the last key, whether it ran once, its graph
+    size_t batch_budget = 0;           // bytes of per-item buffers per batch (batch_pairs)
+    int graphs = 1;
+    GraphKey gkey;
+    bool gseen = false;
+    unsigned ggen = 0;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cstream = nullptr;     // capture stream
+    std::vector<DevBuf *> bufs() {
+        return {&perm, &gsize, &grank, &rowof, &yhat, &rowstart, &xlogx, &status, &geo, &cbuf, &sbuf,
+                &Kb, &kb, &srcb, &A, &scratch, &pairs, &input, &out, &dense, &counters, &fxtab, &lab,
+                &moments, &bdata, &boffs, &bout, &bidx, &rcwords, &rclist, &rcpairs, &rcmeta, &arena,
+                &gitems, &dbg};
+    }
 };
 
 #define HIPCHK(expr)                                   \
@@ -90,10 +128,17 @@ extern "C" const char *micx_strerror(int code) {
     }
 }
 
-extern "C" const char *micx_check_param(double alpha, double c) {
+namespace {
+const char *param_message(double alpha, double c) {
     if (!(alpha > 0.0 && alpha <= 1.0)) return "alpha must be in (0, 1]";
     if (!(c > 0.0) || !isfinite(c)) return "c must be > 0";
     return nullptr;
+}
+}  // namespace
+
+extern "C" const char *micx_check_param(const micx_param *p) {
+    if (!p) return "no parameter structure";
+    return param_message(p->alpha, p->c);
 }
 
 extern "C" int micx_grid_bound(int n, double alpha) {
@@ -112,11 +157,22 @@ extern "C" int micx_ctx_create(micx_ctx **ctx, int device) {
         return MICX_EDEVICE;
     }
     c->cus = device_cus(device);
+    for (DevBuf *b : c->bufs()) b->gen = &c->gen;
     // the no-allocation entry point's array: its address on this device
     const int rc = noalloc_init(device);
     if (rc != MICX_OK) {
         delete c;
         return rc;
+    }
+    if (hipHostMalloc((void **)&c->hstatus, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return MICX_ENOMEM;
+    }
+    *c->hstatus = 0;
+    if (hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking) != hipSuccess) {
+        hipHostFree(c->hstatus);
+        delete c;
+        return MICX_EDEVICE;
     }
     *ctx = c;
     return MICX_OK;
@@ -134,16 +190,13 @@ void ctx_params(const micx_ctx *ctx, int *device, int *cus, int *compat, double 
 extern "C" void micx_ctx_destroy(micx_ctx *c) {
     if (!c) return;
     hipSetDevice(c->device);
-    DevBuf *all[] = {&c->perm, &c->gsize, &c->grank, &c->rowof, &c->yhat, &c->rowstart,
-                     &c->xlogx, &c->status, &c->geo, &c->cbuf, &c->sbuf, &c->Kb, &c->kb,
-                     &c->srcb, &c->A, &c->scratch, &c->pairs, &c->input, &c->out, &c->dense,
-                     &c->counters, &c->fxtab, &c->lab,
-                     &c->bdata, &c->boffs, &c->bout, &c->bidx,
-                     &c->rcwords, &c->rclist, &c->rcpairs, &c->rcmeta, &c->moments};
-    for (DevBuf *b : all) b->release();
-    c->arena.release();
-    c->gitems.release();
+    hipDeviceSynchronize();
+    for (DevBuf *b : c->bufs()) b->release();
     for (hipStream_t st : c->dstreams) hipStreamDestroy(st);
+    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    if (c->cstream) hipStreamDestroy(c->cstream);
+    if (c->stage) hipHostFree(c->stage);
+    if (c->hstatus) hipHostFree(c->hstatus);
     delete c;
 }
 
@@ -193,17 +246,13 @@ void make_geometry(int n, int B, double c, HostGeometry &hg, int compat = 0) {
     g.khat_host = hg.khat.data();
 }
 
-int upload_geometry(micx_ctx *ctx, HostGeometry &hg, hipStream_t s) {
+// The geometry's device copy, computed by a kernel from (n, B, c) with the
+// host's arithmetic (no host staging, so the call stays asynchronous).
+int upload_geometry(micx_ctx *ctx, HostGeometry &hg, hipStream_t s, double c) {
     const int NY = hg.g.NY;
     RETCHK(ctx->geo.ensure(sizeof(int) * 4 * (size_t)NY));
     int *d = ctx->geo.as<int>();
-    std::vector<int> h(4 * (size_t)NY);
-    std::copy(hg.xcnt.begin(), hg.xcnt.end(), h.begin());
-    std::copy(hg.khat.begin(), hg.khat.end(), h.begin() + NY);
-    std::copy(hg.koff.begin(), hg.koff.end(), h.begin() + 2 * NY);
-    std::copy(hg.aoff.begin(), hg.aoff.end(), h.begin() + 3 * NY);
-    HIPCHK(hipMemcpyAsync(d, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));   // h is released on return
+    HIPCHK(launch_geometry(hg.g.n, hg.g.B, c, hg.g.compat, NY, d, s));
     hg.g.xcnt = d;
     hg.g.khat = d + NY;
     hg.g.koff = d + 2 * NY;
@@ -211,9 +260,54 @@ int upload_geometry(micx_ctx *ctx, HostGeometry &hg, hipStream_t s) {
     return MICX_OK;
 }
 
+// Host-to-device copy through the context's pinned staging ring, so that the
+// caller's host memory may change as soon as the call returns.  The ring is
+// reused once every stream that copied out of it has finished those copies.
+int stage_copy(micx_ctx *ctx, void *dst, const void *src, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return MICX_OK;
+    const size_t need = (bytes + 255) & ~(size_t)255;
+    if (ctx->stage_off + need > ctx->stage_cap) {
+        for (hipStream_t st : ctx->stage_streams) HIPCHK(hipStreamSynchronize(st));
+        ctx->stage_streams.clear();
+        ctx->stage_off = 0;
+        if (need > ctx->stage_cap) {
+            if (ctx->stage) hipHostFree(ctx->stage);
+            ctx->stage = nullptr;
+            ctx->stage_cap = 0;
+            const size_t cap = std::max(need, (size_t)64 << 20);
+            if (hipHostMalloc((void **)&ctx->stage, cap, hipHostMallocDefault) != hipSuccess) return MICX_ENOMEM;
+            ctx->stage_cap = cap;
+        }
+    }
+    unsigned char *h = ctx->stage + ctx->stage_off;
+    memcpy(h, src, bytes);
+    ctx->stage_off += need;
+    HIPCHK(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, s));
+    if (std::find(ctx->stage_streams.begin(), ctx->stage_streams.end(), s) == ctx->stage_streams.end())
+        ctx->stage_streams.push_back(s);
+    return MICX_OK;
+}
+
+// Clears the call's device status word (a kernel: no memset node in graphs).
+int begin_status(micx_ctx *ctx, hipStream_t s) {
+    RETCHK(ctx->status.ensure(sizeof(int)));
+    HIPCHK(launch_zero(ctx->status.p, 1, s));
+    return MICX_OK;
+}
+
+// Queues the copy of the call's status word to pinned host memory, read by
+// micx_status() after the stream has finished.
+int end_status(micx_ctx *ctx, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(ctx->hstatus, ctx->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    ctx->last = s;
+    return MICX_OK;
+}
+
+int status_code(int st) { return st == 0 ? MICX_OK : ((st & 1) ? MICX_ENONFINITE : MICX_EDEVICE); }
+
 int check_common(micx_ctx *ctx, int n, double alpha, double c, int mode) {
     if (!ctx) return MICX_EINVAL;
-    if (micx_check_param(alpha, c)) return MICX_EINVAL;
+    if (param_message(alpha, c)) return MICX_EINVAL;
     if (mode != MICX_MODE_FP64 && mode != MICX_MODE_DP32) return MICX_EINVAL;
     if (n < 2) return MICX_EINVAL;
     if (n > MICX_MAX_N) return MICX_ETOOBIG;
@@ -222,8 +316,9 @@ int check_common(micx_ctx *ctx, int n, double alpha, double c, int mode) {
     return MICX_OK;
 }
 
-// Per-variable stages: ranks and equipartitions.  Returns MICX_ENONFINITE if
-// the rank kernel saw a NaN or infinity.
+// Per-variable stages: ranks and equipartitions, queued on s.  The rank
+// kernel sets bit 0 of the call's status word on a NaN or infinity; the
+// statistics kernels then write nothing (begin_status must have run).
 int prepare_variables(micx_ctx *ctx, const void *X, int dtype, int m, int n, const Geometry &g,
                       bool want_rowstart, RankTables &rt, EquipTables &et, hipStream_t s) {
     const size_t mn = (size_t)m * n;
@@ -252,15 +347,9 @@ int prepare_variables(micx_ctx *ctx, const void *X, int dtype, int m, int n, con
         et.rowstart = ctx->rowstart.as<int>();
     }
     int *status = ctx->status.as<int>();
-    HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
     HIPCHK(launch_xlogx(n, ctx->xlogx.as<double>(), s));
     HIPCHK(launch_rank(X, dtype, m, n, rt, status, s));
     HIPCHK(launch_equip(rt, et, s));
-    int hstatus = 0;
-    HIPCHK(hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (hstatus & 1) return MICX_ENONFINITE;
-    if (hstatus) return MICX_EDEVICE;
     return MICX_OK;
 }
 
@@ -270,12 +359,26 @@ int lab_bytes(const Geometry &g) { return g.NY + 1 <= 256 ? 1 : 2; }
 size_t lab_row_bytes(const Geometry &g) { return (size_t)((g.n + 63) / 64 * 64) * lab_bytes(g); }
 
 // Pairs per batch: bounded so that the per-item buffers stay near 2 GB.
-int batch_pairs(const Geometry &g, int64_t total) {
+// Pairs per batch.  The per-item buffers of a batch (clump and superclump
+// ends, row labels, scores, recheck lists) take up to a third of the device
+// memory free at the first call, at most 96 GB: the benchmark workload
+// (m = 1000, n = 1340: about 155 KB per pair) runs as one batch on a 288 GB
+// MI355X.  The budget is fixed per context, so repeated calls reuse the
+// buffers (and a captured graph stays valid).
+int batch_pairs(micx_ctx *ctx, const Geometry &g, int64_t total) {
+    static_assert(sizeof(size_t) >= 8, "64-bit sizes");
     const size_t per_pair = 2 * (2 * (size_t)g.KSUM * sizeof(int) + 3 * (size_t)g.NY * sizeof(int) +
-                                 (size_t)g.ASUM * sizeof(double) + (size_t)g.NY * lab_row_bytes(g));
-    size_t pb = ((size_t)2048 << 20) / (per_pair ? per_pair : 1);
+                                 (size_t)g.ASUM * sizeof(double) + (size_t)g.NY * lab_row_bytes(g) +
+                                 (size_t)g.NY * sizeof(int) + 8);
+    if (ctx->batch_budget == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = (size_t)6 << 30;
+        ctx->batch_budget = std::min(fr / 3, (size_t)96 << 30);
+        ctx->batch_budget = std::max(ctx->batch_budget, (size_t)256 << 20);
+    }
+    size_t pb = ctx->batch_budget / (per_pair ? per_pair : 1);
     if (pb < 1) pb = 1;
-    if (pb > (size_t)1 << 20) pb = (size_t)1 << 20;
+    if (pb > (size_t)INT32_MAX / 4) pb = (size_t)INT32_MAX / 4;
     if ((int64_t)pb > total) pb = (size_t)total;
     return (int)pb;
 }
@@ -306,7 +409,7 @@ int ensure_items(micx_ctx *ctx, const Geometry &g, int pb, ItemBuffers &ib) {
 int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const Geometry &g,
               const int32_t *pairs_dev, int64_t npairs, int m, int mode, double *out_dev,
               double *M, double *Axy, double *Ayx, hipStream_t s) {
-    const int pb = batch_pairs(g, npairs);
+    const int pb = batch_pairs(ctx, g, npairs);
     ItemBuffers ib;
     RETCHK(ensure_items(ctx, g, pb, ib));
     std::vector<DpPlan> plans(g.NY);
@@ -366,8 +469,9 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
     if (ctx->profiling) {
         RETCHK(ctx->counters.ensure(4 * sizeof(unsigned long long)));
         counters = ctx->counters.as<unsigned long long>();
-        HIPCHK(hipMemsetAsync(counters, 0, 4 * sizeof(unsigned long long), s));
+        HIPCHK(launch_zero(counters, 8, s));
     }
+    const int *status = ctx->status.as<int>();
     for (int64_t p0 = 0; p0 < npairs; p0 += pb) {
         const int np = (int)std::min<int64_t>(pb, npairs - p0);
         PairSource ps;
@@ -396,7 +500,8 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
                              ctx->scratch.p, yi, plans[yi], s));
             if (ctx->profiling) HIPCHK(hipEventRecord(ev.back(), s));
         }
-        HIPCHK(launch_stats(g, np, ib, out_dev + 4 * p0, M, Axy, Ayx, s, recheck ? &rc : nullptr));
+        HIPCHK(launch_stats(g, np, ib, out_dev + 4 * p0, M, Axy, Ayx, s, recheck ? &rc : nullptr, nullptr,
+                            nullptr, status));
         if (recheck) {
             // FP64 re-run of the queued items of every row count, then the
             // flagged pairs' statistics again from the updated entries
@@ -410,7 +515,8 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
                 HIPCHK(launch_dp(rt, et, g, ps, np, ib, ctx->xlogx.as<double>(), nullptr,
                                  ctx->scratch.p, yi, plans64[yi], s, rc.ilist + (size_t)yi * rc.icap,
                                  rc.icount + yi, 2 * np));
-            HIPCHK(launch_stats(g, np, ib, out_dev + 4 * p0, M, Axy, Ayx, s, nullptr, rc.plist, rc.pcount));
+            HIPCHK(launch_stats(g, np, ib, out_dev + 4 * p0, M, Axy, Ayx, s, nullptr, rc.plist, rc.pcount,
+                                status));
             if (ctx->profiling) {
                 hipEvent_t b;
                 HIPCHK(hipEventCreate(&b));
@@ -475,24 +581,117 @@ int upload_pair_input(micx_ctx *ctx, const double *x, const double *y, int n, hi
 
 }  // namespace
 
-extern "C" int micx_allpairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n,
-                             double alpha, double c, int mode, double *out_dev, void *stream) {
-    RETCHK(check_common(ctx, n, alpha, c, mode));
-    if (!X_dev || !out_dev || m < 2) return MICX_EINVAL;
-    if (dtype != MICX_F32 && dtype != MICX_F64 && dtype != MICX_I32) return MICX_EINVAL;
-    HIPCHK(hipSetDevice(ctx->device));
-    hipStream_t s = (hipStream_t)stream;
+namespace {
+
+// The work of one all-pairs call, queued on s.
+int allpairs_work(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n, double alpha, double c,
+                  int mode, double *out_dev, hipStream_t s) {
     HostGeometry hg;
     make_geometry(n, micx_grid_bound(n, alpha), c, hg, ctx->compat);
-    if (!dp_fits(hg.g, n)) return MICX_ETOOBIG;
-    RETCHK(upload_geometry(ctx, hg, s));
+    RETCHK(begin_status(ctx, s));
+    RETCHK(upload_geometry(ctx, hg, s, c));
     RankTables rt;
     EquipTables et;
     RETCHK(prepare_variables(ctx, X_dev, dtype, m, n, hg.g, false, rt, et, s));
     const int64_t npairs = (int64_t)m * (m - 1) / 2;
-    RETCHK(run_pairs(ctx, rt, et, hg.g, nullptr, npairs, m, mode, out_dev, nullptr, nullptr,
-                     nullptr, s));
-    HIPCHK(hipStreamSynchronize(s));
+    RETCHK(run_pairs(ctx, rt, et, hg.g, nullptr, npairs, m, mode, out_dev, nullptr, nullptr, nullptr, s));
+    return end_status(ctx, s);
+}
+
+void drop_graph(micx_ctx *ctx) {
+    if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
+    ctx->gexec = nullptr;
+}
+
+}  // namespace
+
+extern "C" int micx_allpairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n,
+                             const micx_param *param, int mode, double *out_dev, void *stream) {
+    if (!param) return MICX_EINVAL;
+    const double alpha = param->alpha, c = param->c;
+    RETCHK(check_common(ctx, n, alpha, c, mode));
+    if (!X_dev || !out_dev || m < 2) return MICX_EINVAL;
+    if (dtype != MICX_F32 && dtype != MICX_F64 && dtype != MICX_I32) return MICX_EINVAL;
+    {
+        HostGeometry hg;
+        make_geometry(n, micx_grid_bound(n, alpha), c, hg, ctx->compat);
+        if (!dp_fits(hg.g, n)) return MICX_ETOOBIG;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    GraphKey key;
+    key.X = X_dev;
+    key.dtype = dtype;
+    key.m = m;
+    key.n = n;
+    key.mode = mode;
+    key.compat = ctx->compat;
+    key.alpha = alpha;
+    key.c = c;
+    key.tol = ctx->dp32_tol;
+    key.out = out_dev;
+    if (!ctx->graphs || ctx->profiling) {
+        drop_graph(ctx);
+        ctx->gseen = false;
+        return allpairs_work(ctx, X_dev, dtype, m, n, alpha, c, mode, out_dev, s);
+    }
+    const bool same = ctx->gseen && key == ctx->gkey && ctx->ggen == ctx->gen;
+    if (same && ctx->gexec) {
+        // replay: the whole call is one graph launch
+        HIPCHK(hipGraphLaunch(ctx->gexec, s));
+        ctx->last = s;
+        return MICX_OK;
+    }
+    drop_graph(ctx);
+    if (!same) {
+        // first call with these arguments: run it eagerly (it sizes the
+        // workspace); the next one captures
+        RETCHK(allpairs_work(ctx, X_dev, dtype, m, n, alpha, c, mode, out_dev, s));
+        ctx->gkey = key;
+        ctx->gseen = true;
+        ctx->ggen = ctx->gen;
+        return MICX_OK;
+    }
+    // second call: capture the work on the context's capture stream, after
+    // the caller's stream has reached this point, then launch the graph on
+    // the caller's stream
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(ctx->cstream, hipStreamCaptureModeRelaxed));
+    const int rc = allpairs_work(ctx, X_dev, dtype, m, n, alpha, c, mode, out_dev, ctx->cstream);
+    const hipError_t ec = hipStreamEndCapture(ctx->cstream, &graph);
+    if (rc != MICX_OK || ec != hipSuccess || ctx->gen != ctx->ggen) {
+        // the workspace moved during capture, or capture failed: run eagerly
+        if (graph) hipGraphDestroy(graph);
+        ctx->gseen = false;
+        RETCHK(rc);
+        return allpairs_work(ctx, X_dev, dtype, m, n, alpha, c, mode, out_dev, s);
+    }
+    const hipError_t ei = hipGraphInstantiate(&ctx->gexec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        ctx->gexec = nullptr;
+        ctx->gseen = false;
+        return allpairs_work(ctx, X_dev, dtype, m, n, alpha, c, mode, out_dev, s);
+    }
+    HIPCHK(hipGraphLaunch(ctx->gexec, s));
+    ctx->last = s;
+    return MICX_OK;
+}
+
+extern "C" int micx_status(micx_ctx *ctx) {
+    if (!ctx) return MICX_EINVAL;
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipStreamSynchronize(ctx->last));
+    return status_code(*ctx->hstatus);
+}
+
+extern "C" int micx_set_graphs(micx_ctx *ctx, int enable) {
+    if (!ctx) return MICX_EINVAL;
+    ctx->graphs = enable ? 1 : 0;
+    if (!enable) {
+        drop_graph(ctx);
+        ctx->gseen = false;
+    }
     return MICX_OK;
 }
 
@@ -515,20 +714,21 @@ extern "C" int micx_pearson(micx_ctx *ctx, const void *X_dev, int dtype, int m, 
     ps.m = m;
     if (pairs_host) {
         RETCHK(ctx->pairs.ensure((size_t)npairs * 2 * sizeof(int32_t)));
-        HIPCHK(hipMemcpyAsync(ctx->pairs.p, pairs_host, (size_t)npairs * 2 * sizeof(int32_t),
-                              hipMemcpyHostToDevice, s));
+        RETCHK(stage_copy(ctx, ctx->pairs.p, pairs_host, (size_t)npairs * 2 * sizeof(int32_t), s));
         ps.pairs = ctx->pairs.as<int32_t>();
     }
     RETCHK(ctx->moments.ensure((size_t)2 * m * sizeof(double)));
     double *mean = ctx->moments.as<double>();
+    RETCHK(begin_status(ctx, s));
     HIPCHK(launch_pearson(X_dev, dtype, m, n, ps, (int)npairs, mean, mean + m, stats_dev, out_dev, s));
-    HIPCHK(hipStreamSynchronize(s));
-    return MICX_OK;
+    return end_status(ctx, s);
 }
 
 extern "C" int micx_pairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n,
-                          const int32_t *pairs_host, int64_t npairs, double alpha, double c,
-                          int mode, double *out_dev, void *stream) {
+                          const int32_t *pairs_host, int64_t npairs, const micx_param *param, int mode,
+                          double *out_dev, void *stream) {
+    if (!param) return MICX_EINVAL;
+    const double alpha = param->alpha, c = param->c;
     RETCHK(check_common(ctx, n, alpha, c, mode));
     if (!X_dev || !out_dev || !pairs_host || m < 2 || npairs < 1) return MICX_EINVAL;
     if (dtype != MICX_F32 && dtype != MICX_F64 && dtype != MICX_I32) return MICX_EINVAL;
@@ -541,17 +741,16 @@ extern "C" int micx_pairs(micx_ctx *ctx, const void *X_dev, int dtype, int m, in
     HostGeometry hg;
     make_geometry(n, micx_grid_bound(n, alpha), c, hg, ctx->compat);
     if (!dp_fits(hg.g, n)) return MICX_ETOOBIG;
-    RETCHK(upload_geometry(ctx, hg, s));
+    RETCHK(begin_status(ctx, s));
+    RETCHK(upload_geometry(ctx, hg, s, c));
     RETCHK(ctx->pairs.ensure((size_t)npairs * 2 * sizeof(int32_t)));
-    HIPCHK(hipMemcpyAsync(ctx->pairs.p, pairs_host, (size_t)npairs * 2 * sizeof(int32_t),
-                          hipMemcpyHostToDevice, s));
+    RETCHK(stage_copy(ctx, ctx->pairs.p, pairs_host, (size_t)npairs * 2 * sizeof(int32_t), s));
     RankTables rt;
     EquipTables et;
     RETCHK(prepare_variables(ctx, X_dev, dtype, m, n, hg.g, false, rt, et, s));
     RETCHK(run_pairs(ctx, rt, et, hg.g, ctx->pairs.as<int32_t>(), npairs, m, mode, out_dev,
                      nullptr, nullptr, nullptr, s));
-    HIPCHK(hipStreamSynchronize(s));
-    return MICX_OK;
+    return end_status(ctx, s);
 }
 
 namespace {
@@ -879,17 +1078,15 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
     memcpy(blob.data() + mequip_off, mequip.data(), mequip.size() * sizeof(int2));
     memcpy(blob.data() + mpart_off, mpart.data(), mpart.size() * sizeof(int2));
     memcpy(blob.data() + mstats_off, mstats.data(), mstats.size() * sizeof(int2));
-    HIPCHK(hipMemcpyAsync(ar, blob.data(), host_bytes, hipMemcpyHostToDevice, s));
+    RETCHK(stage_copy(ctx, ar, blob.data(), host_bytes, s));
     RETCHK(ctx->xlogx.ensure((size_t)(nmax + 1) * sizeof(double)));
-    RETCHK(ctx->status.ensure(sizeof(int)));
     int *status = ctx->status.as<int>();
-    HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
     HIPCHK(launch_xlogx(nmax, ctx->xlogx.as<double>(), s));
     unsigned long long *counters = nullptr;
     if (ctx->profiling) {
         RETCHK(ctx->counters.ensure(4 * sizeof(unsigned long long)));
         counters = ctx->counters.as<unsigned long long>();
-        HIPCHK(hipMemsetAsync(counters, 0, 4 * sizeof(unsigned long long), s));
+        HIPCHK(launch_zero(counters, 8, s));
     }
     while ((int)ctx->dstreams.size() < kDpStreams) {
         hipStream_t st;
@@ -935,11 +1132,6 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
             HIPCHK(launch_work(et, L.hg.g, ps, (int)groups[g0 + i].idx.size(), ib, counters, s));
         }
     }
-    int hstatus = 0;
-    HIPCHK(hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (hstatus & 1) return MICX_ENONFINITE;
-    if (hstatus) return MICX_EDEVICE;
     // DP keys: every (group, row count) class goes to the launch of its shape
     std::map<DpKey, DpBucket> buckets;
     make_buckets(ctx, groups, g0, lay, mode, buckets);
@@ -972,8 +1164,7 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
     std::vector<int> allitems;
     allitems.reserve(nitems * 3);
     for (auto *kp : keys) allitems.insert(allitems.end(), kp->second.items.begin(), kp->second.items.end());
-    HIPCHK(hipMemcpyAsync(ctx->gitems.p, allitems.data(), allitems.size() * sizeof(int),
-                          hipMemcpyHostToDevice, s));
+    RETCHK(stage_copy(ctx, ctx->gitems.p, allitems.data(), allitems.size() * sizeof(int), s));
     // near-tie recheck of the 32-bit form: FP64 launch keys over every class
     // of the pass, each with a device list of the items queued for it
     // (capacity: all items of its classes), per-item flag bits and the
@@ -1032,7 +1223,7 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
         int *meta = ctx->rcmeta.as<int>();
         std::vector<int> hmeta(rkoff);
         hmeta.insert(hmeta.end(), keyof.begin(), keyof.end());
-        HIPCHK(hipMemcpyAsync(meta, hmeta.data(), hmeta.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        RETCHK(stage_copy(ctx, meta, hmeta.data(), hmeta.size() * sizeof(int), s));
         srq.band = 2.0 * bound + 1e-12;
         srq.kcount = ctx->rcwords.as<int>();
         srq.pcount = srq.kcount + rkeys.size();
@@ -1045,10 +1236,8 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
             gdev[i].nyw = (lay[i].hg.g.NY + 31) / 32;
             gdev[i].keyof = meta + rkeys.size() + kbase[i];
         }
-        HIPCHK(hipMemcpyAsync(ar + gdev_off, gdev.data(), ng * sizeof(GroupDev), hipMemcpyHostToDevice, s));
+        RETCHK(stage_copy(ctx, ar + gdev_off, gdev.data(), ng * sizeof(GroupDev), s));
         HIPCHK(launch_zero(ctx->rcwords.p, rc_words, s));
-        // the host tables above are read by the copies: keep them until done
-        HIPCHK(hipStreamSynchronize(s));
     }
     // scratch per DP stream: the largest need among the keys it runs (main
     // and recheck launches run one after the other and share it)
@@ -1098,7 +1287,7 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
     // statistics into the staging rows, once every DP key is done
     RETCHK(join());
     HIPCHK(launch_stats_g(gd, (const int2 *)(ar + mstats_off), (int)mstats.size(), s,
-                          recheck ? &srq : nullptr));
+                          recheck ? &srq : nullptr, status));
     micx_profile pp{};
     if (recheck) {
         // FP64 re-run of the queued items, key by key, then the flagged pairs'
@@ -1118,7 +1307,7 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
                                    ctx->compat, ctx->dstreams[k % kDpStreams], srq.kcount + k));
         }
         RETCHK(join());
-        HIPCHK(launch_stats_g_list(gd, srq.plist, srq.pcount, ptotal, s));
+        HIPCHK(launch_stats_g_list(gd, srq.plist, srq.pcount, ptotal, s, status));
         if (ctx->profiling) {
             HIPCHK(hipEventRecord(r1, s));
             std::vector<int> h(rkeys.size() + 1);
@@ -1133,8 +1322,8 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
             hipEventDestroy(r1);
         }
     }
-    HIPCHK(hipStreamSynchronize(s));
     if (ctx->profiling) {
+        HIPCHK(hipStreamSynchronize(s));
         for (size_t k = 0; k + 1 < ev.size(); k += 2) {
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
@@ -1223,6 +1412,7 @@ extern "C" int micx_batch(micx_ctx *ctx, const void *data_dev, int dtype,
     }
     RETCHK(ctx->bout.ensure((size_t)npairs * 4 * sizeof(double)));
     RETCHK(ctx->bidx.ensure((size_t)npairs * sizeof(int64_t)));
+    RETCHK(begin_status(ctx, s));
     micx_profile total{};
     for (size_t g0 = 0; g0 < groups.size();) {
         size_t g1 = g0, bytes = 0;
@@ -1235,16 +1425,18 @@ extern "C" int micx_batch(micx_ctx *ctx, const void *data_dev, int dtype,
         RETCHK(run_batch_pass(ctx, data_dev, dtype, pairs_host, groups, g0, g1, mode, s, total));
         g0 = g1;
     }
-    HIPCHK(hipMemcpyAsync(ctx->bidx.p, order.data(), order.size() * sizeof(int64_t),
-                          hipMemcpyHostToDevice, s));
-    HIPCHK(launch_scatter_rows(ctx->bout.as<double>(), ctx->bidx.as<int64_t>(), npairs, out_dev, s));
-    HIPCHK(hipStreamSynchronize(s));
+    RETCHK(stage_copy(ctx, ctx->bidx.p, order.data(), order.size() * sizeof(int64_t), s));
+    HIPCHK(launch_scatter_rows(ctx->bout.as<double>(), ctx->bidx.as<int64_t>(), npairs, out_dev, s,
+                               ctx->status.as<int>()));
     ctx->prof = total;
-    return MICX_OK;
+    return end_status(ctx, s);
 }
 
-extern "C" int micx_compute_score(micx_ctx *ctx, const double *x, const double *y, int n,
-                                  double alpha, double c, int mode, micx_score **out) {
+extern "C" int micx_compute_score(micx_ctx *ctx, const micx_problem *problem, const micx_param *param,
+                                  int mode, micx_score **out) {
+    if (!problem || !param) return MICX_EINVAL;
+    const int n = problem->n;
+    const double *x = problem->x, *y = problem->y, alpha = param->alpha, c = param->c;
     RETCHK(check_common(ctx, n, alpha, c, mode));
     if (!x || !y || !out) return MICX_EINVAL;
     HIPCHK(hipSetDevice(ctx->device));
@@ -1253,7 +1445,8 @@ extern "C" int micx_compute_score(micx_ctx *ctx, const double *x, const double *
     const int B = micx_grid_bound(n, alpha);
     make_geometry(n, B, c, hg, ctx->compat);
     if (!dp_fits(hg.g, n)) return MICX_ETOOBIG;
-    RETCHK(upload_geometry(ctx, hg, s));
+    RETCHK(begin_status(ctx, s));
+    RETCHK(upload_geometry(ctx, hg, s, c));
     RETCHK(upload_pair_input(ctx, x, y, n, s));
     RankTables rt;
     EquipTables et;
@@ -1264,9 +1457,11 @@ extern "C" int micx_compute_score(micx_ctx *ctx, const double *x, const double *
     double *d = ctx->dense.as<double>();
     RETCHK(run_pairs(ctx, rt, et, hg.g, ctx->pairs.as<int32_t>(), 1, 2, mode, d, d + 4,
                      d + 4 + WW, d + 4 + 2 * WW, s));
+    RETCHK(end_status(ctx, s));
     std::vector<double> h(4 + 3 * WW);
     HIPCHK(hipMemcpyAsync(h.data(), d, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    RETCHK(status_code(*ctx->hstatus));
     micx_score *sc = (micx_score *)calloc(1, sizeof(micx_score));
     if (!sc) return MICX_ENOMEM;
     sc->n = n;
@@ -1341,31 +1536,50 @@ extern "C" double micx_mcn(const micx_score *s, double eps) {
     return best;
 }
 
-extern "C" int micx_debug_item(micx_ctx *ctx, const double *x, const double *y, int n,
-                               double alpha, double c, int orient, int ry, int *yhat,
-                               int *row_starts, int *k, int *K, int *ends) {
+namespace {
+
+// Integer stages of one pair for the debug readbacks: geometry, ranks,
+// equipartitions (with row starts) and partitions of both orientations,
+// synchronised; MICX_ENONFINITE for NaN or infinite input.
+int debug_stages(micx_ctx *ctx, const micx_problem *problem, const micx_param *param, int orient, int ry,
+                 HostGeometry &hg, RankTables &rt, EquipTables &et, ItemBuffers &ib) {
+    if (!problem || !param) return MICX_EINVAL;
+    const int n = problem->n;
+    const double alpha = param->alpha, c = param->c;
     RETCHK(check_common(ctx, n, alpha, c, MICX_MODE_FP64));
     const int B = micx_grid_bound(n, alpha);
-    if (!x || !y || !yhat || !row_starts || !k || !K || !ends) return MICX_EINVAL;
+    if (!problem->x || !problem->y) return MICX_EINVAL;
     if (orient != 0 && orient != 1) return MICX_EINVAL;
     if (ry < 2 || ry > B / 2) return MICX_EINVAL;
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t s = nullptr;
-    HostGeometry hg;
     make_geometry(n, B, c, hg, ctx->compat);
+    if (ry - 2 >= hg.g.NY) return MICX_EINVAL;
     if (!dp_fits(hg.g, n)) return MICX_ETOOBIG;
-    RETCHK(upload_geometry(ctx, hg, s));
-    RETCHK(upload_pair_input(ctx, x, y, n, s));
-    RankTables rt;
-    EquipTables et;
+    RETCHK(begin_status(ctx, s));
+    RETCHK(upload_geometry(ctx, hg, s, c));
+    RETCHK(upload_pair_input(ctx, problem->x, problem->y, n, s));
     RETCHK(prepare_variables(ctx, ctx->input.p, MICX_F64, 2, n, hg.g, true, rt, et, s));
-    ItemBuffers ib;
     RETCHK(ensure_items(ctx, hg.g, 1, ib));
     PairSource ps;
     ps.pairs = ctx->pairs.as<int32_t>();
     ps.m = 2;
     HIPCHK(launch_part(rt, et, hg.g, ps, 1, ib, s));
+    RETCHK(end_status(ctx, s));
     HIPCHK(hipStreamSynchronize(s));
+    return status_code(*ctx->hstatus);
+}
+
+}  // namespace
+
+extern "C" int micx_debug_item(micx_ctx *ctx, const micx_problem *problem, const micx_param *param,
+                               int orient, int ry, int *yhat, int *row_starts, int *k, int *K, int *ends) {
+    if (!yhat || !row_starts || !k || !K || !ends) return MICX_EINVAL;
+    HostGeometry hg;
+    RankTables rt;
+    EquipTables et;
+    ItemBuffers ib;
+    RETCHK(debug_stages(ctx, problem, param, orient, ry, hg, rt, et, ib));
     const Geometry &g = hg.g;
     const int yi = ry - 2;
     const int V = orient ? 0 : 1;   // row variable
@@ -1382,5 +1596,44 @@ extern "C" int micx_debug_item(micx_ctx *ctx, const double *x, const double *y, 
     *yhat = yh;
     *k = kk;
     *K = KK;
+    return MICX_OK;
+}
+
+extern "C" int micx_debug_tables(micx_ctx *ctx, const micx_problem *problem, const micx_param *param,
+                                 int orient, int ry, int *group_start_x, int *group_start_y, int *counts) {
+    if (!group_start_x || !group_start_y) return MICX_EINVAL;
+    HostGeometry hg;
+    RankTables rt;
+    EquipTables et;
+    ItemBuffers ib;
+    RETCHK(debug_stages(ctx, problem, param, orient, ry, hg, rt, et, ib));
+    const int n = problem->n;
+    HIPCHK(hipMemcpy(group_start_x, rt.grank, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(group_start_y, rt.grank + n, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost));
+    if (!counts) return MICX_OK;
+    // the DP's own count table: a debug instance of the DP kernel writes the
+    // table it builds in LDS for both items of the row count
+    const Geometry &g = hg.g;
+    const int yi = ry - 2;
+    const size_t per = (size_t)(hg.khat[yi] + 1) * (size_t)(ry + 1);
+    RETCHK(ctx->dbg.ensure(4 * per * sizeof(int)));
+    PairSource ps;
+    ps.pairs = ctx->pairs.as<int32_t>();
+    ps.m = 2;
+    HIPCHK(launch_dp_debug(rt, et, g, ps, ib, ctx->xlogx.as<double>(), yi, ctx->cus, ctx->dbg.as<int>(), nullptr));
+    int yh = 0, KK = 0;
+    const int V = orient ? 0 : 1;
+    HIPCHK(hipMemcpy(&yh, et.yhat + (size_t)V * g.NY + yi, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&KK, ib.K + (size_t)orient * g.NY + yi, sizeof(int), hipMemcpyDeviceToHost));
+    std::vector<int> tab(4 * per);
+    HIPCHK(hipMemcpy(tab.data(), ctx->dbg.as<int>(), 4 * per * sizeof(int), hipMemcpyDeviceToHost));
+    // the kernel's records: (K+1) rows of stride ry+1, e_t then the rows'
+    // counts; the two count scans must agree
+    const int *t0 = tab.data() + (size_t)orient * per, *t1 = tab.data() + (2 + (size_t)orient) * per;
+    for (int t = 0; t <= KK; t++)
+        for (int r = 0; r <= yh; r++)
+            if (t0[(size_t)t * (ry + 1) + r] != t1[(size_t)t * (ry + 1) + r]) return MICX_EDEVICE;
+    for (int t = 0; t <= KK; t++)
+        for (int r = 0; r < yh; r++) counts[(size_t)t * yh + r] = t0[(size_t)t * (ry + 1) + 1 + r];
     return MICX_OK;
 }

@@ -265,7 +265,7 @@ hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry
     a.scratch = scratch; a.slot_bytes = p.slot_bytes;
     a.lds_L = p.lds_L; a.lds_stage = p.lds_stage; a.lds_wave = p.lds_wave;
     a.groups = nullptr; a.gitems = nullptr; a.compat = g.compat;
-    a.ilist = ilist; a.icount = icount;
+    a.ilist = ilist; a.icount = icount; a.dbg = nullptr;
     if (ilist) a.nitems = std::min(a.nitems, cap);
     dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T);
     if (!k) return hipErrorInvalidValue;
@@ -277,6 +277,43 @@ hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry
     const int blocks = (waves + p.WPB - 1) / p.WPB;
     hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * p.WPB), p.lds, s, a);
     return hipGetLastError();
+}
+
+// The debug instances of the DP kernel (count tables only) for the two items
+// of row count class yi of one pair: the label-run count scan of passes under
+// 20 layers and the ballot scan of wider passes, each writing (khat+1)(y+1)
+// ints per item (records of stride y+1: e_t, then the rows' counts), to
+// out[0..] and out[2*(khat+1)(y+1)..].
+hipError_t launch_dp_debug(const RankTables &rt, const EquipTables &et, const Geometry &g, PairSource ps,
+                           const ItemBuffers &ib, const double *xlogx, int yi, int cus, int *out,
+                           hipStream_t s) {
+    const dp_kernel_t ks[2] = {k_dp<double, 4, 0, 1, false, true>, k_dp<double, 24, 0, 1, false, true>};
+    const int nls[2] = {4, 24};
+    for (int v = 0; v < 2; v++) {
+        DpPlan p = dp_shape(g, rt.n, yi, MICX_MODE_FP64, 0.0);
+        p.NL = nls[v];
+        p.YR = 0;
+        p.T = 1;
+        p.RS = yi + 3;
+        dp_fit_lds(p, rt.n, (size_t)p.KS * p.RS * 4, cus);
+        DpArgs a = {};
+        a.n = rt.n; a.NY = g.NY; a.KSUM = g.KSUM; a.ASUM = g.ASUM;
+        a.yi = yi; a.x = p.x; a.RS = p.RS; a.KS = p.KS;
+        a.nitems = 2; a.npairs = 1; a.SB = p.SB; a.ps = ps;
+        a.yhat = et.yhat; a.koff = g.koff; a.aoff = g.aoff;
+        a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.src = ib.src; a.A = ib.A;
+        a.lab = ib.lab; a.lab_row = ib.lab_row; a.lab16 = ib.lab16;
+        a.xlogx = xlogx; a.compat = g.compat;
+        a.lds_L = p.lds_L; a.lds_stage = p.lds_stage; a.lds_wave = p.lds_wave;
+        a.dbg = out + (size_t)v * 2 * p.KS * p.RS;
+        if (p.lds > 160 * 1024) return hipErrorInvalidValue;
+        hipError_t e = ensure_lds_attr((const void *)ks[v]);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(ks[v], dim3((2 + p.WPB - 1) / p.WPB), dim3(64 * p.WPB), p.lds, s, a);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_dp_items(const DpGroup *groups, const int *gitems, int nitems, int nmax,

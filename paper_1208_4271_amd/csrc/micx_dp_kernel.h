@@ -71,6 +71,7 @@ struct DpArgs {
     // (pair*2+orientation; the GR instances take gitems) and its length, both
     // in device memory, or null: every item
     const int *ilist, *icount;
+    int *dbg;                    // debug instances: the count tables, (KS*RS) ints per item
 };
 
 template <class V> struct DpVal;
@@ -115,7 +116,9 @@ struct alignas(16) Pack {
     V v[DpVal<V>::PK];
 };
 
-template <class V, int NL, int YR, int T, bool GR>
+// DBG: a debug instance that writes each item's cumulative count table (as
+// counts) to a.dbg and skips the DP (bit-exact readback of item 10a).
+template <class V, int NL, int YR, int T, bool GR, bool DBG = false>
 __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
     using DV = DpVal<V>;
     constexpr int PK = DV::PK;
@@ -337,6 +340,11 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
             }
         }
         wave_sync();
+        if constexpr (DBG) {
+            int *o = a.dbg + (size_t)wi * KS * RS;
+            for (int k = lane; k < (K + 1) * RS; k += 64) o[k] = rec[k] / VB;
+            continue;
+        }
 
         // column cost h(s,t) with both records read from LDS (any row count)
         auto hcost = [&](int s, int t) -> V {

@@ -154,7 +154,7 @@ hipError_t launch_stats_g(const GroupDev *G, const int2 *map, int blocks, hipStr
                           const StreamRecheck *flag = nullptr, const int *status = nullptr);
 // statistics again for the flagged pairs of a pass (after the FP64 recheck)
 hipError_t launch_stats_g_list(const GroupDev *G, const int *plist, const int *pcount, int cap,
-                               hipStream_t s);
+                               hipStream_t s, const int *status = nullptr);
 
 // Pair source for a batch: either an explicit list (pairs != null) or the
 // row-major upper triangle starting at global pair index p0.
@@ -186,6 +186,11 @@ hipError_t launch_dp_items(const DpGroup *groups, const int *gitems, int nitems,
                            const DpPlan &p, int compat, hipStream_t s, const int *icount = nullptr);
 hipError_t launch_fxtable(int n, const DpPlan &p, const double *xlogx, uint32_t *tab,
                           hipStream_t s);
+// Debug instances of the DP kernel: the count tables of the two items of
+// class yi of one pair, from both count scans (see micx_debug_tables).
+hipError_t launch_dp_debug(const RankTables &rt, const EquipTables &et, const Geometry &g, PairSource ps,
+                           const ItemBuffers &ib, const double *xlogx, int yi, int cus, int *out,
+                           hipStream_t s);
 // ilist/icount (device, may be null): run only the items ilist[0..*icount)
 // (pair*2+orientation) of the class, at most `cap` of them.
 hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry &g,
@@ -205,10 +210,15 @@ hipError_t launch_stats(const Geometry &g, int npairs, const ItemBuffers &ib, do
 // memset nodes).
 hipError_t launch_zero(void *p, size_t nwords, hipStream_t s);
 hipError_t launch_xlogx(int n, double *xlogx, hipStream_t s);
+// Grid geometry of (n, B, c) into geo (4 NY ints: xcnt | khat | koff | aoff),
+// computed on the device with the host's arithmetic; B already lowered by
+// MICX_COMPAT_BOUND_STRICT.
+hipError_t launch_geometry(int n, int B, double c, int compat, int NY, int *geo, hipStream_t s);
 hipError_t launch_gather(const void *src, int esize, const int64_t *offs, int nv, int n, void *dst,
                          hipStream_t s);
+// status (device, may be null): nothing is written while *status != 0
 hipError_t launch_scatter_rows(const double *src, const int64_t *idx, int64_t rows, double *dst,
-                               hipStream_t s);
+                               hipStream_t s, const int *status = nullptr);
 // Accumulates the algorithmic work of a batch into counters[0..3]
 // (items, dp_cells, h_evals, h_terms).
 hipError_t launch_work(const EquipTables &et, const Geometry &g, PairSource ps, int npairs,

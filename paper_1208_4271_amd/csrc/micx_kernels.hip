@@ -68,6 +68,30 @@ __global__ void k_xlogx(int n, double *L) {
     if (j <= n) L[j] = j > 1 ? (double)j * log((double)j) : 0.0;
 }
 
+// --------------------------------------------------------------- k_geometry
+// Grid geometry on the device (asynchronous calls need no host staging for it): x(y) = floor(B/y),
+// khat(y) = max(1, min(floor(c x(y)) (+1 with MICX_COMPAT_KHAT_PLUS1), n)),
+// and the prefix offsets of the per-item end buffers and score rows; the
+// same arithmetic as the host's geometry of the other entry points.
+__global__ void k_geometry(int n, int B, double c, int compat, int NY, int *geo) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int ks = 0, as = 0;
+    for (int yi = 0; yi < NY; yi++) {
+        const int y = yi + 2, x = B / y;
+        double kd = floor(c * (double)x);
+        if (compat & MICX_COMPAT_KHAT_PLUS1) kd += 1.0;
+        int kh = kd >= (double)n ? n : (int)kd;
+        if (kh < 1) kh = 1;
+        geo[yi] = x;
+        geo[NY + yi] = kh;
+        geo[2 * NY + yi] = ks;
+        geo[3 * NY + yi] = as;
+        ks += kh;
+        as += x - 1;
+    }
+}
+
+
 // ------------------------------------------------------------------- k_rank
 // One workgroup per variable.  Bitonic sort of (key, sample index) pairs in
 // LDS (N2 = next power of two >= n), then tie-group starts by a max-scan.
@@ -627,6 +651,11 @@ hipError_t launch_work(const EquipTables &et, const Geometry &g, PairSource ps, 
     return hipGetLastError();
 }
 
+hipError_t launch_geometry(int n, int B, double c, int compat, int NY, int *geo, hipStream_t s) {
+    hipLaunchKernelGGL(k_geometry, dim3(1), dim3(64), 0, s, n, B, c, compat, NY, geo);
+    return hipGetLastError();
+}
+
 hipError_t launch_xlogx(int n, double *xlogx, hipStream_t s) {
     hipLaunchKernelGGL(k_xlogx, dim3((n + 256) / 256), dim3(256), 0, s, n, xlogx);
     return hipGetLastError();
@@ -707,7 +736,9 @@ __global__ void k_gather(const E *src, const int64_t *offs, int n, E *dst) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = s[i];
 }
 
-__global__ void k_scatter_rows(const double *src, const int64_t *idx, int64_t rows, double *dst) {
+__global__ void k_scatter_rows(const double *src, const int64_t *idx, int64_t rows, double *dst,
+                               const int *status) {
+    if (status && *status) return;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= 4 * rows) return;
     dst[4 * idx[k >> 2] + (k & 3)] = src[k];
@@ -725,10 +756,10 @@ hipError_t launch_gather(const void *src, int esize, const int64_t *offs, int nv
 }
 
 hipError_t launch_scatter_rows(const double *src, const int64_t *idx, int64_t rows, double *dst,
-                               hipStream_t s) {
+                               hipStream_t s, const int *status) {
     const int64_t th = 4 * rows;
     hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)((th + 255) / 256)), dim3(256), 0, s, src, idx,
-                       rows, dst);
+                       rows, dst, status);
     return hipGetLastError();
 }
 
@@ -806,7 +837,9 @@ __global__ void k_stats_g(const GroupDev *G, const int2 *map, StreamRecheck q, c
 }
 
 // the flagged pairs of a pass, (group, pair) each
-__global__ void k_stats_g_list(const GroupDev *G, const int *plist, const int *pcount, int cap) {
+__global__ void k_stats_g_list(const GroupDev *G, const int *plist, const int *pcount, int cap,
+                               const int *status) {
+    if (status && *status) return;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= min(*pcount, cap)) return;
     stats_g_pair(G, plist[2 * k], plist[2 * k + 1], nullptr);
@@ -848,9 +881,10 @@ hipError_t launch_stats_g(const GroupDev *G, const int2 *map, int blocks, hipStr
 }
 
 hipError_t launch_stats_g_list(const GroupDev *G, const int *plist, const int *pcount, int cap,
-                               hipStream_t s) {
+                               hipStream_t s, const int *status) {
     if (cap <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_stats_g_list, dim3((cap + 127) / 128), dim3(128), 0, s, G, plist, pcount, cap);
+    hipLaunchKernelGGL(k_stats_g_list, dim3((cap + 127) / 128), dim3(128), 0, s, G, plist, pcount, cap,
+                       status);
     return hipGetLastError();
 }
 

@@ -45,28 +45,6 @@ __global__ void k_status_out(const int *status, int *out) {
     }
 }
 
-// Grid geometry on the device (no host staging): x(y) = floor(B/y),
-// khat(y) = max(1, min(floor(c x(y)) (+1 with MICX_COMPAT_KHAT_PLUS1), n)),
-// and the prefix offsets of the per-item end buffers and score rows; the
-// same arithmetic as the host's geometry of the other entry points.
-__global__ void k_geometry(int n, int B, double c, int compat, int NY, int *geo) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int ks = 0, as = 0;
-    for (int yi = 0; yi < NY; yi++) {
-        const int y = yi + 2, x = B / y;
-        double kd = floor(c * (double)x);
-        if (compat & MICX_COMPAT_KHAT_PLUS1) kd += 1.0;
-        int kh = kd >= (double)n ? n : (int)kd;
-        if (kh < 1) kh = 1;
-        geo[yi] = x;
-        geo[NY + yi] = kh;
-        geo[2 * NY + yi] = ks;
-        geo[3 * NY + yi] = as;
-        ks += kh;
-        as += x - 1;
-    }
-}
-
 }  // namespace
 
 // Called by micx_ctx_create with `device` current: resolves the array's
@@ -86,13 +64,14 @@ int noalloc_init(int device) {
 using namespace micx;
 
 extern "C" int micx_score_noalloc(micx_ctx *ctx, const void *x_dev, const void *y_dev, int dtype,
-                                  int n, double alpha, double c, int mode, double *stats_dev,
+                                  int n, const micx_param *param, int mode, double *stats_dev,
                                   double *mats_dev, int *status_dev, void *stream) {
     int device = 0, cus = 0, compat = 0;
     double tol = 0.0;
-    if (!ctx || !x_dev || !y_dev || !stats_dev) return MICX_EINVAL;
+    if (!ctx || !x_dev || !y_dev || !stats_dev || !param) return MICX_EINVAL;
     ctx_params(ctx, &device, &cus, &compat, &tol);
-    if (micx_check_param(alpha, c)) return MICX_EINVAL;
+    if (micx_check_param(param)) return MICX_EINVAL;
+    const double alpha = param->alpha, c = param->c;
     if (mode != MICX_MODE_FP64 && mode != MICX_MODE_DP32) return MICX_EINVAL;
     if (dtype != MICX_F32 && dtype != MICX_F64 && dtype != MICX_I32) return MICX_EINVAL;
     if (n < 2) return MICX_EINVAL;
@@ -246,8 +225,7 @@ extern "C" int micx_score_noalloc(micx_ctx *ctx, const void *x_dev, const void *
         if ((expr) != hipSuccess) return MICX_EDEVICE; \
     } while (0)
     NACHK(launch_zero(status, words, s));
-    hipLaunchKernelGGL(k_geometry, dim3(1), dim3(64), 0, s, n, B, c, compat, NY, geo);
-    NACHK(hipGetLastError());
+    NACHK(launch_geometry(n, B, c, compat, NY, geo, s));
     NACHK(hipMemcpyAsync(base + o_X, x_dev, (size_t)n * esize, hipMemcpyDeviceToDevice, s));
     NACHK(hipMemcpyAsync(base + o_X + (size_t)n * esize, y_dev, (size_t)n * esize, hipMemcpyDeviceToDevice, s));
     NACHK(launch_xlogx(n, (double *)xlogx, s));

@@ -349,3 +349,47 @@ def test_nonlinearity_index():
     rho = oracle.pearson(x, y)
     assert abs(mic - 1.0) <= 1e-12 and rho < 0.9
     assert abs(oracle.nonlinearity(mic, rho) - (1.0 - rho * rho)) <= 1e-15
+
+
+# ------------------------------------------- count table and tie-group starts
+def test_fig2_count_table():
+    # App. A item 10a on Fig. 2's data: with the printed rows Q and clumps P
+    # (no superclumping: khat = 15 * floor(14/3) > 5 clumps), N[t][r] counts
+    # the points of clumps 1..t in row r+1
+    rows = np.array(_read_golden("fig2_getclumps.txt"), dtype=np.float64)
+    a, b = rows[:, 0], rows[:, 1]
+    Q, P = rows[:, 2].astype(int), rows[:, 3].astype(int)
+    K = P.max()
+    want = np.zeros((K + 1, 3), dtype=np.int32)
+    for t in range(1, K + 1):
+        for r in range(3):
+            want[t, r] = int(((P <= t) & (Q == r + 1)).sum())
+    got = oracle.counts(a, b, 1.0, 15.0, 0, 3)
+    assert np.array_equal(got, want)
+
+
+def test_count_table_invariants_on_tied_data():
+    # the last row holds the row sizes; each step adds exactly the points of
+    # one superclump (its size from the item's ends); counts never decrease
+    rng = np.random.default_rng(31)
+    n = 300
+    x = np.floor(rng.uniform(0, 30, n))
+    y = np.floor(rng.uniform(0, 12, n))
+    for orient in (0, 1):
+        for ry, c in ((2, 15.0), (4, 15.0), (5, 1.0), (9, 2.0)):
+            it = oracle.item(x, y, 0.6, c, orient, ry)
+            N = oracle.counts(x, y, 0.6, c, orient, ry)
+            assert N.shape == (it["K"] + 1, it["yhat"])
+            sizes = np.diff(np.concatenate([it["row_starts"][:it["yhat"]], [n]]))
+            assert np.array_equal(N[-1], sizes)
+            steps = np.diff(N, axis=0)
+            assert (steps >= 0).all()
+            assert np.array_equal(steps.sum(axis=1), np.diff(np.concatenate([[0], it["ends"]])))
+
+
+def test_group_starts_brute_force():
+    rng = np.random.default_rng(32)
+    for n in (1, 2, 17, 200):
+        v = np.floor(rng.uniform(0, 6, n)) * 0.5
+        want = np.array([int((v < v[j]).sum()) for j in range(n)], dtype=np.int32)
+        assert np.array_equal(oracle.group_starts(v), want)
