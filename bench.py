@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the grid-bound scaling sweep (uniform random data, "
                          "alpha in {0.5, 0.6, 0.7}, growing n)")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch every all-pairs call's kernels one by one (no captured graph)")
     ap.add_argument("--no-counts", action="store_true",
                     help="skip the RNA-seq-shaped counts workload (2000 x 1340 int32)")
     ap.add_argument("--no-stream", action="store_true",
@@ -372,6 +374,8 @@ def main():
     import workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.no_graphs:
+        micx.set_graphs(False)
     alpha, c = 0.6, 15.0
     X, planted = workloads.microarray_matrix()
     X = X[: args.m]
