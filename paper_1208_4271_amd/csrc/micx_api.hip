@@ -69,7 +69,7 @@ struct micx_ctx {
     unsigned gen = 0;         // workspace generation (see DevBuf)
     DevBuf perm, gsize, grank, rowof, yhat, rowstart, xlogx, status;
     DevBuf geo;        // xcnt | khat | koff | aoff
-    DevBuf cbuf, sbuf, Kb, kb, srcb, A, scratch, pairs, input, out, dense;
+    DevBuf cbuf, sbuf, Kb, kb, srcb, yhb, A, scratch, pairs, input, out, dense;
     DevBuf counters, fxtab, lab;
     DevBuf moments;                    // micx_pearson: per-variable mean and 1/norm
     DevBuf bdata, boffs, bout, bidx;   // micx_batch: gathered variables, offsets, staged results
@@ -81,6 +81,8 @@ struct micx_ctx {
     DevBuf rcmeta;                     // near-tie recheck of a batch pass: key offsets, key of each class
     DevBuf arena, gitems;              // micx_batch: per-pass group buffers, DP item lists
     DevBuf dbg;                        // micx_debug_tables: the DP's count table
+    DevBuf grp;                        // the batch of a pair call as one group of the descriptor kernels
+    DevBuf litems;                     // descriptors of the x = 2 row counts of a batch (one launch)
     std::vector<hipStream_t> dstreams; // micx_batch: DP launches of different shapes run side by side
     // pinned host memory: the device status word of the last call, and a
     // staging ring for host-to-device copies of asynchronous calls
@@ -99,9 +101,9 @@ struct micx_ctx {
     hipStream_t cstream = nullptr;     // capture stream
     std::vector<DevBuf *> bufs() {
         return {&perm, &gsize, &grank, &rowof, &yhat, &rowstart, &xlogx, &status, &geo, &cbuf, &sbuf,
-                &Kb, &kb, &srcb, &A, &scratch, &pairs, &input, &out, &dense, &counters, &fxtab, &lab,
+                &Kb, &kb, &srcb, &yhb, &A, &scratch, &pairs, &input, &out, &dense, &counters, &fxtab, &lab,
                 &moments, &bdata, &boffs, &bout, &bidx, &rcwords, &rclist, &rcpairs, &rcmeta, &arena,
-                &gitems, &dbg};
+                &gitems, &dbg, &grp, &litems};
     }
 };
 
@@ -369,7 +371,7 @@ int batch_pairs(micx_ctx *ctx, const Geometry &g, int64_t total) {
     static_assert(sizeof(size_t) >= 8, "64-bit sizes");
     const size_t per_pair = 2 * (2 * (size_t)g.KSUM * sizeof(int) + 3 * (size_t)g.NY * sizeof(int) +
                                  (size_t)g.ASUM * sizeof(double) + (size_t)g.NY * lab_row_bytes(g) +
-                                 (size_t)g.NY * sizeof(int) + 8);
+                                 2 * (size_t)g.NY * sizeof(int) + 8);
     if (ctx->batch_budget == 0) {
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = (size_t)6 << 30;
@@ -390,6 +392,7 @@ int ensure_items(micx_ctx *ctx, const Geometry &g, int pb, ItemBuffers &ib) {
     RETCHK(ctx->Kb.ensure(npo * g.NY * sizeof(int)));
     RETCHK(ctx->kb.ensure(npo * g.NY * sizeof(int)));
     RETCHK(ctx->srcb.ensure(npo * g.NY * sizeof(int)));
+    RETCHK(ctx->yhb.ensure(npo * g.NY * sizeof(int)));
     RETCHK(ctx->A.ensure(npo * g.ASUM * sizeof(double)));
     ib.lab16 = lab_bytes(g) == 2;
     ib.lab_row = lab_row_bytes(g);
@@ -400,6 +403,7 @@ int ensure_items(micx_ctx *ctx, const Geometry &g, int pb, ItemBuffers &ib) {
     ib.K = ctx->Kb.as<int>();
     ib.k = ctx->kb.as<int>();
     ib.src = ctx->srcb.as<int>();
+    ib.Yh = ctx->yhb.as<int>();
     ib.A = ctx->A.as<double>();
     return MICX_OK;
 }
@@ -410,58 +414,115 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
               const int32_t *pairs_dev, int64_t npairs, int m, int mode, double *out_dev,
               double *M, double *Axy, double *Ayx, hipStream_t s) {
     const int pb = batch_pairs(ctx, g, npairs);
+    const int n = rt.n;
     ItemBuffers ib;
     RETCHK(ensure_items(ctx, g, pb, ib));
     std::vector<DpPlan> plans(g.NY);
     size_t scratch = 0;
-    int nfx = 0;
-    double bound = 0.0;
-    auto grid_bytes = [&](const DpPlan &p) {
-        const size_t waves = (size_t)std::min<int64_t>(p.max_waves, 2 * (int64_t)pb);
+    auto grid_bytes = [&](const DpPlan &p, int64_t items) {
+        const size_t waves = (size_t)std::min<int64_t>(p.max_waves, items);
         return ((waves + p.WPB - 1) / p.WPB) * p.WPB * p.slot_bytes;
     };
-    for (int yi = 0; yi < g.NY; yi++) {
-        plans[yi] = dp_plan(g, rt.n, yi, ctx->cus, mode, ctx->dp32_tol);
-        scratch = std::max(scratch, grid_bytes(plans[yi]));
-        if (plans[yi].fx) {
-            nfx++;
-            bound = std::max(bound, plans[yi].bound);
+    // the row counts with x = 2 (one layer at the last target only, the lean
+    // shape) form one launch over all their items: the last classes, sharing
+    // the smallest fixed-point scale among them (that of the largest y)
+    int ylean = g.NY;
+    while (ylean > 0 && g.B / (ylean + 1) == 2) ylean--;
+    for (int yi = 0; yi < g.NY; yi++) plans[yi] = dp_plan(g, n, yi, ctx->cus, mode, ctx->dp32_tol);
+    DpPlan lean;
+    std::vector<double> bnd(g.NY, 0.0);
+    bool lean_fx = false;
+    if (ylean < g.NY) {
+        lean = dp_shape(g, n, g.NY - 1, mode, ctx->dp32_tol);
+        lean_fx = lean.fx;
+        size_t rec = 0, slot = 0;
+        for (int yi = ylean; yi < g.NY; yi++) {
+            const int y = yi + 2;
+            bnd[yi] = 0.5 * (double)(y + 1) * 2.0 / (lean.scale * (double)n * log(2.0));
+            if (bnd[yi] > ctx->dp32_tol) lean_fx = false;
+            rec = std::max(rec, (size_t)(g.khat_host[yi] + 1) * (size_t)(y + 1) * 4);
         }
+        if (!lean_fx) {
+            lean = dp_shape(g, n, g.NY - 1, MICX_MODE_FP64, 0.0);
+            for (int yi = ylean; yi < g.NY; yi++) bnd[yi] = 0.0;
+        }
+        for (int yi = ylean; yi < g.NY; yi++)
+            slot = std::max(slot, (size_t)2 * (size_t)(g.khat_host[yi] + 1) * (lean_fx ? 4 : 8));
+        lean.slot_bytes = slot;
+        lean.groups = true;
+        dp_fit_lds(lean, n, rec, ctx->cus);
+        scratch = std::max(scratch, grid_bytes(lean, (int64_t)(g.NY - ylean) * 2 * pb));
+        RETCHK(ctx->litems.ensure((size_t)(g.NY - ylean) * 2 * pb * 3 * sizeof(int)));
     }
-    // near-tie recheck of the 32-bit form: FP64 plans of every row count, the
-    // item flags, per-row-count item lists and the flagged pairs (Recheck)
+    int nfx = 0;
+    double bound = 0.0;
+    for (int yi = 0; yi < g.NY; yi++) {
+        if (yi < ylean) {
+            scratch = std::max(scratch, grid_bytes(plans[yi], 2 * (int64_t)pb));
+            if (plans[yi].fx) bnd[yi] = plans[yi].bound;
+        }
+        const bool fx = yi < ylean ? plans[yi].fx : lean_fx;
+        nfx += fx ? 1 : 0;
+        bound = std::max(bound, bnd[yi]);
+    }
+    // near-tie recheck of the 32-bit form (Recheck): the queued items run in
+    // FP64 in one launch of a descriptor kernel that takes any row count
+    // (eight layers per pass, counts read from LDS)
     const bool recheck = nfx > 0;
-    std::vector<DpPlan> plans64;
     Recheck rc;
     size_t rc_words = 0;
+    DpPlan gen;
+    const size_t icap = (size_t)g.NY * 2 * pb;
     if (recheck) {
-        plans64.resize(g.NY);
+        gen = dp_shape(g, n, 0, MICX_MODE_FP64, 0.0);
+        gen.NL = 8;
+        gen.YR = 0;
+        gen.T = 1;
+        gen.groups = true;
+        size_t rec = 0, slot = 0;
         for (int yi = 0; yi < g.NY; yi++) {
-            plans64[yi] = dp_plan(g, rt.n, yi, ctx->cus, MICX_MODE_FP64, 0.0);
-            scratch = std::max(scratch, grid_bytes(plans64[yi]));
+            const size_t kh1 = (size_t)g.khat_host[yi] + 1;
+            rec = std::max(rec, kh1 * (size_t)(yi + 3) * 4);
+            slot = std::max(slot, (size_t)(g.B / (yi + 2)) * kh1 * 8);
         }
+        gen.slot_bytes = slot;
+        dp_fit_lds(gen, n, rec, ctx->cus);
+        scratch = std::max(scratch, grid_bytes(gen, (int64_t)icap));
         rc.band = 2.0 * bound + 1e-12;
         rc.nyw = (g.NY + 31) / 32;
-        rc.icap = 2 * pb;
-        rc_words = (size_t)g.NY + 1 + (size_t)rc.icap * rc.nyw;
+        rc_words = 2 + (size_t)2 * pb * rc.nyw;
         RETCHK(ctx->rcwords.ensure(rc_words * sizeof(unsigned)));
-        RETCHK(ctx->rclist.ensure((size_t)g.NY * rc.icap * sizeof(int)));
+        RETCHK(ctx->rclist.ensure(icap * 3 * sizeof(int)));
         RETCHK(ctx->rcpairs.ensure((size_t)pb * sizeof(int)));
         rc.icount = ctx->rcwords.as<int>();
-        rc.pcount = rc.icount + g.NY;
+        rc.pcount = rc.icount + 1;
         rc.iflag = (unsigned *)(rc.pcount + 1);
         rc.ilist = ctx->rclist.as<int>();
         rc.plist = ctx->rcpairs.as<int>();
     }
     RETCHK(ctx->scratch.ensure(scratch));
-    // fixed-point cost tables, one per row count that runs in 32 bits
-    const size_t tabn = (size_t)rt.n + 1;
+    RETCHK(ctx->grp.ensure(sizeof(DpGroup)));
+    DpGroup *grp = ctx->grp.as<DpGroup>();
+    // fixed-point cost tables of the row counts that run in 32 bits, in
+    // launches of up to kFxBatch classes
+    const size_t tabn = (size_t)n + 1;
     if (nfx) {
         RETCHK(ctx->fxtab.ensure((size_t)g.NY * tabn * sizeof(uint32_t)));
-        for (int yi = 0; yi < g.NY; yi++)
-            if (plans[yi].fx)
-                HIPCHK(launch_fxtable(rt.n, plans[yi], ctx->xlogx.as<double>(),
-                                      ctx->fxtab.as<uint32_t>() + yi * tabn, s));
+        FxScales sc;
+        int cnt = 0;
+        for (int yi = 0; yi <= g.NY; yi++) {
+            const bool flush = yi == g.NY || cnt == kFxBatch;
+            if (flush && cnt) {
+                HIPCHK(launch_fxtables(n, sc, cnt, ctx->xlogx.as<double>(), ctx->fxtab.as<uint32_t>(), tabn, s));
+                cnt = 0;
+            }
+            if (yi == g.NY) break;
+            const bool fx = yi < ylean ? plans[yi].fx : (lean_fx && yi == g.NY - 1);
+            if (!fx) continue;
+            sc.scale[cnt] = yi < ylean ? plans[yi].scale : lean.scale;
+            sc.cls[cnt] = yi;
+            cnt++;
+        }
     }
     std::vector<hipEvent_t> ev, ev_rc;
     unsigned long long *counters = nullptr;
@@ -471,6 +532,14 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
         counters = ctx->counters.as<unsigned long long>();
         HIPCHK(launch_zero(counters, 8, s));
     }
+    auto mark = [&](std::vector<hipEvent_t> &v) -> int {
+        if (!ctx->profiling) return MICX_OK;
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        v.push_back(e);
+        HIPCHK(hipEventRecord(e, s));
+        return MICX_OK;
+    };
     const int *status = ctx->status.as<int>();
     for (int64_t p0 = 0; p0 < npairs; p0 += pb) {
         const int np = (int)std::min<int64_t>(pb, npairs - p0);
@@ -483,50 +552,62 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
             ps.pairs = nullptr;
             ps.p0 = p0;
         }
+        // the batch as one group of the descriptor kernels
+        DpGroup dg;
+        dg.n = n;
+        dg.NY = g.NY;
+        dg.KSUM = g.KSUM;
+        dg.ASUM = g.ASUM;
+        dg.lab16 = ib.lab16;
+        dg.lab_row = ib.lab_row;
+        dg.xcnt = g.xcnt;
+        dg.khat = g.khat;
+        dg.koff = g.koff;
+        dg.aoff = g.aoff;
+        dg.Yh = ib.Yh;
+        dg.cbuf = ib.cbuf;
+        dg.sbuf = ib.sbuf;
+        dg.K = ib.K;
+        dg.src = ib.src;
+        dg.lab = ib.lab;
+        dg.A = ib.A;
+        HIPCHK(launch_put_group(dg, grp, s));
         if (recheck) HIPCHK(launch_zero(ctx->rcwords.p, rc_words, s));
         HIPCHK(launch_part(rt, et, g, ps, np, ib, s));
         if (counters) HIPCHK(launch_work(et, g, ps, np, ib, counters, s));
-        for (int yi = 0; yi < g.NY; yi++) {
-            if (ctx->profiling) {
-                hipEvent_t a, b;
-                HIPCHK(hipEventCreate(&a));
-                HIPCHK(hipEventCreate(&b));
-                ev.push_back(a);
-                ev.push_back(b);
-                HIPCHK(hipEventRecord(a, s));
-            }
+        for (int yi = 0; yi < ylean; yi++) {
+            RETCHK(mark(ev));
             const uint32_t *tab = plans[yi].fx ? ctx->fxtab.as<uint32_t>() + yi * tabn : nullptr;
             HIPCHK(launch_dp(rt, et, g, ps, np, ib, ctx->xlogx.as<double>(), tab,
                              ctx->scratch.p, yi, plans[yi], s));
-            if (ctx->profiling) HIPCHK(hipEventRecord(ev.back(), s));
+            RETCHK(mark(ev));
+        }
+        if (ylean < g.NY) {
+            HIPCHK(launch_range_items(ylean, g.NY - ylean, 2 * np, ctx->litems.as<int>(), s));
+            RETCHK(mark(ev));
+            const uint32_t *tab = lean_fx ? ctx->fxtab.as<uint32_t>() + (size_t)(g.NY - 1) * tabn : nullptr;
+            HIPCHK(launch_dp_items(grp, ctx->litems.as<int>(), (g.NY - ylean) * 2 * np, n,
+                                   ctx->xlogx.as<double>(), tab, ctx->scratch.p, lean, g.compat, s));
+            RETCHK(mark(ev));
         }
         HIPCHK(launch_stats(g, np, ib, out_dev + 4 * p0, M, Axy, Ayx, s, recheck ? &rc : nullptr, nullptr,
                             nullptr, status));
         if (recheck) {
-            // FP64 re-run of the queued items of every row count, then the
-            // flagged pairs' statistics again from the updated entries
-            if (ctx->profiling) {
-                hipEvent_t a;
-                HIPCHK(hipEventCreate(&a));
-                ev_rc.push_back(a);
-                HIPCHK(hipEventRecord(a, s));
-            }
-            for (int yi = 0; yi < g.NY; yi++)
-                HIPCHK(launch_dp(rt, et, g, ps, np, ib, ctx->xlogx.as<double>(), nullptr,
-                                 ctx->scratch.p, yi, plans64[yi], s, rc.ilist + (size_t)yi * rc.icap,
-                                 rc.icount + yi, 2 * np));
+            // FP64 re-run of the queued items, then the flagged pairs'
+            // statistics again from the updated entries
+            RETCHK(mark(ev_rc));
+            HIPCHK(launch_dp_items(grp, rc.ilist, (int)std::min<size_t>(icap, INT32_MAX), n,
+                                   ctx->xlogx.as<double>(), nullptr, ctx->scratch.p, gen, g.compat, s,
+                                   rc.icount));
             HIPCHK(launch_stats(g, np, ib, out_dev + 4 * p0, M, Axy, Ayx, s, nullptr, rc.plist, rc.pcount,
                                 status));
+            RETCHK(mark(ev_rc));
             if (ctx->profiling) {
-                hipEvent_t b;
-                HIPCHK(hipEventCreate(&b));
-                ev_rc.push_back(b);
-                HIPCHK(hipEventRecord(b, s));
-                std::vector<int> h(g.NY + 1);
-                HIPCHK(hipMemcpyAsync(h.data(), rc.icount, h.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+                int h[2];
+                HIPCHK(hipMemcpyAsync(h, rc.icount, sizeof(h), hipMemcpyDeviceToHost, s));
                 HIPCHK(hipStreamSynchronize(s));
-                for (int yi = 0; yi < g.NY; yi++) ctx->prof.recheck_items += h[yi];
-                ctx->prof.recheck_pairs += h[g.NY];
+                ctx->prof.recheck_items += h[0];
+                ctx->prof.recheck_pairs += h[1];
             }
         }
     }
@@ -556,10 +637,11 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
         ctx->prof.dp_ms = ms;
         ctx->prof.dp_launches = (int)(ev.size() / 2);
     }
-    for (const DpPlan &p : plans) {
-        if (p.fx) {
+    for (int yi = 0; yi < g.NY; yi++) {
+        const bool fx = yi < ylean ? plans[yi].fx : lean_fx;
+        if (fx) {
             ctx->prof.dp32_classes++;
-            ctx->prof.dp32_bound = std::max(ctx->prof.dp32_bound, p.bound);
+            ctx->prof.dp32_bound = std::max(ctx->prof.dp32_bound, bnd[yi]);
         } else {
             ctx->prof.fp64_classes++;
         }
@@ -768,7 +850,7 @@ struct GroupLayout {
     HostGeometry hg;
     int NYP = 0;
     size_t X, perm, gsize, grank, rowof, yhat, geo, pairs, offs;
-    size_t cbuf, sbuf, K, k, src, lab, A;
+    size_t cbuf, sbuf, K, k, src, Yh, lab, A;
     size_t lab_row = 0;
     int lab16 = 0;
 };
@@ -803,6 +885,7 @@ void layout_group(const BatchGroup &bg, int esize, size_t &hc, size_t &dc, Group
     L.K = take(dc, nv * NY * 4);
     L.k = take(dc, nv * NY * 4);
     L.src = take(dc, nv * NY * 4);
+    L.Yh = take(dc, nv * NY * 4);
     L.lab = take(dc, nv * NY * L.lab_row);
     L.A = take(dc, nv * g.ASUM * 8);
 }
@@ -988,7 +1071,7 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
     const size_t host_bytes = align256(hc);
     for (GroupLayout &L : lay)
         for (size_t *o : {&L.X, &L.perm, &L.gsize, &L.grank, &L.rowof, &L.yhat, &L.cbuf, &L.sbuf,
-                          &L.K, &L.k, &L.src, &L.lab, &L.A})
+                          &L.K, &L.k, &L.src, &L.Yh, &L.lab, &L.A})
             *o += host_bytes;
     const size_t bytes = host_bytes + dc;
     RETCHK(ctx->arena.ensure(bytes));
@@ -1031,13 +1114,14 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
         t.khat = g.khat;
         t.koff = g.koff;
         t.aoff = g.aoff;
-        t.yhat = (const int *)(ar + L.yhat);
+        t.Yh = (const int *)(ar + L.Yh);
         t.cbuf = (const int *)(ar + L.cbuf);
         t.sbuf = (const int *)(ar + L.sbuf);
         t.K = (const int *)(ar + L.K);
         t.src = (const int *)(ar + L.src);
         t.lab = ar + L.lab;
         t.A = (double *)(ar + L.A);
+
         GroupDev &d = gdev[i];
         d.n = bg.n;
         d.NY = NY;
@@ -1066,6 +1150,7 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
         d.K = (int *)(ar + L.K);
         d.k = (int *)(ar + L.k);
         d.src = (int *)(ar + L.src);
+        d.Yh = (int *)(ar + L.Yh);
         d.lab = ar + L.lab;
         d.A = (double *)(ar + L.A);
         d.pairs = (const int32_t *)(ar + L.pairs);

@@ -257,9 +257,8 @@ hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry
     a.n = rt.n; a.NY = g.NY; a.KSUM = g.KSUM; a.ASUM = g.ASUM;
     a.yi = yi; a.x = p.x; a.RS = p.RS; a.KS = p.KS;
     a.nitems = 2 * npairs; a.npairs = npairs; a.SB = p.SB; a.ps = ps;
-    a.yhat = et.yhat;
     a.koff = g.koff; a.aoff = g.aoff;
-    a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.src = ib.src; a.A = ib.A;
+    a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.src = ib.src; a.Yh = ib.Yh; a.A = ib.A;
     a.lab = ib.lab; a.lab_row = ib.lab_row; a.lab16 = ib.lab16;
     a.xlogx = xlogx; a.fxtab = fxtab; a.inv_scale = 1.0 / p.scale;
     a.scratch = scratch; a.slot_bytes = p.slot_bytes;
@@ -300,8 +299,8 @@ hipError_t launch_dp_debug(const RankTables &rt, const EquipTables &et, const Ge
         a.n = rt.n; a.NY = g.NY; a.KSUM = g.KSUM; a.ASUM = g.ASUM;
         a.yi = yi; a.x = p.x; a.RS = p.RS; a.KS = p.KS;
         a.nitems = 2; a.npairs = 1; a.SB = p.SB; a.ps = ps;
-        a.yhat = et.yhat; a.koff = g.koff; a.aoff = g.aoff;
-        a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.src = ib.src; a.A = ib.A;
+        a.koff = g.koff; a.aoff = g.aoff;
+        a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.src = ib.src; a.Yh = ib.Yh; a.A = ib.A;
         a.lab = ib.lab; a.lab_row = ib.lab_row; a.lab16 = ib.lab16;
         a.xlogx = xlogx; a.compat = g.compat;
         a.lds_L = p.lds_L; a.lds_stage = p.lds_stage; a.lds_wave = p.lds_wave;

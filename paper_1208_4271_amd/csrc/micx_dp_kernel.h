@@ -49,8 +49,8 @@ struct DpArgs {
     int yi, x, RS, KS;           // class: row count y = yi+2, x(y), count-record stride, G row stride
     int nitems, npairs, SB;      // items of the class = 2 * npairs
     PairSource ps;
-    const int *yhat, *koff, *aoff;
-    const int *cbuf, *sbuf, *K, *src;
+    const int *koff, *aoff;
+    const int *cbuf, *sbuf, *K, *src, *Yh;   // per item: ends, K, which ends, yhat
     const unsigned char *lab;    // row labels in column order, [item][y-2][p]
     size_t lab_row;
     int lab16;
@@ -166,7 +166,6 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
             const int yi = __builtin_amdgcn_readfirstlane(d[1]);
             const int po = __builtin_amdgcn_readfirstlane(d[2]);
             const DpGroup &gr = a.groups[gi];
-            const int pl = po >> 1, Vv = (po & 1) ? 2 * pl : 2 * pl + 1;
             const size_t it = (size_t)po * gr.NY + yi;
             n = gr.n;
             ycls = yi + 2;
@@ -174,7 +173,7 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
             KS = gr.khat[yi] + 1;
             RS = YR > 0 ? YR + 1 : yi + 3;
             K = __builtin_amdgcn_readfirstlane(gr.K[it]);
-            yh = __builtin_amdgcn_readfirstlane(gr.yhat[(size_t)Vv * gr.NY + yi]);
+            yh = __builtin_amdgcn_readfirstlane(gr.Yh[it]);
             ends = (gr.src[it] ? gr.sbuf : gr.cbuf) + (size_t)po * gr.KSUM + gr.koff[yi];
             lb8 = gr.lab + it * gr.lab_row;
             l16 = gr.lab16 != 0;
@@ -182,10 +181,6 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
         } else {
             const int po = a.ilist ? __builtin_amdgcn_readfirstlane(a.ilist[wi]) : wi;
             const int yi = a.yi, NY = a.NY;
-            const int o = po & 1, pl = po >> 1;
-            int pi, pj;
-            pair_of(a.ps, pl, pi, pj);
-            const int Vv = o ? pi : pj;
             const size_t it = (size_t)po * NY + yi;
             n = a.n;
             ycls = yi + 2;
@@ -193,7 +188,7 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
             KS = a.KS;
             RS = a.RS;
             K = __builtin_amdgcn_readfirstlane(a.K[it]);
-            yh = __builtin_amdgcn_readfirstlane(a.yhat[(size_t)Vv * NY + yi]);
+            yh = __builtin_amdgcn_readfirstlane(a.Yh[it]);
             ends = (a.src[it] ? a.sbuf : a.cbuf) + (size_t)po * a.KSUM + a.koff[yi];
             lb8 = a.lab + it * a.lab_row;
             l16 = a.lab16 != 0;

@@ -64,6 +64,7 @@ struct ItemBuffers {
     int *K = nullptr;      // (super)clumps used by the DP
     int *k = nullptr;      // clumps before merging
     int *src = nullptr;    // 0: DP columns are the clumps (cbuf), 1: the superclumps (sbuf)
+    int *Yh = nullptr;     // rows yhat of the item's row variable (equipartition result)
     // Row labels of every point in column order, per (pair, orientation) and
     // row count: [item][y-2][p], lab_row bytes per row (n rounded up to 64
     // entries), one byte per label, two when some row count exceeds 255.
@@ -84,11 +85,18 @@ struct Recheck {
     double band = 0.0;          // twice the largest entry bound plus the MCN slack; 0: no flags
     unsigned *iflag = nullptr;  // [pair*2+orientation][nyw]: one bit per row count, item queued
     int nyw = 0;                // 32-bit words per (pair, orientation)
-    int *ilist = nullptr;       // [y-2][icap]: queued items (pair*2+orientation) per row count
-    int icap = 0;               // capacity per row count (2 * pairs of the batch)
-    int *icount = nullptr;      // [y-2]: items queued per row count
+    int *ilist = nullptr;       // queued items as descriptors (0, y-2, pair*2+orientation)
+    int *icount = nullptr;      // number of queued items
     int *plist = nullptr;       // flagged pairs (batch-local index)
     int *pcount = nullptr;      // number of flagged pairs
+};
+
+// Pair source for a batch: either an explicit list (pairs != null) or the
+// row-major upper triangle starting at global pair index p0.
+struct PairSource {
+    const int32_t *pairs = nullptr;   // device, 2 ints per pair
+    int64_t p0 = 0;
+    int m = 0;
 };
 
 // One group of a batch stream on the device (pairs sharing n, alpha and c):
@@ -98,7 +106,7 @@ struct DpGroup {
     int n = 0, NY = 0, KSUM = 0, ASUM = 0, lab16 = 0, pad = 0;
     size_t lab_row = 0;
     const int *xcnt = nullptr, *khat = nullptr, *koff = nullptr, *aoff = nullptr;
-    const int *yhat = nullptr;
+    const int *Yh = nullptr;     // yhat per item
     const int *cbuf = nullptr, *sbuf = nullptr, *K = nullptr, *src = nullptr;
     const unsigned char *lab = nullptr;
     double *A = nullptr;
@@ -115,7 +123,7 @@ struct GroupDev {
     uint16_t *rowof = nullptr;
     int *yhat = nullptr;
     const int *xcnt = nullptr, *khat = nullptr, *koff = nullptr, *aoff = nullptr;
-    int *cbuf = nullptr, *sbuf = nullptr, *K = nullptr, *k = nullptr, *src = nullptr;
+    int *cbuf = nullptr, *sbuf = nullptr, *K = nullptr, *k = nullptr, *src = nullptr, *Yh = nullptr;
     unsigned char *lab = nullptr;
     double *A = nullptr;
     const int32_t *pairs = nullptr;  // (2i, 2i+1) per pair
@@ -156,13 +164,6 @@ hipError_t launch_stats_g(const GroupDev *G, const int2 *map, int blocks, hipStr
 hipError_t launch_stats_g_list(const GroupDev *G, const int *plist, const int *pcount, int cap,
                                hipStream_t s, const int *status = nullptr);
 
-// Pair source for a batch: either an explicit list (pairs != null) or the
-// row-major upper triangle starting at global pair index p0.
-struct PairSource {
-    const int32_t *pairs = nullptr;   // device, 2 ints per pair
-    int64_t p0 = 0;
-    int m = 0;
-};
 
 hipError_t launch_pearson(const void *X, int dtype, int m, int n, PairSource ps, int npairs,
                           double *mean, double *inorm, const double *stats, double *out, hipStream_t s);
@@ -184,6 +185,21 @@ void dp_fit_lds(DpPlan &p, int nmax, size_t rec_bytes, int cus);
 hipError_t launch_dp_items(const DpGroup *groups, const int *gitems, int nitems, int nmax,
                            const double *xlogx, const uint32_t *fxtab, void *scratch,
                            const DpPlan &p, int compat, hipStream_t s, const int *icount = nullptr);
+// Item descriptors (0, y-2, pair*2+orientation) of row counts yi_lo ..
+// yi_lo+ncls-1, npo items each, class by class (a kernel).
+hipError_t launch_range_items(int yi_lo, int ncls, int npo, int *items, hipStream_t s);
+// Writes one DpGroup into device memory (a kernel, so that captured graphs
+// hold no host copies).
+hipError_t launch_put_group(const DpGroup &g, DpGroup *dst, hipStream_t s);
+// Fixed-point cost tables of several row-count classes in one launch:
+// tab + cls[i] * stride gets round(scale[i] * j ln j), j = 0..n.
+constexpr int kFxBatch = 64;
+struct FxScales {
+    double scale[kFxBatch];
+    int cls[kFxBatch];
+};
+hipError_t launch_fxtables(int n, const FxScales &sc, int count, const double *xlogx, uint32_t *tab,
+                           size_t stride, hipStream_t s);
 hipError_t launch_fxtable(int n, const DpPlan &p, const double *xlogx, uint32_t *tab,
                           hipStream_t s);
 // Debug instances of the DP kernel: the count tables of the two items of

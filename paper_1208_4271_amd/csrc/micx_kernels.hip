@@ -231,7 +231,8 @@ struct PartArgs {
     const int *perm, *gsize, *grank;
     const uint16_t *rowof;       // [v][p][NYP]
     const int *khat, *koff;
-    int *cbuf, *sbuf, *K, *k, *src;
+    const int *yhat;             // [v][y-2]: rows of each variable's equipartitions
+    int *cbuf, *sbuf, *K, *k, *src, *Yh;
     unsigned char *lab;          // row labels in column order, [item][y-2][p]
     size_t lab_row;
     int compat;                  // MICX_COMPAT_* flags
@@ -356,6 +357,7 @@ __device__ __forceinline__ void part_body(const PartArgs &a, int w, unsigned cha
     if (act) {
         const size_t it = (size_t)po * a.NY + yi;
         a.k[it] = k;
+        a.Yh[it] = a.yhat[(size_t)V * a.NY + yi];
         if (k <= kh) {
             a.K[it] = k;
             a.src[it] = 0;
@@ -487,8 +489,10 @@ __device__ __forceinline__ void queue_item(const Recheck &rc, int po, int yi) {
     const unsigned bit = 1u << (yi & 31);
     const unsigned old = atomicOr(rc.iflag + (size_t)po * rc.nyw + (yi >> 5), bit);
     if (!(old & bit)) {
-        const int slot = atomicAdd(rc.icount + yi, 1);
-        rc.ilist[(size_t)yi * rc.icap + slot] = po;
+        int *d = rc.ilist + 3 * (size_t)atomicAdd(rc.icount, 1);
+        d[0] = 0;
+        d[1] = yi;
+        d[2] = po;
     }
 }
 
@@ -688,8 +692,8 @@ hipError_t launch_part(const RankTables &rt, const EquipTables &et, const Geomet
     PartArgs a;
     a.n = rt.n; a.NY = g.NY; a.KSUM = g.KSUM; a.ps = ps;
     a.perm = rt.perm; a.gsize = rt.gsize; a.grank = rt.grank; a.rowof = et.rowof; a.NYP = et.NYP;
-    a.khat = g.khat; a.koff = g.koff;
-    a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.k = ib.k; a.src = ib.src;
+    a.khat = g.khat; a.koff = g.koff; a.yhat = et.yhat;
+    a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.k = ib.k; a.src = ib.src; a.Yh = ib.Yh;
     a.lab = ib.lab; a.lab_row = ib.lab_row; a.compat = et.compat;
     const int nyb = (g.NY + 63) / 64;
     if (ib.lab16) hipLaunchKernelGGL(k_part<true>, dim3((unsigned)(2 * npairs * nyb)), dim3(64), 0, s, a);
@@ -707,6 +711,48 @@ hipError_t launch_stats(const Geometry &g, int npairs, const ItemBuffers &ib, do
     a.plist = plist; a.pcount = pcount; a.status = status;
     a.srq = nullptr; a.grp = nullptr; a.gi = 0;
     hipLaunchKernelGGL(k_stats, dim3((npairs + 127) / 128), dim3(128), 0, s, a);
+    return hipGetLastError();
+}
+
+__global__ void k_put_group(DpGroup g, DpGroup *dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = g;
+}
+
+__global__ void k_range_items(int yi_lo, int npo, int64_t total, int *items) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = i / npo;
+        items[3 * i] = 0;
+        items[3 * i + 1] = yi_lo + (int)c;
+        items[3 * i + 2] = (int)(i - c * npo);
+    }
+}
+
+hipError_t launch_range_items(int yi_lo, int ncls, int npo, int *items, hipStream_t s) {
+    const int64_t total = (int64_t)ncls * npo;
+    if (total <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_range_items, dim3((unsigned)blocks), dim3(256), 0, s, yi_lo, npo, total, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_put_group(const DpGroup &g, DpGroup *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_put_group, dim3(1), dim3(64), 0, s, g, dst);
+    return hipGetLastError();
+}
+
+// T[j] = round(S * j ln j) mod 2^32 for several row-count classes at once
+// (blockIdx.y = class).
+__global__ void k_fxtables(int n, FxScales sc, const double *xlogx, uint32_t *tab, size_t stride) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (j <= n) tab[(size_t)sc.cls[c] * stride + j] = (uint32_t)(unsigned long long)__double2ll_rn(sc.scale[c] * xlogx[j]);
+}
+
+hipError_t launch_fxtables(int n, const FxScales &sc, int count, const double *xlogx, uint32_t *tab,
+                           size_t stride, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fxtables, dim3((n + 256) / 256, count), dim3(256), 0, s, n, sc, xlogx, tab, stride);
     return hipGetLastError();
 }
 
@@ -806,8 +852,8 @@ __global__ __launch_bounds__(64) void k_part_g(const GroupDev *G, const int2 *ma
     a.n = g.n; a.NY = g.NY; a.NYP = g.NYP; a.KSUM = g.KSUM;
     a.ps.pairs = g.pairs; a.ps.p0 = 0; a.ps.m = g.nv;
     a.perm = g.perm; a.gsize = g.gsize; a.grank = g.grank; a.rowof = g.rowof;
-    a.khat = g.khat; a.koff = g.koff;
-    a.cbuf = g.cbuf; a.sbuf = g.sbuf; a.K = g.K; a.k = g.k; a.src = g.src;
+    a.khat = g.khat; a.koff = g.koff; a.yhat = g.yhat;
+    a.cbuf = g.cbuf; a.sbuf = g.sbuf; a.K = g.K; a.k = g.k; a.src = g.src; a.Yh = g.Yh;
     a.lab = g.lab; a.lab_row = g.lab_row; a.compat = g.compat;
     if (g.lab16) part_dispatch<true>(a, m.y, tile);
     else part_dispatch<false>(a, m.y, tile);

@@ -111,16 +111,34 @@ extern "C" int micx_score_noalloc(micx_ctx *ctx, const void *x_dev, const void *
     if (!dp_fits(g, n)) return MICX_ETOOBIG;
 
     // launch plans of every row count (and the FP64 plans of the recheck)
-    DpPlan plans[kMaxRows], plans64[kMaxRows];
+    DpPlan plans[kMaxRows];
     int nfx = 0;
     double bound = 0.0;
     size_t gbytes = 0;
-    auto grid_bytes = [](const DpPlan &p) {
-        const size_t waves = (size_t)std::min(p.max_waves, 2);
+    auto grid_bytes = [NY](const DpPlan &p) {
+        const size_t waves = (size_t)std::min(p.max_waves, p.groups ? 2 * NY : 2);
         return (waves + p.WPB - 1) / p.WPB * p.WPB * p.slot_bytes;
     };
+    for (int yi = 0; yi < NY; yi++) plans[yi] = dp_plan(g, n, yi, cus, mode, tol);
+    // the row counts with x = 2 share the fixed-point scale of the largest y,
+    // as in the other entry points (so that both give the same entries)
+    int ylean = NY;
+    while (ylean > 0 && B / (ylean + 1) == 2) ylean--;
+    if (ylean < NY) {
+        const double S = plans[NY - 1].scale;
+        bool fx = plans[NY - 1].fx;
+        for (int yi = ylean; yi < NY; yi++)
+            if (0.5 * (double)(yi + 3) * 2.0 / (S * (double)n * log(2.0)) > tol) fx = false;
+        for (int yi = ylean; yi < NY; yi++) {
+            if (fx) {
+                plans[yi].scale = S;
+                plans[yi].bound = 0.5 * (double)(yi + 3) * 2.0 / (S * (double)n * log(2.0));
+            } else if (plans[yi].fx) {
+                plans[yi] = dp_plan(g, n, yi, cus, MICX_MODE_FP64, 0.0);
+            }
+        }
+    }
     for (int yi = 0; yi < NY; yi++) {
-        plans[yi] = dp_plan(g, n, yi, cus, mode, tol);
         gbytes = std::max(gbytes, grid_bytes(plans[yi]));
         if (plans[yi].fx) {
             nfx++;
@@ -128,11 +146,24 @@ extern "C" int micx_score_noalloc(micx_ctx *ctx, const void *x_dev, const void *
         }
     }
     const bool recheck = nfx > 0;
-    if (recheck)
+    DpPlan gen;   // the FP64 recheck: a descriptor kernel that takes any row count
+    if (recheck) {
+        gen = dp_shape(g, n, 0, MICX_MODE_FP64, 0.0);
+        gen.NL = 8;
+        gen.YR = 0;
+        gen.T = 1;
+        gen.groups = true;
+        size_t rec = 0, slot = 0;
         for (int yi = 0; yi < NY; yi++) {
-            plans64[yi] = dp_plan(g, n, yi, cus, MICX_MODE_FP64, 0.0);
-            gbytes = std::max(gbytes, grid_bytes(plans64[yi]));
+            const size_t kh1 = (size_t)khat[yi] + 1;
+            rec = std::max(rec, kh1 * (size_t)(yi + 3) * 4);
+            slot = std::max(slot, (size_t)(B / (yi + 2)) * kh1 * 8);
         }
+        gen.slot_bytes = slot;
+        dp_fit_lds(gen, n, rec, cus);
+        gen.max_waves = gen.WPB;   // one workgroup: the queued items of one pair are few
+        gbytes = std::max(gbytes, grid_bytes(gen));
+    }
 
     // layout of the array
     const int esize = dtype == MICX_F64 ? 8 : 4;
@@ -140,7 +171,7 @@ extern "C" int micx_score_noalloc(micx_ctx *ctx, const void *x_dev, const void *
     const int lab16 = NY + 1 <= 256 ? 0 : 1;
     const size_t lab_row = (size_t)((n + 63) / 64 * 64) * (lab16 ? 2 : 1);
     const int nyw = (NY + 31) / 32;
-    const size_t words = 1 + (size_t)NY + 1 + 2 * (size_t)nyw;   // status, recheck counters and flags
+    const size_t words = 1 + 2 + 2 * (size_t)nyw;   // status, recheck counters and flags
     size_t cur = 0;
     auto take = [&](size_t bytes) {
         const size_t at = cur;
@@ -161,11 +192,13 @@ extern "C" int micx_score_noalloc(micx_ctx *ctx, const void *x_dev, const void *
     const size_t o_K = take(2 * (size_t)NY * 4);
     const size_t o_k = take(2 * (size_t)NY * 4);
     const size_t o_src = take(2 * (size_t)NY * 4);
+    const size_t o_Yh = take(2 * (size_t)NY * 4);
     const size_t o_A = take(2 * (size_t)ASUM * 8);
     const size_t o_lab = take(2 * (size_t)NY * lab_row);
     const size_t o_fx = take(nfx ? (size_t)NY * ((size_t)n + 1) * 4 : 0);
-    const size_t o_ilist = take((size_t)NY * 2 * 4);
+    const size_t o_ilist = take((size_t)NY * 2 * 3 * 4);
     const size_t o_plist = take(4);
+    const size_t o_grp = take(sizeof(DpGroup));
     const size_t o_G = take(gbytes);
     if (cur > MICX_NOALLOC_BYTES) return MICX_ETOOBIG;
 
@@ -196,6 +229,7 @@ extern "C" int micx_score_noalloc(micx_ctx *ctx, const void *x_dev, const void *
     ib.K = (int *)(base + o_K);
     ib.k = (int *)(base + o_k);
     ib.src = (int *)(base + o_src);
+    ib.Yh = (int *)(base + o_Yh);
     ib.A = (double *)(base + o_A);
     ib.lab = base + o_lab;
     ib.lab_row = lab_row;
@@ -206,13 +240,13 @@ extern "C" int micx_score_noalloc(micx_ctx *ctx, const void *x_dev, const void *
     if (recheck) {
         rc.band = 2.0 * bound + 1e-12;
         rc.icount = status + 1;
-        rc.pcount = rc.icount + NY;
+        rc.pcount = rc.icount + 1;
         rc.iflag = (unsigned *)(rc.pcount + 1);
         rc.nyw = nyw;
-        rc.icap = 2;
         rc.ilist = (int *)(base + o_ilist);
         rc.plist = (int *)(base + o_plist);
     }
+    DpGroup *grp = (DpGroup *)(base + o_grp);
     PairSource ps;   // the one pair (0, 1) of the two gathered variables
     ps.pairs = nullptr;
     ps.p0 = 0;
@@ -244,9 +278,26 @@ extern "C" int micx_score_noalloc(micx_ctx *ctx, const void *x_dev, const void *
     NACHK(launch_stats(g, 1, ib, stats_dev, M, Axy, Ayx, s, recheck ? &rc : nullptr, nullptr, nullptr,
                        status));
     if (recheck) {
-        for (int yi = 0; yi < NY; yi++)
-            NACHK(launch_dp(rt, et, g, ps, 1, ib, xlogx, nullptr, base + o_G, yi, plans64[yi], s,
-                            rc.ilist + (size_t)yi * rc.icap, rc.icount + yi, 2));
+        DpGroup dg;
+        dg.n = n;
+        dg.NY = NY;
+        dg.KSUM = KSUM;
+        dg.ASUM = ASUM;
+        dg.lab16 = lab16;
+        dg.lab_row = lab_row;
+        dg.xcnt = g.xcnt;
+        dg.khat = g.khat;
+        dg.koff = g.koff;
+        dg.aoff = g.aoff;
+        dg.Yh = ib.Yh;
+        dg.cbuf = ib.cbuf;
+        dg.sbuf = ib.sbuf;
+        dg.K = ib.K;
+        dg.src = ib.src;
+        dg.lab = ib.lab;
+        dg.A = ib.A;
+        NACHK(launch_put_group(dg, grp, s));
+        NACHK(launch_dp_items(grp, rc.ilist, 2 * NY, n, xlogx, nullptr, base + o_G, gen, compat, s, rc.icount));
         NACHK(launch_stats(g, 1, ib, stats_dev, M, Axy, Ayx, s, nullptr, rc.plist, rc.pcount, status));
     }
     if (status_dev) {
