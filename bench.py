@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the grid-bound scaling sweep (uniform random data, "
                          "alpha in {0.5, 0.6, 0.7}, growing n)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (default launch-shape rules)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every all-pairs call's kernels one by one (no captured graph)")
     ap.add_argument("--no-counts", action="store_true",
@@ -387,6 +389,17 @@ def main():
     print("bench: m=%d n=%d pairs=%d warmup=%d steps=%d" %
           (m, n, npairs, args.warmup, args.steps), file=sys.stderr, flush=True)
 
+    # the autotuner picks the DP launch shapes of every row count by timing
+    # them on all pairs of 192 of the variables (both forms)
+    tune = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        micx.autotune(Xd, alpha, c, micx.MODE_DP32)
+        micx.autotune(Xd, alpha, c, micx.MODE_FP64)
+        tune = {"seconds": round(time.perf_counter() - t0, 2),
+                "sample": "all pairs of the first 192 variables, every distinct launch shape per row count"}
+        print("bench: autotune done (%.1f s)" % tune["seconds"], file=sys.stderr, flush=True)
+
     forms = {}
     order = ["dp32", "fp64"] if args.mode == "dp32" else ["fp64", "dp32"]
     if args.only:
@@ -427,6 +440,7 @@ def main():
                    "form": main_form, "parallelism": "single GPU"},
         "roofline": roof,
         "forms": forms,
+        "autotune": tune,
     }
 
     stream = None

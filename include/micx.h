@@ -314,6 +314,27 @@ int micx_set_dp32_tolerance(micx_ctx *ctx, double tol);
  * Returns MICX_EINVAL for unknown bits. */
 int micx_set_compat(micx_ctx *ctx, int flags);
 
+/* Autotuner of the DP launch shapes (the OptimizeXAxis speed-ups the paper
+ * tunes for its engine, App. A item 10, picked by measurement on this
+ * device).  For every row count of the (n, alpha, c, mode) problem, it times
+ * each distinct launch shape -- targets per lane (1-3), cap on the layers
+ * per pass (12-36), workgroups per CU the LDS split aims for (1, 2, 4) -- on
+ * all pairs of the first min(m, 192) rows of X_dev, checks that every shape
+ * gives bit-identical entries (else MICX_EDEVICE and no choice is kept),
+ * and keeps the fastest in a process-wide table that later calls on any
+ * context use for classes with the same key (numeric form, n rounded up to a
+ * power of two, y, x, khat rounded up to a power of two).
+ * cache_path: file the whole table is written to (micx_tune_save), or NULL.
+ * Synchronous; takes seconds. */
+int micx_autotune(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n, const micx_param *param,
+                  int mode, const char *cache_path, void *stream);
+/* Write the tuned table to a text file / merge a file written by
+ * micx_tune_save into it (MICX_EINVAL if unreadable or for another device
+ * architecture) / empty it (later calls use the default rules). */
+int micx_tune_save(const char *path);
+int micx_tune_load(const char *path);
+int micx_tune_clear(void);
+
 /* Size of the device array behind micx_score_noalloc (per device, held
  * until the process ends). */
 #define MICX_NOALLOC_BYTES (32u << 20)

@@ -45,6 +45,7 @@ EXPORTS = (
     "micx_allpairs", "micx_pairs", "micx_batch", "micx_debug_item", "micx_strerror",
     "micx_set_profiling", "micx_get_profile", "micx_set_dp32_tolerance", "micx_set_compat",
     "micx_pearson", "micx_score_noalloc", "micx_status", "micx_set_graphs", "micx_debug_tables",
+    "micx_autotune", "micx_tune_save", "micx_tune_load", "micx_tune_clear",
 )
 
 # Size of the device array behind micx_score_noalloc (include/micx.h).
@@ -124,6 +125,14 @@ def load_library():
     lib.micx_allpairs.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(_Param),
                                   ctypes.c_int, vp, vp]
     lib.micx_allpairs.restype = ctypes.c_int
+    lib.micx_autotune.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(_Param),
+                                  ctypes.c_int, ctypes.c_char_p, vp]
+    lib.micx_autotune.restype = ctypes.c_int
+    for f in ("micx_tune_save", "micx_tune_load"):
+        getattr(lib, f).argtypes = [ctypes.c_char_p]
+        getattr(lib, f).restype = ctypes.c_int
+    lib.micx_tune_clear.argtypes = []
+    lib.micx_tune_clear.restype = ctypes.c_int
     lib.micx_status.argtypes = [vp]
     lib.micx_status.restype = ctypes.c_int
     lib.micx_set_graphs.argtypes = [vp, ctypes.c_int]
@@ -186,6 +195,37 @@ def status(device: int = 0) -> int:
     """micx_status: waits for the last pair call's work and returns its
     device-side result code."""
     return load_library().micx_status(context(device))
+
+
+def autotune(X, alpha: float = 0.6, c: float = 15.0, mode: int = MODE_DP32, cache_path=None,
+             stream=None):
+    """micx_autotune: time the DP launch shapes of every row count on all pairs
+    of the first min(m, 192) rows of the CUDA tensor X and keep the fastest
+    (process-wide).  cache_path: file for the table, or None."""
+    if not X.is_cuda or X.dim() != 2:
+        raise ValueError("X must be a 2-D CUDA tensor")
+    X = X.contiguous()
+    dt = _DTYPES.get(str(X.dtype))
+    if dt is None:
+        raise ValueError("X dtype must be float32, float64 or int32")
+    m, n = X.shape
+    par = _param(alpha, c)
+    rc = load_library().micx_autotune(context(X.device.index or 0), ctypes.c_void_p(X.data_ptr()), dt, m, n,
+                                      ctypes.byref(par), int(mode),
+                                      cache_path.encode() if cache_path else None, _stream_ptr(stream))
+    _check(rc, "micx_autotune")
+
+
+def tune_save(path):
+    _check(load_library().micx_tune_save(path.encode()), "micx_tune_save")
+
+
+def tune_load(path):
+    _check(load_library().micx_tune_load(path.encode()), "micx_tune_load")
+
+
+def tune_clear():
+    _check(load_library().micx_tune_clear(), "micx_tune_clear")
 
 
 def set_graphs(enable: bool = True, device: int = 0):

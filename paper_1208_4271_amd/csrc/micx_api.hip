@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -956,7 +957,9 @@ void make_buckets(micx_ctx *ctx, const std::vector<BatchGroup> &groups, size_t g
             // (FP64) or three (32-bit) targets per lane without spilling, which
             // shortens the stream's largest items (measured: FP64 3.40 -> 2.95 s,
             // DP32 2.29 -> 2.13 s on the 8,192-pair stream)
-            DpPlan p = dp_shape(g, bg.n, yi, mode, ctx->dp32_tol, 24);
+            // (the default rules: tuned choices are made for the all-pairs kernels)
+            const DpTune rule;
+            DpPlan p = dp_shape(g, bg.n, yi, mode, ctx->dp32_tol, 24, &rule);
             // a shared table uses the smallest scale of its bucket, at most a
             // factor 2 below the class's own: keep the bound within tolerance
             if (p.fx && 2.0 * p.bound > ctx->dp32_tol) {
@@ -1720,5 +1723,173 @@ extern "C" int micx_debug_tables(micx_ctx *ctx, const micx_problem *problem, con
             if (t0[(size_t)t * (ry + 1) + r] != t1[(size_t)t * (ry + 1) + r]) return MICX_EDEVICE;
     for (int t = 0; t <= KK; t++)
         for (int r = 0; r < yh; r++) counts[(size_t)t * yh + r] = t0[(size_t)t * (ry + 1) + 1 + r];
+    return MICX_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+
+namespace {
+
+struct TuneCand {
+    DpTune tv;
+    DpPlan p;
+};
+
+}  // namespace
+
+extern "C" int micx_autotune(micx_ctx *ctx, const void *X_dev, int dtype, int m, int n,
+                             const micx_param *param, int mode, const char *cache_path, void *stream) {
+    if (!param) return MICX_EINVAL;
+    const double alpha = param->alpha, c = param->c;
+    RETCHK(check_common(ctx, n, alpha, c, mode));
+    if (!X_dev || m < 2) return MICX_EINVAL;
+    if (dtype != MICX_F32 && dtype != MICX_F64 && dtype != MICX_I32) return MICX_EINVAL;
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    HostGeometry hg;
+    make_geometry(n, micx_grid_bound(n, alpha), c, hg, ctx->compat);
+    const Geometry &g = hg.g;
+    if (!dp_fits(g, n)) return MICX_ETOOBIG;
+    // the sample: all pairs of the first (up to) 192 variables, enough items
+    // per row count to fill the device several times over
+    const int ms = std::min(m, 192);
+    const int npairs = ms * (ms - 1) / 2;
+    RETCHK(begin_status(ctx, s));
+    RETCHK(upload_geometry(ctx, hg, s, c));
+    RankTables rt;
+    EquipTables et;
+    RETCHK(prepare_variables(ctx, X_dev, dtype, ms, n, g, false, rt, et, s));
+    ItemBuffers ib;
+    RETCHK(ensure_items(ctx, g, npairs, ib));
+    PairSource ps;
+    ps.pairs = nullptr;
+    ps.p0 = 0;
+    ps.m = ms;
+    HIPCHK(launch_part(rt, et, g, ps, npairs, ib, s));
+    RETCHK(end_status(ctx, s));
+    HIPCHK(hipStreamSynchronize(s));
+    RETCHK(status_code(*ctx->hstatus));
+    int ylean = g.NY;
+    while (ylean > 0 && g.B / (ylean + 1) == 2) ylean--;
+    const size_t tabn = (size_t)n + 1;
+    RETCHK(ctx->fxtab.ensure((size_t)g.NY * tabn * sizeof(uint32_t)));
+    RETCHK(ctx->counters.ensure(4 * sizeof(unsigned long long)));
+    unsigned long long *sum = ctx->counters.as<unsigned long long>();
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const DpTune rule;   // all zero: the default rules
+    int rc = MICX_OK;
+    for (int yi = 0; yi < ylean && rc == MICX_OK; yi++) {
+        const DpPlan p0 = dp_shape(g, n, yi, mode, ctx->dp32_tol, 36, &rule);
+        const uint32_t *tab = nullptr;
+        if (p0.fx) {
+            FxScales sc;
+            sc.scale[0] = p0.scale;
+            sc.cls[0] = yi;
+            HIPCHK(launch_fxtables(n, sc, 1, ctx->xlogx.as<double>(), ctx->fxtab.as<uint32_t>(), tabn, s));
+            tab = ctx->fxtab.as<uint32_t>() + yi * tabn;
+        }
+        // candidate shapes: targets per lane, layer cap, workgroups per CU;
+        // distinct launches only (the planner steps down to built shapes)
+        std::vector<TuneCand> cands;
+        for (int T : {0, 1, 2, 3})
+            for (int cap : {0, 36, 24, 16, 12})
+                for (int wgs : {0, 1, 2, 4}) {
+                    TuneCand tc;
+                    tc.tv.T = T;
+                    tc.tv.nlcap = cap;
+                    tc.tv.wgs = wgs;
+                    tc.p = dp_shape(g, n, yi, mode, ctx->dp32_tol, 36, &tc.tv);
+                    dp_fit_lds(tc.p, n, (size_t)tc.p.KS * tc.p.RS * 4, ctx->cus);
+                    if (tc.p.lds > 160 * 1024) continue;
+                    bool dup = false;
+                    for (const TuneCand &o : cands)
+                        dup |= o.p.NL == tc.p.NL && o.p.YR == tc.p.YR && o.p.T == tc.p.T && o.p.SB == tc.p.SB &&
+                               o.p.WPB == tc.p.WPB;
+                    if (!dup) cands.push_back(tc);
+                }
+        double best_ms = 1e300;
+        DpTune best;
+        unsigned long long ref = 0;
+        for (size_t k = 0; k < cands.size(); k++) {
+            const DpPlan &p = cands[k].p;
+            const size_t waves = (size_t)std::min<int64_t>(p.max_waves, 2 * (int64_t)npairs);
+            RETCHK(ctx->scratch.ensure(((waves + p.WPB - 1) / p.WPB) * p.WPB * p.slot_bytes));
+            HIPCHK(launch_dp(rt, et, g, ps, npairs, ib, ctx->xlogx.as<double>(), tab, ctx->scratch.p, yi, p, s));
+            HIPCHK(hipEventRecord(e0, s));
+            for (int r = 0; r < 2; r++)
+                HIPCHK(launch_dp(rt, et, g, ps, npairs, ib, ctx->xlogx.as<double>(), tab, ctx->scratch.p, yi, p,
+                                 s));
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(launch_zero(sum, 2, s));
+            HIPCHK(launch_checksum(ib.A, 2 * npairs, g.ASUM, hg.aoff[yi], hg.xcnt[yi] - 1, sum, s));
+            unsigned long long h = 0;
+            HIPCHK(hipMemcpyAsync(&h, sum, sizeof(h), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            float ms_t = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms_t, e0, e1));
+            if (k == 0) ref = h;
+            else if (h != ref) {
+                rc = MICX_EDEVICE;   // a launch shape changed the results: keep the rules
+                break;
+            }
+            if (ms_t < best_ms) {
+                best_ms = ms_t;
+                best.T = p.T;
+                best.nlcap = p.NL;
+                best.wgs = cands[k].tv.wgs > 0 ? cands[k].tv.wgs : ((p.T == 1 && p.NL >= 14) ? 4 : 2);
+            }
+        }
+        if (rc == MICX_OK)
+            tune_set(tune_key(p0.fx, n, yi + 2, hg.xcnt[yi], hg.khat[yi]), best);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    RETCHK(rc);
+    // captured graphs hold the old launch shapes
+    drop_graph(ctx);
+    ctx->gseen = false;
+    if (cache_path) return micx_tune_save(cache_path);
+    return MICX_OK;
+}
+
+extern "C" int micx_tune_save(const char *path) {
+    if (!path) return MICX_EINVAL;
+    FILE *f = fopen(path, "w");
+    if (!f) return MICX_EINVAL;
+    fprintf(f, "micx-tune 1 gfx950\n");
+    const int cnt = tune_count();
+    for (int i = 0; i < cnt; i++) {
+        DpTuneKey k;
+        DpTune v;
+        tune_entry(i, k, v);
+        fprintf(f, "%d %d %d %d %d %d %d %d\n", k.fx, k.nb, k.y, k.x, k.khb, v.T, v.nlcap, v.wgs);
+    }
+    fclose(f);
+    return MICX_OK;
+}
+
+extern "C" int micx_tune_load(const char *path) {
+    if (!path) return MICX_EINVAL;
+    FILE *f = fopen(path, "r");
+    if (!f) return MICX_EINVAL;
+    char tag[32], arch[32];
+    int ver = 0;
+    if (fscanf(f, "%31s %d %31s", tag, &ver, arch) != 3 || strcmp(tag, "micx-tune") != 0 || ver != 1 ||
+        strcmp(arch, "gfx950") != 0) {
+        fclose(f);
+        return MICX_EINVAL;
+    }
+    DpTuneKey k;
+    DpTune v;
+    while (fscanf(f, "%d %d %d %d %d %d %d %d", &k.fx, &k.nb, &k.y, &k.x, &k.khb, &v.T, &v.nlcap, &v.wgs) == 8)
+        tune_set(k, v);
+    fclose(f);
+    return MICX_OK;
+}
+
+extern "C" int micx_tune_clear(void) {
+    tune_clear();
     return MICX_OK;
 }

@@ -43,11 +43,6 @@ dp_kernel_t pick(bool fx, int NL, int YR, int T, bool gr = false) {
 
 bool have_shape(int NL, int YR) { return pick(false, NL, YR, 1) != nullptr; }
 
-int env_int(const char *name, int dflt) {
-    const char *v = getenv(name);
-    return v && *v ? atoi(v) : dflt;
-}
-
 int round_up_in(int v, const int *set, int count, int otherwise) {
     for (int i = 0; i < count; i++)
         if (set[i] >= v) return set[i];
@@ -73,7 +68,77 @@ __global__ void k_fxtable(int n, double scale, const double *xlogx, uint32_t *ta
 // a partition into at most l <= x columns by l(yhat+1)/2, so an entry M of
 // the class is off by at most (y+1) x / (2 S n ln 2).  Classes whose bound
 // exceeds the tolerance run in FP64.
-DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol, int nl_max) {
+namespace {
+
+constexpr int kTuneSlots = 4096;
+struct TuneEntry {
+    DpTuneKey k;
+    DpTune v;
+    bool used;
+};
+TuneEntry g_tune[kTuneSlots];
+int g_tune_n = 0;
+std::mutex g_tune_mu;
+
+bool same_key(const DpTuneKey &a, const DpTuneKey &b) {
+    return a.fx == b.fx && a.nb == b.nb && a.y == b.y && a.x == b.x && a.khb == b.khb;
+}
+
+int ceil_log2(int v) {
+    int b = 0;
+    while ((1 << b) < v) b++;
+    return b;
+}
+
+}  // namespace
+
+DpTuneKey tune_key(bool fx, int n, int y, int x, int khat) {
+    DpTuneKey k;
+    k.fx = fx ? 1 : 0;
+    k.nb = ceil_log2(n);
+    k.y = y;
+    k.x = x;
+    k.khb = ceil_log2(khat + 1);
+    return k;
+}
+
+void tune_set(const DpTuneKey &k, const DpTune &v) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (int i = 0; i < g_tune_n; i++)
+        if (same_key(g_tune[i].k, k)) {
+            g_tune[i].v = v;
+            return;
+        }
+    if (g_tune_n < kTuneSlots) g_tune[g_tune_n++] = TuneEntry{k, v, true};
+}
+
+bool tune_get(const DpTuneKey &k, DpTune &v) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (int i = 0; i < g_tune_n; i++)
+        if (same_key(g_tune[i].k, k)) {
+            v = g_tune[i].v;
+            return true;
+        }
+    return false;
+}
+
+void tune_clear() {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_n = 0;
+}
+
+int tune_count() {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    return g_tune_n;
+}
+
+void tune_entry(int i, DpTuneKey &k, DpTune &v) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    k = g_tune[i].k;
+    v = g_tune[i].v;
+}
+
+DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol, int nl_max, const DpTune *force) {
     static const int NLS[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32, 36};
     static const int YRS[] = {2, 3, 4, 5, 6, 7, 8, 10, 12, 16, 20, 24, 32, 40};
     DpPlan p;
@@ -85,9 +150,10 @@ DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol, int nl_m
     const int vb = p.fx ? 4 : 8;                       // bytes per DP value
     const int PK = 16 / vb;
     const int nf = std::max(x - 2, 1);                 // full layers (at least one shape)
-    // tuning overrides: MICX_DP_NLCAP caps the layers per pass, MICX_DP_T
-    // forces the targets per lane (1 or 2)
-    const int nlcap = env_int("MICX_DP_NLCAP", nl_max);
+    // a tuned choice (micx_autotune) for this class, else the default rules
+    DpTune tv;
+    const bool tuned = force ? (tv = *force, true) : tune_get(tune_key(p.fx, n, y, x, kh), tv);
+    const int nlcap = tuned && tv.nlcap > 0 ? std::min(tv.nlcap, nl_max) : nl_max;
     p.NL = round_up_in(std::min(nf, nlcap), NLS, 17, 36);
     p.YR = round_up_in(y, YRS, 14, 0);
     if (!have_shape(p.NL, p.YR)) p.YR = 0;
@@ -95,9 +161,9 @@ DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol, int nl_m
     // three in the 32-bit form with few rows, else two; one for smaller passes
     p.T = (p.NL >= 20 && p.YR > 0 && p.YR <= 12) ? 2 : 1;
     if (p.fx && p.NL >= 20 && p.YR > 0 && p.YR <= 5) p.T = 3;
-    const int tforce = env_int("MICX_DP_T", 0);
-    if (tforce == 1 || (tforce == 2 && p.NL >= 5 && p.YR > 0 && p.YR <= 12)) p.T = tforce;
-    if (tforce == 3 && p.fx && p.YR > 0 && pick(true, p.NL, p.YR, 3)) p.T = 3;
+    if (tuned && tv.T > 0) p.T = (tv.T == 1 || p.YR > 0) ? tv.T : 1;
+    if (p.T == 3 && !p.fx) p.T = 2;                    // three targets per lane exist in 32 bits only
+    p.wgs = tuned ? tv.wgs : 0;
     if (x == 2) {                                      // no full layer: the lean shape
         p.NL = 0;
         p.YR = 0;
@@ -217,10 +283,10 @@ void dp_fit_lds(DpPlan &p, int nmax, size_t rec_bytes, int cus) {
     const int lds_rec = align16(rec_bytes);
     const int budget = 160 * 1024;
     p.WPB = 4;
-    // workgroups per CU the staging split aims for: four for one-target
-    // passes of 14 layers or more (their registers allow four waves per SIMD;
-    // measured 7% faster than two), else two (tuning override MICX_DP_WGS)
-    const int wgs = std::max(1, env_int("MICX_DP_WGS", (p.T == 1 && p.NL >= 14) ? 4 : 2));
+    // workgroups per CU the staging split aims for: the tuned choice, else
+    // four for one-target passes of 14 layers or more (their registers allow
+    // four waves per SIMD; measured 7% faster than two), else two
+    const int wgs = p.wgs > 0 ? p.wgs : ((p.T == 1 && p.NL >= 14) ? 4 : 2);
     for (p.SB = 64;; p.SB >>= 1) {
         const int lds_stage = align16(std::max((size_t)p.SB * NLP * vb, (size_t)nmax));
         const int wave = align16((size_t)lds_stage + lds_rec);

@@ -43,6 +43,26 @@ struct Geometry {
     int compat = 0;                                // MICX_COMPAT_* flags
 };
 
+// A launch-shape choice for one DP class, made by the autotuner
+// (micx_autotune): targets per lane, cap on the layers per pass, workgroups
+// per CU that the LDS split aims for.  0 leaves a field to the default rule.
+struct DpTune {
+    int T = 0, nlcap = 0, wgs = 0;
+};
+// Classes are keyed by their numeric form, n rounded up to a power of two,
+// y, x and khat rounded up to a power of two.
+struct DpTuneKey {
+    int fx = 0, nb = 0, y = 0, x = 0, khb = 0;
+};
+DpTuneKey tune_key(bool fx, int n, int y, int x, int khat);
+// Process-wide table of tuned choices (fixed size, no heap).
+void tune_set(const DpTuneKey &k, const DpTune &v);
+bool tune_get(const DpTuneKey &k, DpTune &v);
+void tune_clear();
+// The i-th entry (i < tune_count()), for saving.
+int tune_count();
+void tune_entry(int i, DpTuneKey &k, DpTune &v);
+
 // Launch shape of the DP for one row count y.
 struct DpPlan {
     bool fx = false;              // 32-bit fixed-point DP (else FP64)
@@ -55,6 +75,7 @@ struct DpPlan {
     int blocks_per_cu = 0, max_waves = 0;
     size_t slot_bytes = 0;        // G table bytes per wavefront
     bool groups = false;          // launched over batch-stream item descriptors
+    int wgs = 0;                  // workgroups per CU the LDS split aims for (0: default rule)
 };
 
 // Per-batch item buffers.
@@ -173,8 +194,10 @@ hipError_t launch_equip(const RankTables &rt, EquipTables &et, hipStream_t s);
 hipError_t launch_part(const RankTables &rt, const EquipTables &et, const Geometry &g,
                        PairSource ps, int npairs, ItemBuffers &ib, hipStream_t s);
 DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol);
-// without the LDS split; nl_max caps the layers per pass
-DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol, int nl_max = 36);
+// without the LDS split; nl_max caps the layers per pass; force (may be
+// null) overrides the tuned table and the default rule
+DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol, int nl_max = 36,
+                const DpTune *force = nullptr);
 bool dp_fits(const Geometry &g, int n);   // every row count's DP item fits one CU's LDS
 void dp_fit_lds(DpPlan &p, int nmax, size_t rec_bytes, int cus);
 // DP over items of several groups (see DpGroup): gitems holds 3 ints per item
@@ -188,6 +211,10 @@ hipError_t launch_dp_items(const DpGroup *groups, const int *gitems, int nitems,
 // Item descriptors (0, y-2, pair*2+orientation) of row counts yi_lo ..
 // yi_lo+ncls-1, npo items each, class by class (a kernel).
 hipError_t launch_range_items(int yi_lo, int ncls, int npo, int *items, hipStream_t s);
+// Adds the bit patterns of one row count's entries (all items of a batch) to
+// *sum (the autotuner's determinism check).
+hipError_t launch_checksum(const double *A, int npo, int ASUM, int off, int cnt, unsigned long long *sum,
+                           hipStream_t s);
 // Writes one DpGroup into device memory (a kernel, so that captured graphs
 // hold no host copies).
 hipError_t launch_put_group(const DpGroup &g, DpGroup *dst, hipStream_t s);

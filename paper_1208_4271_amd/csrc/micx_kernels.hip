@@ -714,6 +714,27 @@ hipError_t launch_stats(const Geometry &g, int npairs, const ItemBuffers &ib, do
     return hipGetLastError();
 }
 
+// Sum (mod 2^64) of the bit patterns of the entries A[po * ASUM + off + l],
+// l < cnt, over all npo items: an order-free fingerprint of one row count's
+// results (the autotuner checks that every launch shape gives the same bits).
+__global__ void k_checksum(const double *A, int npo, int ASUM, int off, int cnt, unsigned long long *sum) {
+    unsigned long long acc = 0;
+    const int64_t total = (int64_t)npo * cnt;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t po = i / cnt;
+        acc += (unsigned long long)__double_as_longlong(A[po * ASUM + off + (i - po * cnt)]);
+    }
+    for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(sum, acc);
+}
+
+hipError_t launch_checksum(const double *A, int npo, int ASUM, int off, int cnt, unsigned long long *sum,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_checksum, dim3(256), dim3(256), 0, s, A, npo, ASUM, off, cnt, sum);
+    return hipGetLastError();
+}
+
 __global__ void k_put_group(DpGroup g, DpGroup *dst) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = g;
 }

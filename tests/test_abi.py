@@ -136,3 +136,23 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_tune_table_round_trip(tmp_path):
+    # the autotuner's table: load a file, save it back (host only, no device)
+    src = tmp_path / "in.txt"
+    src.write_text("micx-tune 1 gfx950\n1 11 2 37 10 3 36 2\n0 11 5 15 8 1 14 4\n")
+    micx.tune_clear()
+    try:
+        micx.tune_load(str(src))
+        out = tmp_path / "out.txt"
+        micx.tune_save(str(out))
+        lines = out.read_text().splitlines()
+        assert lines[0] == "micx-tune 1 gfx950"
+        assert sorted(lines[1:]) == sorted(["1 11 2 37 10 3 36 2", "0 11 5 15 8 1 14 4"])
+        bad = tmp_path / "bad.txt"
+        bad.write_text("micx-tune 1 gfx942\n")
+        with pytest.raises(micx.MicxError):
+            micx.tune_load(str(bad))
+    finally:
+        micx.tune_clear()

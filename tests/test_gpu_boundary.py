@@ -133,3 +133,29 @@ def test_mcn_with_eps_follows_its_definition(micx):
                         best = min(best, np.log2(xx * yy))
             assert abs(got["mcn"][e] - best) < 1e-9, (e, got["mcn"][e], best)
         assert got["mcn"][0.0] == got["stats"][3]
+
+
+def test_autotune_keeps_results_bit_identical(micx, tmp_path):
+    # every launch shape the tuner may pick gives the same bits (it checks
+    # this itself per row count); the tuned table must leave the results of
+    # both forms unchanged, also after a save/load round trip
+    import torch
+    _log("case autotune")
+    X = workloads.relations_matrix()
+    Xd = torch.from_numpy(X).cuda()
+    micx.tune_clear()
+    try:
+        ref64 = micx.allpairs(Xd, 0.6, 15.0, micx.MODE_FP64).cpu().numpy()
+        ref32 = micx.allpairs(Xd, 0.6, 15.0, micx.MODE_DP32).cpu().numpy()
+        path = str(tmp_path / "tune.txt")
+        micx.autotune(Xd, 0.6, 15.0, micx.MODE_DP32)
+        micx.autotune(Xd, 0.6, 15.0, micx.MODE_FP64, cache_path=path)
+        lines = open(path).read().splitlines()
+        assert lines[0] == "micx-tune 1 gfx950" and len(lines) > 10
+        assert np.array_equal(micx.allpairs(Xd, 0.6, 15.0, micx.MODE_FP64).cpu().numpy(), ref64)
+        assert np.array_equal(micx.allpairs(Xd, 0.6, 15.0, micx.MODE_DP32).cpu().numpy(), ref32)
+        micx.tune_clear()
+        micx.tune_load(path)
+        assert np.array_equal(micx.allpairs(Xd, 0.6, 15.0, micx.MODE_DP32).cpu().numpy(), ref32)
+    finally:
+        micx.tune_clear()
