@@ -920,10 +920,16 @@ inline size_t align16b(size_t b) { return (b + 15) & ~(size_t)15; }
 
 struct DpKey {
     int fx, NL, YR, T, sb, grp;   // grp: part of a key split to fit the LDS
+    int co;                       // cooperative launch (one item per workgroup)
     bool operator<(const DpKey &o) const {
-        return std::tie(fx, NL, YR, T, sb, grp) < std::tie(o.fx, o.NL, o.YR, o.T, o.sb, o.grp);
+        return std::tie(co, fx, NL, YR, T, sb, grp) < std::tie(o.co, o.fx, o.NL, o.YR, o.T, o.sb, o.grp);
     }
 };
+
+// Row-count classes of a batch stream whose items hold at least this many
+// superclumps (khat + 1) run cooperatively, one item per workgroup: their
+// one-wave time would otherwise bound the whole stream.
+constexpr int kCoopMinK = 2048;
 struct DpBucket {
     DpPlan plan;
     int nmax = 0;
@@ -966,7 +972,12 @@ void make_buckets(micx_ctx *ctx, const std::vector<BatchGroup> &groups, size_t g
                 p.fx = false;
                 if (p.T == 3) p.T = 2;   // three targets per lane exist in 32 bits only
             }
-            DpKey key{p.fx ? 1 : 0, p.NL, p.YR, p.T, p.fx ? (int)floor(log2(p.scale)) : 0, -1};
+            int co = 0;
+            if (p.KS >= kCoopMinK) {
+                if (!p.fx && !dp_co_built(false, p.NL, p.YR, p.T) && dp_co_built(false, p.NL, p.YR, 1)) p.T = 1;
+                co = dp_co_built(p.fx, p.NL, p.YR, p.T) ? 1 : 0;
+            }
+            DpKey key{p.fx ? 1 : 0, p.NL, p.YR, p.T, p.fx ? (int)floor(log2(p.scale)) : 0, -1, co};
             byShape[key].push_back({p, (int)i, yi, bg.n, (size_t)p.KS * p.RS * 4,
                                     (size_t)p.x * p.KS * (p.fx ? 4 : 8), (double)p.x * p.KS * p.KS});
         }
@@ -977,6 +988,9 @@ void make_buckets(micx_ctx *ctx, const std::vector<BatchGroup> &groups, size_t g
         const int vb = kv.first.fx ? 4 : 8;
         const int NLP = (kv.first.NL + 16 / vb - 1) / (16 / vb) * (16 / vb);
         auto need = [&](int nmax, size_t rec) {
+            if (kv.first.co)   // shared records and flags, four waves of eight staged sources
+                return (size_t)align16b((size_t)(nmax + 1) * vb) + align16b(rec) + kCoMeta + align16b(nmax) +
+                       4 * align16b((size_t)8 * NLP * vb);
             return (size_t)align16b((size_t)(nmax + 1) * vb) + align16b(std::max((size_t)8 * NLP * vb, (size_t)nmax)) +
                    align16b(rec);
         };
@@ -1009,6 +1023,8 @@ void make_buckets(micx_ctx *ctx, const std::vector<BatchGroup> &groups, size_t g
         p.scale = b.scale;
         p.slot_bytes = b.slot;
         p.groups = true;
+        if (kv.first.co && dp_fit_lds_co(p, b.nmax, b.rec, ctx->cus)) continue;
+        p.co = false;
         dp_fit_lds(p, b.nmax, b.rec, ctx->cus);
     }
 }
@@ -1021,7 +1037,8 @@ size_t stream_scratch(const std::vector<std::pair<const DpPlan *, size_t>> &laun
     for (size_t k = 0; k < launches.size(); k++) {
         const DpPlan &p = *launches[k].first;
         const size_t waves = std::min<size_t>(launches[k].second, (size_t)p.max_waves);
-        const size_t w = (waves + p.WPB - 1) / p.WPB * p.WPB;
+        // one G table per wave, or per workgroup in a cooperative launch
+        const size_t w = p.co ? waves : (waves + p.WPB - 1) / p.WPB * p.WPB;
         need[k % nstreams] = std::max(need[k % nstreams], w * p.slot_bytes);
     }
     size_t scr = 0;
@@ -1366,7 +1383,7 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
             HIPCHK(launch_dp_items((const DpGroup *)(ar + tab_off), ctx->gitems.as<int>() + off, nit, b.nmax,
                                    ctx->xlogx.as<double>(), tab,
                                    ctx->scratch.as<unsigned char>() + scr_off[k % kDpStreams], b.plan,
-                                   ctx->compat, st));
+                                   ctx->compat, st, nullptr, status));
             if (ctx->profiling) HIPCHK(hipEventRecord(ev.back(), st));
             off += b.items.size();
             k++;
@@ -1392,7 +1409,7 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
             HIPCHK(launch_dp_items((const DpGroup *)(ar + tab_off), srq.klist + 3 * (size_t)rkoff[k], rcap[k],
                                    b.nmax, ctx->xlogx.as<double>(), nullptr,
                                    ctx->scratch.as<unsigned char>() + rscr_off[k % kDpStreams], b.plan,
-                                   ctx->compat, ctx->dstreams[k % kDpStreams], srq.kcount + k));
+                                   ctx->compat, ctx->dstreams[k % kDpStreams], srq.kcount + k, status));
         }
         RETCHK(join());
         HIPCHK(launch_stats_g_list(gd, srq.plist, srq.pcount, ptotal, s, status));

@@ -25,6 +25,7 @@ dp_kernel_t dp_pickg_u32_0(int NL, int YR, int T);
 dp_kernel_t dp_pickg_u32_1(int NL, int YR, int T);
 dp_kernel_t dp_pickg_u32_2(int NL, int YR, int T);
 dp_kernel_t dp_pickg_u32_3(int NL, int YR, int T);
+dp_kernel_t dp_pick_co(bool fx, int NL, int YR, int T);
 
 namespace {
 
@@ -309,6 +310,45 @@ void dp_fit_lds(DpPlan &p, int nmax, size_t rec_bytes, int cus) {
     p.max_waves = cus * p.blocks_per_cu * p.WPB;
 }
 
+bool dp_co_built(bool fx, int NL, int YR, int T) { return dp_pick_co(fx, NL, YR, T) != nullptr; }
+
+// LDS of a cooperative launch: the table, the shared count records, the chunk
+// flags and minima, the superclump flags (nmax bytes), then one staging buffer
+// per wave.  Eight waves per workgroup where they fit, else four; the
+// largest staging block that fits.
+bool dp_fit_lds_co(DpPlan &p, int nmax, size_t rec_bytes, int cus) {
+    p.co = true;
+    const int vb = p.fx ? 4 : 8;
+    const int PK = 16 / vb;
+    const int NLP = (p.NL + PK - 1) / PK * PK;
+    const int budget = 160 * 1024;
+    p.lds_L = align16((size_t)(nmax + 1) * vb);
+    p.lds_rec = align16(rec_bytes);
+    p.lds_flags = align16((size_t)nmax);
+    const int fixed = p.lds_L + p.lds_rec + kCoMeta + p.lds_flags;
+    // (the FP64 instances are built for four waves per workgroup)
+    for (int w : {8, 4}) {
+        if (w == 8 && !p.fx) continue;
+        for (int sb : {32, 16, 8}) {
+            const int stage = align16((size_t)sb * NLP * vb);
+            if (fixed + w * stage <= budget) {
+                p.WPB = w;
+                p.SB = sb;
+                p.lds_stage = stage;
+                p.lds_wave = stage;
+                p.lds = fixed + w * stage;
+                dp_kernel_t k = dp_pick_co(p.fx, p.NL, p.YR, p.T);
+                if (!k) return false;
+                const int occ = cached_occupancy(k, 64 * p.WPB, p.lds);
+                p.blocks_per_cu = std::max(1, std::min(budget / p.lds, occ > 0 ? occ : 1));
+                p.max_waves = cus * p.blocks_per_cu;   // cooperative: workgroups, one item each
+                return true;
+            }
+        }
+    }
+    return false;
+}
+
 hipError_t launch_fxtable(int n, const DpPlan &p, const double *xlogx, uint32_t *tab,
                           hipStream_t s) {
     hipLaunchKernelGGL(k_fxtable, dim3((n + 256) / 256), dim3(256), 0, s, n, p.scale, xlogx, tab);
@@ -383,7 +423,7 @@ hipError_t launch_dp_debug(const RankTables &rt, const EquipTables &et, const Ge
 
 hipError_t launch_dp_items(const DpGroup *groups, const int *gitems, int nitems, int nmax,
                            const double *xlogx, const uint32_t *fxtab, void *scratch,
-                           const DpPlan &p, int compat, hipStream_t s, const int *icount) {
+                           const DpPlan &p, int compat, hipStream_t s, const int *icount, int *status) {
     DpArgs a = {};
     a.compat = compat;
     a.n = nmax;
@@ -395,12 +435,15 @@ hipError_t launch_dp_items(const DpGroup *groups, const int *gitems, int nitems,
     a.scratch = scratch; a.slot_bytes = p.slot_bytes;
     a.lds_L = p.lds_L; a.lds_stage = p.lds_stage; a.lds_wave = p.lds_wave;
     a.ilist = nullptr; a.icount = icount;
-    dp_kernel_t k = pick(p.fx, p.NL, p.YR, p.T, true);
+    a.lds_rec = p.lds_rec; a.lds_flags = p.lds_flags; a.status = status;
+    dp_kernel_t k = p.co ? dp_pick_co(p.fx, p.NL, p.YR, p.T) : pick(p.fx, p.NL, p.YR, p.T, true);
     if (!k) return hipErrorInvalidValue;
     if (p.lds > 160 * 1024) return hipErrorInvalidValue;
+    if (p.co && !status) return hipErrorInvalidValue;
     hipError_t e = ensure_lds_attr((const void *)k);
     if (e != hipSuccess) return e;
-    const int waves = std::min(nitems, p.max_waves);
+    // cooperative: one item per workgroup; else one per wave
+    const int waves = p.co ? std::min(nitems, p.max_waves) * p.WPB : std::min(nitems, p.max_waves);
     const int blocks = (waves + p.WPB - 1) / p.WPB;
     hipLaunchKernelGGL(k, dim3(blocks), dim3(64 * p.WPB), p.lds, s, a);
     return hipGetLastError();

@@ -72,7 +72,19 @@ struct DpArgs {
     // in device memory, or null: every item
     const int *ilist, *icount;
     int *dbg;                    // debug instances: the count tables, (KS*RS) ints per item
+    // cooperative instances (one item per workgroup): the shared region after
+    // the table holds the count records (lds_rec bytes), then the chunk
+    // completion flags, the per-wave minima and the abort flag, then the
+    // superclump flags of the count-table build (lds_flags bytes); each
+    // wave's staging buffer follows.  status: bit 1 set if a wait gave up.
+    int lds_rec, lds_flags;
+    int *status;
 };
+
+// A wait on another wave's chunk gives up after this many sleeps (about 0.5 s,
+// hundreds of times a chunk's time): the kernel then ends in bounded time
+// and the status word reports it.
+constexpr int kCoSpinMax = 1 << 23;
 
 template <class V> struct DpVal;
 
@@ -118,8 +130,14 @@ struct alignas(16) Pack {
 
 // DBG: a debug instance that writes each item's cumulative count table (as
 // counts) to a.dbg and skips the DP (bit-exact readback of item 10a).
-template <class V, int NL, int YR, int T, bool GR, bool DBG = false>
-__global__ __launch_bounds__(256) void k_dp(DpArgs a) {
+// CO: a cooperative instance -- the waves of a workgroup share one item: the
+// count table is built once, the chunks of every pass are dealt round-robin
+// to the waves, and a chunk's sources from earlier chunks are staged as soon
+// as those chunks' completion flags (LDS) show them final; each chunk's own
+// triangle stays in order.  For items with thousands of superclumps, whose
+// one-wave time would otherwise bound a whole launch.
+template <class V, int NL, int YR, int T, bool GR, bool DBG = false, bool CO = false>
+__global__ __launch_bounds__((CO && sizeof(V) == 4) ? 512 : 256) void k_dp(DpArgs a) {
     using DV = DpVal<V>;
     constexpr int PK = DV::PK;
     constexpr int NLP = (NL + PK - 1) / PK * PK;
@@ -143,12 +161,30 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
         else L[j] = a.xlogx[j];
     }
     __syncthreads();
-    unsigned char *wb = smem + a.lds_L + (size_t)wv * a.lds_wave;
-    V *stage = (V *)wb;                                        // SB x NLP, or labels and flags
-    int *rec = (int *)(wb + a.lds_stage);                      // (K+1) x RS: e_t, N_t[0..RS-2]
     const int wpb = blockDim.x >> 6;
-    const int gw = blockIdx.x * wpb + wv, nw = gridDim.x * wpb;
+    V *stage;                                                  // SB x NLP, or labels and flags
+    int *rec;                                                  // (K+1) x RS: e_t, N_t[0..RS-2]
+    int *done = nullptr, *abort_flag = nullptr;                // cooperative: chunk flags
+    V *wmin = nullptr;                                         // cooperative: per-wave minima
+    unsigned char *coflags = nullptr;                          // cooperative: superclump flags
+    if constexpr (CO) {
+        unsigned char *sh = smem + a.lds_L;
+        rec = (int *)sh;
+        done = (int *)(sh + a.lds_rec);
+        wmin = (V *)(sh + a.lds_rec + 4 * kCoChunks);
+        abort_flag = (int *)(sh + a.lds_rec + 4 * kCoChunks + 8 * 16);
+        coflags = sh + a.lds_rec + kCoMeta;
+        stage = (V *)(sh + a.lds_rec + kCoMeta + a.lds_flags + (size_t)wv * a.lds_stage);
+        if (threadIdx.x == 0) *abort_flag = 0;
+    } else {
+        unsigned char *wb = smem + a.lds_L + (size_t)wv * a.lds_wave;
+        stage = (V *)wb;
+        rec = (int *)(wb + a.lds_stage);
+    }
+    const int gw = CO ? blockIdx.x : blockIdx.x * wpb + wv;
+    const int nw = CO ? gridDim.x : gridDim.x * wpb;
     V *G = (V *)((unsigned char *)a.scratch + (size_t)gw * a.slot_bytes);
+    if constexpr (CO) __syncthreads();
 
     int nitems = a.nitems;
     if (a.icount) nitems = min(nitems, __builtin_amdgcn_readfirstlane(*a.icount));
@@ -198,9 +234,12 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
         // ---- cumulative counts (item 10a); rows beyond yhat stay 0 ----
         // A flag per superclump start gives each point its superclump; the
         // point's row label (stored in column order by the partition kernel)
-        // selects the count, and LDS atomics count.
-        unsigned char *F = (unsigned char *)stage;
-        if constexpr (NL < 20) {
+        // selects the count, and LDS atomics count.  (Cooperative: wave 0
+        // builds the shared table while the others wait.)
+        unsigned char *F = CO ? coflags : (unsigned char *)stage;
+        if (CO && wv != 0) {
+            // the other waves skip the build
+        } else if constexpr (NL < 20) {
             // Every lane takes a run of consecutive points: one 16-byte load
             // of labels (the first loads are issued before the table is
             // cleared); a wavefront prefix sum of the lanes' flag counts
@@ -302,7 +341,8 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
             }
             wave_sync();
         }
-        if (yh >= 8) {
+        if (CO && wv != 0) {
+        } else if (yh >= 8) {
             // one row per lane, eight superclumps per step (loads issued together)
             for (int r = lane; r < yh; r += 64) {
                 int *col = rec + 1 + r;
@@ -335,6 +375,11 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
             }
         }
         wave_sync();
+        if constexpr (CO) {
+            for (int k = lane; k < kCoChunks; k += 64)
+                if (wv == 0) done[k] = 0;
+            __syncthreads();
+        }
         if constexpr (DBG) {
             int *o = a.dbg + (size_t)wi * KS * RS;
             for (int k = lane; k < (K + 1) * RS; k += 64) o[k] = rec[k] / VB;
@@ -351,11 +396,31 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
 
         // ---- full layers l = 2..x-1 for every target (item 10b costs, OptimizeXAxis) ----
         // (NL = 0 is the shape for x = 2, where no layer is needed at every target)
+        // cooperative: the pass number whose chunk flags a wave waits for
+        int pass = 0;
+        // waits until chunk ci has finished pass `pass` (cooperative only)
+        auto wait_chunk = [&](int ci) {
+            int spins = 0;
+            while (__hip_atomic_load(done + ci, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < pass) {
+                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > kCoSpinMax) {
+                    if (lane == 0) {
+                        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        atomicOr(a.status, 2);
+                    }
+                    break;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        };
         if constexpr (NL > 0)
         for (int l0 = 2; l0 <= x - 1; l0 += NL) {
             const int nl = min(NL, x - l0);
             const int nlp = (nl + PK - 1) / PK * PK;
+            pass++;
             for (int c0 = 0; c0 < K; c0 += 64 * T) {
+                if (CO && (c0 / (64 * T)) % wpb != wv) continue;   // another wave's chunk
                 int tt[T], et[T];
                 int Nt[T][YR > 0 ? YR : 1];
                 V g[T][NLP], gprev[T];
@@ -404,6 +469,10 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
                 constexpr int SP = DV::SP;
                 for (int sb = 1; sb <= c0; sb += SB) {
                     const int ns = min(SB, c0 - sb + 1);
+                    // cooperative: the block's sources are final once the
+                    // chunk of its last source has finished this pass (a
+                    // chunk finishes only after every earlier one)
+                    if constexpr (CO) wait_chunk((sb + ns - 2) / (64 * T));
                     for (int k = lane; k < nlp * SB; k += 64) {
                         const int q = k >> sbs, sl = k & (SB - 1);
                         stage[sl * NLP + q] = (sl < ns && q < nl)
@@ -496,18 +565,39 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
                     }
                 }
                 global_sync();
+                if constexpr (CO) {
+                    // release: the chunk's layers of this pass are in G
+                    if (lane == 0)
+                        __hip_atomic_store(done + c0 / (64 * T), pass, __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
             }
+        }
+        if constexpr (CO) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
 
         // ---- last layer only at t = K: G_x(K) = min_{0 <= s < K} G_{x-1}(s) + h(s,K) ----
         V best = DV::big();
-        for (int s = lane; s < K; s += 64) {
+        for (int s = lane + (CO ? 64 * wv : 0); s < K; s += (CO ? 64 * wpb : 64)) {
             V gs = 0;   // G_{x-1}(0) = 0
             if (s > 0) gs = (x == 2) ? hcost(0, s) : G[(size_t)(x - 1) * KS + s];
             best = DV::mn(best, gs + hcost(s, K));
         }
 #pragma unroll
         for (int d = 32; d > 0; d >>= 1) best = DV::mn(best, (V)__shfl_xor(best, d, 64));
+        if constexpr (CO) {
+            // the waves' minima, combined by wave 0, which writes the scores
+            if (lane == 0) wmin[wv] = best;
+            __syncthreads();
+            if (wv != 0) {
+                __syncthreads();   // the item's end (wave 0 writes the scores)
+                continue;
+            }
+            for (int w = 1; w < wpb; w++) best = DV::mn(best, wmin[w]);
+        }
 
         // ---- I_l = (L[n] - sum_r L[q_r] - G_l(K)) / n in FP64, normalised by ln min(l, yhat) ----
         // H(Q) term: the rows' q ln q summed over lanes (a butterfly, so every
@@ -525,6 +615,7 @@ __global__ __launch_bounds__(256) void k_dp(DpArgs a) {
             Aout[l - 2] = norm >= 2 ? I * (double)norm / a.xlogx[norm] : 0.0;
         }
         wave_sync();
+        if constexpr (CO) __syncthreads();   // the item's end: rec and G are reused
     }
 }
 

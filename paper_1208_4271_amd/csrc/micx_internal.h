@@ -76,6 +76,8 @@ struct DpPlan {
     size_t slot_bytes = 0;        // G table bytes per wavefront
     bool groups = false;          // launched over batch-stream item descriptors
     int wgs = 0;                  // workgroups per CU the LDS split aims for (0: default rule)
+    bool co = false;              // cooperative: one item per workgroup of WPB waves
+    int lds_rec = 0, lds_flags = 0;   // cooperative: shared count records and superclump flags
 };
 
 // Per-batch item buffers.
@@ -207,7 +209,8 @@ void dp_fit_lds(DpPlan &p, int nmax, size_t rec_bytes, int cus);
 // icount (device, may be null): only the first min(nitems, *icount) items.
 hipError_t launch_dp_items(const DpGroup *groups, const int *gitems, int nitems, int nmax,
                            const double *xlogx, const uint32_t *fxtab, void *scratch,
-                           const DpPlan &p, int compat, hipStream_t s, const int *icount = nullptr);
+                           const DpPlan &p, int compat, hipStream_t s, const int *icount = nullptr,
+                           int *status = nullptr);
 // Item descriptors (0, y-2, pair*2+orientation) of row counts yi_lo ..
 // yi_lo+ncls-1, npo items each, class by class (a kernel).
 hipError_t launch_range_items(int yi_lo, int ncls, int npo, int *items, hipStream_t s);
@@ -229,6 +232,17 @@ hipError_t launch_fxtables(int n, const FxScales &sc, int count, const double *x
                            size_t stride, hipStream_t s);
 hipError_t launch_fxtable(int n, const DpPlan &p, const double *xlogx, uint32_t *tab,
                           hipStream_t s);
+// Cooperative DP instances: chunk completion flags per item (chunks of 64T
+// targets, K <= MICX_MAX_N) and the bytes of the shared flags, per-wave
+// minima and abort flag.
+constexpr int kCoChunks = 128;
+constexpr int kCoMeta = 4 * kCoChunks + 8 * 16 + 16;
+// Cooperative DP (one item per workgroup) for the largest stream items:
+// whether the shape has a cooperative instance, and its LDS split (WPB waves
+// per workgroup, shared records of rec_bytes); launch_dp_items then runs it
+// (status: the call's status word, bit 1 on a wait that gave up).
+bool dp_co_built(bool fx, int NL, int YR, int T);
+bool dp_fit_lds_co(DpPlan &p, int nmax, size_t rec_bytes, int cus);
 // Debug instances of the DP kernel: the count tables of the two items of
 // class yi of one pair, from both count scans (see micx_debug_tables).
 hipError_t launch_dp_debug(const RankTables &rt, const EquipTables &et, const Geometry &g, PairSource ps,
