@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmicx.so")
 SOURCES = ["micx_api.hip", "micx_kernels.hip", "micx_dp.hip", "micx_noalloc.hip", "micx_dp_co.hip"] + [
-    "micx_dp_%s_%s%d.hip" % (v, f, k) for f in ("i", "g") for v in ("f64", "u32") for k in range(4)]
+    "micx_dp_%s_%s%d.hip" % (v, f, k) for f in ("i", "g") for v in ("f64", "u32") for k in range(5)]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

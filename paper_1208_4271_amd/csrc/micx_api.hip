@@ -929,7 +929,7 @@ struct DpKey {
 // Row-count classes of a batch stream whose items hold at least this many
 // superclumps (khat + 1) run cooperatively, one item per workgroup: their
 // one-wave time would otherwise bound the whole stream.
-constexpr int kCoopMinK = 2048;
+constexpr int kCoopMinK = 1024;
 struct DpBucket {
     DpPlan plan;
     int nmax = 0;
@@ -965,13 +965,7 @@ void make_buckets(micx_ctx *ctx, const std::vector<BatchGroup> &groups, size_t g
             // DP32 2.29 -> 2.13 s on the 8,192-pair stream)
             // (the default rules: tuned choices are made for the all-pairs kernels)
             const DpTune rule;
-            DpPlan p = dp_shape(g, bg.n, yi, mode, ctx->dp32_tol, 24, &rule);
-            // a shared table uses the smallest scale of its bucket, at most a
-            // factor 2 below the class's own: keep the bound within tolerance
-            if (p.fx && 2.0 * p.bound > ctx->dp32_tol) {
-                p.fx = false;
-                if (p.T == 3) p.T = 2;   // three targets per lane exist in 32 bits only
-            }
+            DpPlan p = dp_shape(g, bg.n, yi, mode, ctx->dp32_tol, 24, &rule, true);
             int co = 0;
             if (p.KS >= kCoopMinK) {
                 if (!p.fx && !dp_co_built(false, p.NL, p.YR, p.T) && dp_co_built(false, p.NL, p.YR, 1)) p.T = 1;
@@ -981,6 +975,39 @@ void make_buckets(micx_ctx *ctx, const std::vector<BatchGroup> &groups, size_t g
             byShape[key].push_back({p, (int)i, yi, bg.n, (size_t)p.KS * p.RS * 4,
                                     (size_t)p.x * p.KS * (p.fx ? 4 : 8), (double)p.x * p.KS * p.KS});
         }
+    }
+    // a 32-bit key's classes share one table at the smallest scale among them
+    // (scales within a factor 2): a class whose bound at that scale exceeds
+    // the tolerance moves to the FP64 key of its shape
+    {
+        std::map<DpKey, std::vector<DpClass>> moved;
+        for (auto &kv : byShape) {
+            if (!kv.first.fx) continue;
+            double smin = 0.0;
+            for (const DpClass &c : kv.second) smin = smin == 0.0 ? c.p.scale : std::min(smin, c.p.scale);
+            std::vector<DpClass> keep;
+            for (const DpClass &c : kv.second) {
+                if (c.p.bound * (c.p.scale / smin) <= ctx->dp32_tol) {
+                    keep.push_back(c);
+                    continue;
+                }
+                const BatchGroup &bg = groups[g0 + c.gi];
+                const DpTune rule;
+                DpPlan p = dp_shape(lay[c.gi].hg.g, bg.n, c.yi, MICX_MODE_FP64, 0.0, 24, &rule, true);
+                int co = 0;
+                if (p.KS >= kCoopMinK) {
+                    if (!dp_co_built(false, p.NL, p.YR, p.T) && dp_co_built(false, p.NL, p.YR, 1)) p.T = 1;
+                    co = dp_co_built(false, p.NL, p.YR, p.T) ? 1 : 0;
+                }
+                DpKey key{0, p.NL, p.YR, p.T, 0, -1, co};
+                moved[key].push_back({p, c.gi, c.yi, c.n, (size_t)p.KS * p.RS * 4, (size_t)p.x * p.KS * 8, c.cost});
+            }
+            kv.second.swap(keep);
+        }
+        for (auto &kv : moved)
+            for (DpClass &c : kv.second) byShape[kv.first].push_back(c);
+        for (auto it = byShape.begin(); it != byShape.end();)
+            it = it->second.empty() ? byShape.erase(it) : std::next(it);
     }
     for (auto &kv : byShape) {
         std::vector<DpClass> &cl = kv.second;

@@ -25,6 +25,10 @@ dp_kernel_t dp_pickg_u32_0(int NL, int YR, int T);
 dp_kernel_t dp_pickg_u32_1(int NL, int YR, int T);
 dp_kernel_t dp_pickg_u32_2(int NL, int YR, int T);
 dp_kernel_t dp_pickg_u32_3(int NL, int YR, int T);
+dp_kernel_t dp_pick_f64_4(int NL, int YR, int T);
+dp_kernel_t dp_pick_u32_4(int NL, int YR, int T);
+dp_kernel_t dp_pickg_f64_4(int NL, int YR, int T);
+dp_kernel_t dp_pickg_u32_4(int NL, int YR, int T);
 dp_kernel_t dp_pick_co(bool fx, int NL, int YR, int T);
 
 namespace {
@@ -32,17 +36,21 @@ namespace {
 // gr: the instances that take per-item descriptors (batch streams)
 dp_kernel_t pick(bool fx, int NL, int YR, int T, bool gr = false) {
     typedef dp_kernel_t (*pick_t)(int, int, int);
-    static const pick_t tab[2][2][4] = {
-        {{dp_pick_f64_0, dp_pick_f64_1, dp_pick_f64_2, dp_pick_f64_3},
-         {dp_pick_u32_0, dp_pick_u32_1, dp_pick_u32_2, dp_pick_u32_3}},
-        {{dp_pickg_f64_0, dp_pickg_f64_1, dp_pickg_f64_2, dp_pickg_f64_3},
-         {dp_pickg_u32_0, dp_pickg_u32_1, dp_pickg_u32_2, dp_pickg_u32_3}}};
+    static const pick_t tab[2][2][5] = {
+        {{dp_pick_f64_0, dp_pick_f64_1, dp_pick_f64_2, dp_pick_f64_3, dp_pick_f64_4},
+         {dp_pick_u32_0, dp_pick_u32_1, dp_pick_u32_2, dp_pick_u32_3, dp_pick_u32_4}},
+        {{dp_pickg_f64_0, dp_pickg_f64_1, dp_pickg_f64_2, dp_pickg_f64_3, dp_pickg_f64_4},
+         {dp_pickg_u32_0, dp_pickg_u32_1, dp_pickg_u32_2, dp_pickg_u32_3, dp_pickg_u32_4}}};
     for (pick_t f : tab[gr ? 1 : 0][fx ? 1 : 0])
         if (dp_kernel_t k = f(NL, YR, T)) return k;
     return nullptr;
 }
 
-bool have_shape(int NL, int YR) { return pick(false, NL, YR, 1) != nullptr; }
+// a one-target instance of the shape exists in both forms (for the kernel
+// family: descriptor instances or not)
+bool have_shape(int NL, int YR, bool gr) {
+    return pick(false, NL, YR, 1, gr) != nullptr && pick(true, NL, YR, 1, gr) != nullptr;
+}
 
 int round_up_in(int v, const int *set, int count, int otherwise) {
     for (int i = 0; i < count; i++)
@@ -139,7 +147,8 @@ void tune_entry(int i, DpTuneKey &k, DpTune &v) {
     v = g_tune[i].v;
 }
 
-DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol, int nl_max, const DpTune *force) {
+DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol, int nl_max, const DpTune *force,
+                bool gr) {
     static const int NLS[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32, 36};
     static const int YRS[] = {2, 3, 4, 5, 6, 7, 8, 10, 12, 16, 20, 24, 32, 40};
     DpPlan p;
@@ -157,7 +166,7 @@ DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol, int nl_m
     const int nlcap = tuned && tv.nlcap > 0 ? std::min(tv.nlcap, nl_max) : nl_max;
     p.NL = round_up_in(std::min(nf, nlcap), NLS, 17, 36);
     p.YR = round_up_in(y, YRS, 14, 0);
-    if (!have_shape(p.NL, p.YR)) p.YR = 0;
+    if (!have_shape(p.NL, p.YR, gr)) p.YR = 0;
     // more targets per lane pay off where a pass holds many layers (measured):
     // three in the 32-bit form with few rows, else two; one for smaller passes
     p.T = (p.NL >= 20 && p.YR > 0 && p.YR <= 12) ? 2 : 1;

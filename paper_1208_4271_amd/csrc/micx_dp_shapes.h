@@ -17,7 +17,15 @@ namespace micx {
 // steps down to fewer targets per lane where a shape is not built.
 template <class V, int NL, int YR, int T, bool GR>
 constexpr bool dp_built() {
-    if (T == 1) return true;
+    // one target per lane: every shape, except descriptor instances whose
+    // label-run count scan (passes under 20 layers) and wide count rows
+    // together spill (found by the build's spill check)
+    if (T == 1) {
+        if (!GR || NL < 10 || NL >= 20) return true;
+        if (std::is_same<V, double>::value)
+            return YR <= (NL <= 10 ? 32 : NL <= 12 ? 24 : NL <= 14 ? 20 : 12);
+        return !(NL == 16 && YR == 24);
+    }
     if (NL < 20) return false;
     if (std::is_same<V, double>::value) return T == 2 && (GR ? NL <= 24 : !(NL >= 36 && YR >= 4));
     if (T == 2) return true;
@@ -38,10 +46,15 @@ dp_kernel_t dp_inst() {
 #define MICX_NL_TINY(X, YR) X(1, YR) X(2, YR) X(3, YR) X(4, YR)
 #define MICX_CASE(NLv, YRv) \
     if (NL == NLv && YR == YRv) \
-        return T == 1 ? k_dp<MICX_V, NLv, YRv, 1, MICX_GR> : T == 2 ? micx::dp_inst<MICX_V, NLv, YRv, 2, MICX_GR>() : nullptr;
+        return T == 1 ? micx::dp_inst<MICX_V, NLv, YRv, 1, MICX_GR>() : T == 2 ? micx::dp_inst<MICX_V, NLv, YRv, 2, MICX_GR>() : nullptr;
 // three targets per lane: passes of >= 20 layers with few rows (32-bit form)
 #define MICX_CASE3(NLv, YRv) \
     if (NL == NLv && YR == YRv && T == 3) return micx::dp_inst<MICX_V, NLv, YRv, 3, MICX_GR>();
 #define MICX_NL_BIG(X, YR) X(20, YR) X(24, YR) X(28, YR) X(32, YR) X(36, YR)
+// wide row counts (YR >= 10) with more layers per pass than the lists above
+// hold: large grid bounds (n = 8000 at alpha 0.7-0.75 gives x >= 24 up to
+// y = 35), one target per lane
+#define MICX_NL_MID(X, YR) X(10, YR) X(12, YR) X(14, YR) X(16, YR) X(20, YR) X(24, YR)
+#define MICX_NL_58(X, YR) X(5, YR) X(6, YR) X(7, YR) X(8, YR)
 #define MICX_CASE1(NLv, YRv) \
-    if (NL == NLv && YR == YRv) return T == 1 ? k_dp<MICX_V, NLv, YRv, 1, MICX_GR> : nullptr;
+    if (NL == NLv && YR == YRv) return T == 1 ? micx::dp_inst<MICX_V, NLv, YRv, 1, MICX_GR>() : nullptr;

@@ -199,7 +199,7 @@ DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol);
 // without the LDS split; nl_max caps the layers per pass; force (may be
 // null) overrides the tuned table and the default rule
 DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol, int nl_max = 36,
-                const DpTune *force = nullptr);
+                const DpTune *force = nullptr, bool gr = false);
 bool dp_fits(const Geometry &g, int n);   // every row count's DP item fits one CU's LDS
 void dp_fit_lds(DpPlan &p, int nmax, size_t rec_bytes, int cus);
 // DP over items of several groups (see DpGroup): gitems holds 3 ints per item
