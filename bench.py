@@ -221,15 +221,19 @@ def stream_leg(micx, steps=3):
             micx.batch(dd, offx, offy, ns, alphas, cs, mode=mode, out=out)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
+        # host time inside the last (uninstrumented) call: grouping, launch
+        # planning, uploads and launches
+        host_ms = micx.get_profile()["host_ms"]
         hosts[form] = out.cpu().numpy()
         dt = float(np.median(times))
         leg[form] = {"value": round(len(ns) / dt, 2), "unit": "pairs/s", "median_ms": round(dt * 1e3, 1),
-                     "ms": [round(t * 1e3, 1) for t in times]}
+                     "ms": [round(t * 1e3, 1) for t in times], "host_ms": round(host_ms, 1)}
         micx.set_profiling(True)
         micx.batch(dd, offx, offy, ns, alphas, cs, mode=mode, out=out)
         prof = micx.get_profile()
         micx.set_profiling(False)
         leg[form]["dp_launches"] = prof["dp_launches"]
+        leg[form]["classes"] = {"dp32": prof["dp32_classes"], "fp64": prof["fp64_classes"]}
         if prof["dp32_classes"] > 0:
             leg[form]["recheck"] = {"pairs": prof["recheck_pairs"], "items": prof["recheck_items"],
                                     "ms": round(prof["recheck_ms"], 2)}

@@ -61,9 +61,10 @@ extern "C" {
 /* Numeric forms of the dynamic program (integer stages are identical).
  * MICX_MODE_DP32 runs the DP in 32-bit fixed point: column costs are scaled
  * by S and rounded through a table (T[j] = round(S j ln j)), sums are exact
- * integer arithmetic, and every matrix entry is then within a bound that the
- * library computes per row count y, (y+1) x / (2 S n ln 2) with
- * S ~ 2^32 / (n ln y).  Row counts whose bound exceeds the tolerance (see
+ * integer arithmetic, and every matrix entry M[l][y] is then within
+ * l (yhat+1) / (2 S n ln min(l, yhat)) of the exact one, S ~ 2^32 / (n ln y).
+ * The library bounds that per row count y by its largest value over
+ * 2 <= l <= x(y), 2 <= yhat <= y.  Row counts whose bound exceeds the tolerance (see
  * micx_set_dp32_tolerance, default 5e-7) run in FP64.  Scores, the
  * H(Q) term and all statistics are computed in FP64 in both forms. */
 #define MICX_MODE_FP64  0   /* DP in FP64 */
@@ -299,6 +300,9 @@ typedef struct {
     int64_t recheck_pairs; /* MICX_MODE_DP32: pairs whose MCN the 32-bit entries left open */
     int64_t recheck_items; /* items of those pairs re-run in FP64 */
     double recheck_ms;    /* duration of the FP64 re-runs and the statistics after them */
+    double host_ms;       /* micx_batch: host time inside the call (grouping, launch
+                           * planning, uploads and launches; the device work may
+                           * still run when the call returns); 0 for other calls */
 } micx_profile;
 
 int micx_set_profiling(micx_ctx *ctx, int enable);

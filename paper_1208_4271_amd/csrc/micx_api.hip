@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <map>
 #include <tuple>
 #include <vector>
@@ -361,7 +362,6 @@ int prepare_variables(micx_ctx *ctx, const void *X, int dtype, int m, int n, con
 int lab_bytes(const Geometry &g) { return g.NY + 1 <= 256 ? 1 : 2; }
 size_t lab_row_bytes(const Geometry &g) { return (size_t)((g.n + 63) / 64 * 64) * lab_bytes(g); }
 
-// Pairs per batch: bounded so that the per-item buffers stay near 2 GB.
 // Pairs per batch.  The per-item buffers of a batch (clump and superclump
 // ends, row labels, scores, recheck lists) take up to a third of the device
 // memory free at the first call, at most 96 GB: the benchmark workload
@@ -439,9 +439,9 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
         size_t rec = 0, slot = 0;
         for (int yi = ylean; yi < g.NY; yi++) {
             const int y = yi + 2;
-            bnd[yi] = 0.5 * (double)(y + 1) * 2.0 / (lean.scale * (double)n * log(2.0));
+            bnd[yi] = dp32_bound(n, 2, y, lean.scale);
             if (bnd[yi] > ctx->dp32_tol) lean_fx = false;
-            rec = std::max(rec, (size_t)(g.khat_host[yi] + 1) * (size_t)(y + 1) * 4);
+            rec = std::max(rec, (size_t)(g.khat_host[yi] + 1) * (size_t)rec_stride(0, y) * 4);
         }
         if (!lean_fx) {
             lean = dp_shape(g, n, g.NY - 1, MICX_MODE_FP64, 0.0);
@@ -483,7 +483,7 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
         size_t rec = 0, slot = 0;
         for (int yi = 0; yi < g.NY; yi++) {
             const size_t kh1 = (size_t)g.khat_host[yi] + 1;
-            rec = std::max(rec, kh1 * (size_t)(yi + 3) * 4);
+            rec = std::max(rec, kh1 * (size_t)rec_stride(0, yi + 2) * 4);
             slot = std::max(slot, (size_t)(g.B / (yi + 2)) * kh1 * 8);
         }
         gen.slot_bytes = slot;
@@ -1308,8 +1308,7 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
         for (auto &c : b.classes) {
             const GroupLayout &L = lay[c.second.first];
             const int y = c.second.second + 2, x = L.hg.xcnt[c.second.second];
-            bound = std::max(bound, 0.5 * (double)(y + 1) * (double)x /
-                                        (b.plan.scale * (double)groups[g0 + c.second.first].n * log(2.0)));
+            bound = std::max(bound, dp32_bound(groups[g0 + c.second.first].n, x, y, b.plan.scale));
         }
     }
     const bool recheck = bound > 0.0;
@@ -1477,8 +1476,7 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
                 // the class's bound at the bucket's shared scale
                 const GroupLayout &L = lay[c.second.first];
                 const int y = c.second.second + 2, x = L.hg.xcnt[c.second.second];
-                const double bnd = 0.5 * (double)(y + 1) * (double)x /
-                                   (b.plan.scale * (double)groups[g0 + c.second.first].n * log(2.0));
+                const double bnd = dp32_bound(groups[g0 + c.second.first].n, x, y, b.plan.scale);
                 pp.dp32_classes++;
                 pp.dp32_bound = std::max(pp.dp32_bound, bnd);
             } else {
@@ -1497,6 +1495,7 @@ extern "C" int micx_batch(micx_ctx *ctx, const void *data_dev, int dtype,
                           void *stream) {
     if (!ctx || !data_dev || !pairs_host || !out_dev || npairs < 1) return MICX_EINVAL;
     if (dtype != MICX_F32 && dtype != MICX_F64 && dtype != MICX_I32) return MICX_EINVAL;
+    const auto t_entry = std::chrono::steady_clock::now();
     for (int64_t k = 0; k < npairs; k++) {
         const micx_pair_desc &d = pairs_host[k];
         RETCHK(check_common(ctx, d.n, d.alpha, d.c, mode));
@@ -1560,8 +1559,10 @@ extern "C" int micx_batch(micx_ctx *ctx, const void *data_dev, int dtype,
     RETCHK(stage_copy(ctx, ctx->bidx.p, order.data(), order.size() * sizeof(int64_t), s));
     HIPCHK(launch_scatter_rows(ctx->bout.as<double>(), ctx->bidx.as<int64_t>(), npairs, out_dev, s,
                                ctx->status.as<int>()));
+    const int rc = end_status(ctx, s);
+    total.host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_entry).count();
     ctx->prof = total;
-    return end_status(ctx, s);
+    return rc;
 }
 
 extern "C" int micx_compute_score(micx_ctx *ctx, const micx_problem *problem, const micx_param *param,

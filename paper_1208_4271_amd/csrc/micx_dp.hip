@@ -147,6 +147,31 @@ void tune_entry(int i, DpTuneKey &k, DpTune &v) {
     v = g_tune[i].v;
 }
 
+// Each rounded cost h~(s,t) has 1 + yhat table terms, each within half a unit
+// of S L[j], so a least sum over l columns is within l (yhat+1)/2 units of S
+// times the exact least sum G_l.  The entry M[l][y] divides G_l / (S n) by
+// ln min(l, yhat): its error is at most l (yhat+1) / (2 S n ln min(l, yhat)).
+// The bound is the largest value of that over 2 <= l <= x and 2 <= yhat <= y
+// (a row count with one row scores 0 whatever the DP returns).  For fixed
+// yhat the largest l / ln min(l, yhat) is 2 / ln 2, m / ln m at
+// m = min(x, yhat), or x / ln yhat when x > yhat; over yhat the products with
+// (yhat + 1) peak at yhat = 2, at yhat = min(y, x - 1), or at yhat = y.
+double dp32_bound(int n, int x, int y, double scale) {
+    if (x < 2 || y < 2 || scale <= 0.0) return 0.0;
+    const double c2 = 2.0 / log(2.0);
+    auto lmax = [&](int yh) {   // max over 2 <= l <= x of l / ln min(l, yh)
+        const int m = std::min(x, yh);
+        double v = std::max(c2, (double)m / log((double)m));
+        if (x > yh) v = std::max(v, (double)x / log((double)yh));
+        return v;
+    };
+    double w = 3.0 * lmax(2);
+    const int u = std::min(y, x - 1);
+    if (u >= 2) w = std::max(w, (double)(u + 1) * lmax(u));
+    w = std::max(w, (double)(y + 1) * lmax(y));
+    return 0.5 * w / (scale * (double)n);
+}
+
 DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol, int nl_max, const DpTune *force,
                 bool gr) {
     static const int NLS[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32, 36};
@@ -155,7 +180,7 @@ DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol, int nl_m
     const int y = yi + 2, x = g.B / y;
     const int kh = g.khat_host[yi];
     p.scale = floor(4294967296.0 / (1.02 * (double)n * log((double)std::max(y, 2))));
-    p.bound = 0.5 * (double)(y + 1) * (double)x / (p.scale * (double)n * log(2.0));
+    p.bound = dp32_bound(n, x, y, p.scale);
     p.fx = mode == MICX_MODE_DP32 && p.bound <= tol && p.scale >= 1.0;
     const int vb = p.fx ? 4 : 8;                       // bytes per DP value
     const int PK = 16 / vb;
@@ -181,7 +206,7 @@ DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol, int nl_m
     }
     const int NLP = (p.NL + PK - 1) / PK * PK;
     p.KS = kh + 1;
-    p.RS = (p.YR > 0 ? p.YR : y) + 1;
+    p.RS = rec_stride(p.YR, y);
     p.x = x;
     p.slot_bytes = (size_t)x * (size_t)p.KS * vb;      // layers 0..x-1 (0 unused)
     return p;
@@ -396,7 +421,7 @@ hipError_t launch_dp(const RankTables &rt, const EquipTables &et, const Geometry
 // The debug instances of the DP kernel (count tables only) for the two items
 // of row count class yi of one pair: the label-run count scan of passes under
 // 20 layers and the ballot scan of wider passes, each writing (khat+1)(y+1)
-// ints per item (records of stride y+1: e_t, then the rows' counts), to
+// ints per item (records of y+1 ints: e_t, then the rows' counts), to
 // out[0..] and out[2*(khat+1)(y+1)..].
 hipError_t launch_dp_debug(const RankTables &rt, const EquipTables &et, const Geometry &g, PairSource ps,
                            const ItemBuffers &ib, const double *xlogx, int yi, int cus, int *out,
@@ -408,7 +433,7 @@ hipError_t launch_dp_debug(const RankTables &rt, const EquipTables &et, const Ge
         p.NL = nls[v];
         p.YR = 0;
         p.T = 1;
-        p.RS = yi + 3;
+        p.RS = rec_stride(0, yi + 2);
         dp_fit_lds(p, rt.n, (size_t)p.KS * p.RS * 4, cus);
         DpArgs a = {};
         a.n = rt.n; a.NY = g.NY; a.KSUM = g.KSUM; a.ASUM = g.ASUM;
@@ -419,7 +444,7 @@ hipError_t launch_dp_debug(const RankTables &rt, const EquipTables &et, const Ge
         a.lab = ib.lab; a.lab_row = ib.lab_row; a.lab16 = ib.lab16;
         a.xlogx = xlogx; a.compat = g.compat;
         a.lds_L = p.lds_L; a.lds_stage = p.lds_stage; a.lds_wave = p.lds_wave;
-        a.dbg = out + (size_t)v * 2 * p.KS * p.RS;
+        a.dbg = out + (size_t)v * 2 * p.KS * (yi + 3);
         if (p.lds > 160 * 1024) return hipErrorInvalidValue;
         hipError_t e = ensure_lds_attr((const void *)ks[v]);
         if (e != hipSuccess) return e;

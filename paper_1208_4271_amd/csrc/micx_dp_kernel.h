@@ -207,7 +207,7 @@ __global__ __launch_bounds__((CO && sizeof(V) == 4) ? 512 : 256) void k_dp(DpArg
             ycls = yi + 2;
             x = gr.xcnt[yi];
             KS = gr.khat[yi] + 1;
-            RS = YR > 0 ? YR + 1 : yi + 3;
+            RS = rec_stride(YR, ycls);
             K = __builtin_amdgcn_readfirstlane(gr.K[it]);
             yh = __builtin_amdgcn_readfirstlane(gr.Yh[it]);
             ends = (gr.src[it] ? gr.sbuf : gr.cbuf) + (size_t)po * gr.KSUM + gr.koff[yi];
@@ -381,17 +381,34 @@ __global__ __launch_bounds__((CO && sizeof(V) == 4) ? 512 : 256) void k_dp(DpArg
             __syncthreads();
         }
         if constexpr (DBG) {
-            int *o = a.dbg + (size_t)wi * KS * RS;
-            for (int k = lane; k < (K + 1) * RS; k += 64) o[k] = rec[k] / VB;
+            // records of y+1 ints (the padding dropped)
+            const int W = ycls + 1;
+            int *o = a.dbg + (size_t)wi * KS * W;
+            for (int k = lane; k < (K + 1) * W; k += 64) o[k] = rec[(k / W) * RS + k % W] / VB;
             continue;
         }
 
-        // column cost h(s,t) with both records read from LDS (any row count)
+        // column cost h(s,t) with both records read from LDS (any row count).
+        // Records of all y rows (YR = 0) are read as 16-byte vectors, four
+        // table reads in flight per vector (entries past yhat are zero in both
+        // records: L[0] = 0); records of YR rows (stride YR+1), entry by entry.
         auto hcost = [&](int s, int t) -> V {
-            const int *rs = rec + s * RS, *rt = rec + t * RS;
-            V acc = LB(rt[0] - rs[0]);
-            for (int r = 0; r < yh; r++) acc -= LB(rt[1 + r] - rs[1 + r]);
-            return acc;
+            if constexpr (YR > 0) {
+                const int *rs = rec + s * RS, *rt = rec + t * RS;
+                V acc = LB(rt[0] - rs[0]);
+                for (int r = 0; r < yh; r++) acc -= LB(rt[1 + r] - rs[1 + r]);
+                return acc;
+            }
+            const int4 *rs = (const int4 *)(rec + s * RS), *rt = (const int4 *)(rec + t * RS);
+            const int4 a0 = rt[0], b0 = rs[0];
+            const V acc = LB(a0.x - b0.x);
+            V sub = LB(a0.y - b0.y) + (LB(a0.z - b0.z) + LB(a0.w - b0.w));
+            const int nq = (yh + 4) >> 2;
+            for (int q = 1; q < nq; q++) {
+                const int4 u = rt[q], v = rs[q];
+                sub += (LB(u.x - v.x) + LB(u.y - v.y)) + (LB(u.z - v.z) + LB(u.w - v.w));
+            }
+            return acc - sub;
         };
 
         // ---- full layers l = 2..x-1 for every target (item 10b costs, OptimizeXAxis) ----
@@ -438,7 +455,7 @@ __global__ __launch_bounds__((CO && sizeof(V) == 4) ? 512 : 256) void k_dp(DpArg
                             h0 -= LA(Nt[j][r]);
                         }
                     } else {
-                        for (int r = 0; r < yh; r++) h0 -= LB(rt[1 + r]);
+                        h0 = hcost(0, tc);   // record 0 is all zeros
                     }
                     gprev[j] = l0 == 2 ? h0 : G[(size_t)(l0 - 1) * KS + tc];
 #pragma unroll

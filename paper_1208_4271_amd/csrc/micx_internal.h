@@ -122,6 +122,12 @@ struct PairSource {
     int m = 0;
 };
 
+// Ints per superclump record of the DP's count table: e_t, then the rows'
+// cumulative counts.  YR rows when the kernel keeps them in registers, else
+// all y rows, padded to a multiple of four so that a record reads as 16-byte
+// vectors (the padding holds zeros).
+__host__ __device__ inline int rec_stride(int YR, int y) { return YR > 0 ? YR + 1 : (y + 4) & ~3; }
+
 // One group of a batch stream on the device (pairs sharing n, alpha and c):
 // its geometry and item buffers, for DP launches that mix groups.  The
 // group's variables are rows 2i and 2i+1 for its pair i.
@@ -200,6 +206,9 @@ DpPlan dp_plan(const Geometry &g, int n, int yi, int cus, int mode, double tol);
 // null) overrides the tuned table and the default rule
 DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol, int nl_max = 36,
                 const DpTune *force = nullptr, bool gr = false);
+// The 32-bit form's a-priori bound on |dM| for the entries M[l][y], l <= x,
+// at fixed-point scale S (rows yhat <= y, at least two; see micx_dp.hip).
+double dp32_bound(int n, int x, int y, double scale);
 bool dp_fits(const Geometry &g, int n);   // every row count's DP item fits one CU's LDS
 void dp_fit_lds(DpPlan &p, int nmax, size_t rec_bytes, int cus);
 // DP over items of several groups (see DpGroup): gitems holds 3 ints per item

@@ -128,11 +128,11 @@ extern "C" int micx_score_noalloc(micx_ctx *ctx, const void *x_dev, const void *
         const double S = plans[NY - 1].scale;
         bool fx = plans[NY - 1].fx;
         for (int yi = ylean; yi < NY; yi++)
-            if (0.5 * (double)(yi + 3) * 2.0 / (S * (double)n * log(2.0)) > tol) fx = false;
+            if (dp32_bound(n, 2, yi + 2, S) > tol) fx = false;
         for (int yi = ylean; yi < NY; yi++) {
             if (fx) {
                 plans[yi].scale = S;
-                plans[yi].bound = 0.5 * (double)(yi + 3) * 2.0 / (S * (double)n * log(2.0));
+                plans[yi].bound = dp32_bound(n, 2, yi + 2, S);
             } else if (plans[yi].fx) {
                 plans[yi] = dp_plan(g, n, yi, cus, MICX_MODE_FP64, 0.0);
             }
@@ -156,7 +156,7 @@ extern "C" int micx_score_noalloc(micx_ctx *ctx, const void *x_dev, const void *
         size_t rec = 0, slot = 0;
         for (int yi = 0; yi < NY; yi++) {
             const size_t kh1 = (size_t)khat[yi] + 1;
-            rec = std::max(rec, kh1 * (size_t)(yi + 3) * 4);
+            rec = std::max(rec, kh1 * (size_t)rec_stride(0, yi + 2) * 4);
             slot = std::max(slot, (size_t)(B / (yi + 2)) * kh1 * 8);
         }
         gen.slot_bytes = slot;
