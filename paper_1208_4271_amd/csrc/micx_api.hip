@@ -12,6 +12,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <unordered_map>
+#include <thread>
+#include <atomic>
 #include <chrono>
 #include <map>
 #include <tuple>
@@ -844,6 +847,7 @@ struct BatchGroup {
     double alpha, c, cost;
     std::vector<int64_t> idx;   // the caller's pair indices
     int64_t row0;               // first staged result row
+    const HostGeometry *hg;     // the grid geometry of (n, alpha, c), made once per call
 };
 
 // Device layout of one group inside the batch arena (byte offsets).
@@ -860,10 +864,8 @@ inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Assigns the arena offsets of a group: the parts the host fills (geometry,
 // pair list, gather offsets) from *hc, the device-only parts from *dc.
-void layout_group(const BatchGroup &bg, int esize, size_t &hc, size_t &dc, GroupLayout &L, int compat) {
-    make_geometry(bg.n, micx_grid_bound(bg.n, bg.alpha), bg.c, L.hg, compat);
-    const Geometry &g = L.hg.g;
-    const size_t P = bg.idx.size(), nv = 2 * P, n = (size_t)bg.n, NY = (size_t)g.NY;
+void layout_offsets(const Geometry &g, size_t P, int esize, size_t &hc, size_t &dc, GroupLayout &L) {
+    const size_t nv = 2 * P, n = (size_t)g.n, NY = (size_t)g.NY;
     L.NYP = (g.NY + 7) / 8 * 8;
     L.lab16 = lab_bytes(g) == 2;
     L.lab_row = lab_row_bytes(g);
@@ -891,12 +893,40 @@ void layout_group(const BatchGroup &bg, int esize, size_t &hc, size_t &dc, Group
     L.A = take(dc, nv * g.ASUM * 8);
 }
 
+void layout_group(const BatchGroup &bg, int esize, size_t &hc, size_t &dc, GroupLayout &L) {
+    L.hg = *bg.hg;
+    L.hg.g.khat_host = L.hg.khat.data();
+    layout_offsets(L.hg.g, bg.idx.size(), esize, hc, dc, L);
+}
+
 // Arena bytes of a group (both parts).
 size_t group_bytes(const BatchGroup &bg, int esize) {
     GroupLayout L;
     size_t hc = 0, dc = 0;
-    layout_group(bg, esize, hc, dc, L, 0);
+    layout_offsets(bg.hg->g, bg.idx.size(), esize, hc, dc, L);
     return hc + dc;
+}
+
+// f(i) for every i in [0, n) on up to 16 host threads, taking `chunk`
+// indices at a time (the batch stream's per-group planning: groups differ
+// widely in their row counts).
+template <class F>
+void parallel_for(size_t n, size_t chunk, F &&f) {
+    const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>(std::min<size_t>(hw, 16), (n + chunk - 1) / chunk);
+    std::atomic<size_t> next{0};
+    auto work = [&]() {
+        for (;;) {
+            const size_t lo = next.fetch_add(chunk);
+            if (lo >= n) break;
+            const size_t hi = std::min(n, lo + chunk);
+            for (size_t i = lo; i < hi; i++) f(i);
+        }
+    };
+    std::vector<std::thread> th;
+    for (size_t t = 1; t < nt; t++) th.emplace_back(work);
+    work();
+    for (std::thread &t : th) t.join();
 }
 
 void add_profile(micx_profile &t, const micx_profile &p) {
@@ -941,81 +971,151 @@ struct DpBucket {
 
 constexpr size_t kArenaBytes = (size_t)16 << 30;  // per pass over the stream (of 288 GB)
 
+// The launch shape of one (group, row count) class of a batch pass in one
+// numeric form.
+struct ClassShape {
+    DpKey key;          // grp: -1 (set when a key is split)
+    int n;
+    size_t rec, slot;   // count-record and G-table bytes per item
+    double cost, scale, bound;
+};
+
+// Shapes of every class of a pass: s[off[i] + yi] for group i, in the
+// requested form (s32: the 32-bit form where its bound allows, else FP64)
+// and in FP64 (s64: the near-tie recheck and the classes a shared scale
+// moves to FP64).
+struct PassShapes {
+    std::vector<size_t> off;
+    std::vector<ClassShape> s32, s64;
+};
+
+// The default rules, passes of at most 24 layers: the descriptor kernels then
+// keep two (FP64) or three (32-bit) targets per lane without spilling, which
+// shortens the stream's largest items (measured: FP64 3.40 -> 2.95 s, DP32
+// 2.29 -> 2.13 s on the 8,192-pair stream).  (Tuned choices are made for the
+// all-pairs kernels.)
+DpPlan class_plan(const Geometry &g, int n, int yi, int mode, double tol) {
+    const DpTune rule;
+    DpPlan p = dp_shape(g, n, yi, mode, tol, 24, &rule, true);
+    if (p.KS >= kCoopMinK) {
+        if (!p.fx && !dp_co_built(false, p.NL, p.YR, p.T) && dp_co_built(false, p.NL, p.YR, 1)) p.T = 1;
+        p.co = dp_co_built(p.fx, p.NL, p.YR, p.T);
+    }
+    return p;
+}
+
+ClassShape class_shape(const DpPlan &p, int n) {
+    ClassShape c;
+    c.key = DpKey{p.fx ? 1 : 0, p.NL, p.YR, p.T, p.fx ? (int)floor(log2(p.scale)) : 0, -1, p.co ? 1 : 0};
+    c.n = n;
+    c.rec = (size_t)p.KS * p.RS * 4;
+    c.slot = (size_t)p.x * p.KS * (p.fx ? 4 : 8);
+    c.cost = (double)p.x * p.KS * p.KS;
+    c.scale = p.scale;
+    c.bound = p.bound;
+    return c;
+}
+
+// Plans every class of groups[g0, g0 + lay.size()) on the host's threads.
+void plan_pass_shapes(micx_ctx *ctx, const std::vector<BatchGroup> &groups, size_t g0,
+                      const std::vector<GroupLayout> &lay, int mode, PassShapes &ps) {
+    const size_t ng = lay.size();
+    ps.off.assign(ng + 1, 0);
+    for (size_t i = 0; i < ng; i++) ps.off[i + 1] = ps.off[i] + (size_t)lay[i].hg.g.NY;
+    const bool fx = mode == MICX_MODE_DP32;
+    ps.s64.resize(ps.off[ng]);
+    ps.s32.resize(fx ? ps.off[ng] : 0);
+    const double tol = ctx->dp32_tol;
+    parallel_for(ng, 16, [&](size_t i) {
+        const Geometry &g = lay[i].hg.g;
+        const int n = groups[g0 + i].n;
+        for (int yi = 0; yi < g.NY; yi++) {
+            ps.s64[ps.off[i] + yi] = class_shape(class_plan(g, n, yi, MICX_MODE_FP64, 0.0), n);
+            if (fx) ps.s32[ps.off[i] + yi] = class_shape(class_plan(g, n, yi, MICX_MODE_DP32, tol), n);
+        }
+    });
+}
+
+// A DpKey (grp -1) as one integer, for hashing.
+uint64_t key_code(const DpKey &k) {
+    return ((uint64_t)k.co << 40) | ((uint64_t)k.fx << 39) | ((uint64_t)(k.NL & 0xff) << 31) |
+           ((uint64_t)(k.YR & 0xff) << 23) | ((uint64_t)(k.T & 0xff) << 15) | (uint64_t)(k.sb + 1024);
+}
+
 // Launch keys of a batch pass for one numeric form: every (group, row count)
 // class goes to the launch of its kernel shape (and fixed-point scale
 // bucket); a key whose largest table and largest count records together
 // exceed the LDS is split, largest n first, into launches that fit (every
 // class fits on its own).
 void make_buckets(micx_ctx *ctx, const std::vector<BatchGroup> &groups, size_t g0,
-                  const std::vector<GroupLayout> &lay, int mode, std::map<DpKey, DpBucket> &buckets) {
-    struct DpClass {
-        DpPlan p;
-        int gi, yi, n;
-        size_t rec, slot;
-        double cost;
+                  const std::vector<GroupLayout> &lay, const PassShapes &ps, int mode,
+                  std::map<DpKey, DpBucket> &buckets) {
+    const size_t ng = lay.size();
+    const bool fx = mode == MICX_MODE_DP32;
+    const std::vector<ClassShape> &sh = fx ? ps.s32 : ps.s64;
+    // class ids (off[i] + yi, plus total for the FP64 shape of a moved
+    // class) by key, groups taken in order of decreasing n so that every
+    // key's list is sorted by n
+    const size_t total = ps.off[ng];
+    std::vector<int> order(ng);
+    for (size_t i = 0; i < ng; i++) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int u, int v) { return groups[g0 + u].n > groups[g0 + v].n; });
+    std::vector<int> cgroup(total);   // group of each class
+    for (size_t i = 0; i < ng; i++)
+        for (size_t k = ps.off[i]; k < ps.off[i + 1]; k++) cgroup[k] = (int)i;
+    std::unordered_map<uint64_t, int> kid;
+    std::vector<DpKey> keys;
+    std::vector<std::vector<size_t>> members;
+    auto add = [&](const DpKey &key, size_t id) {
+        auto it = kid.find(key_code(key));
+        int k;
+        if (it == kid.end()) {
+            k = (int)keys.size();
+            kid.emplace(key_code(key), k);
+            keys.push_back(key);
+            members.emplace_back();
+        } else {
+            k = it->second;
+        }
+        members[k].push_back(id);
     };
-    std::map<DpKey, std::vector<DpClass>> byShape;
-    for (size_t i = 0; i < lay.size(); i++) {
-        const BatchGroup &bg = groups[g0 + i];
-        const Geometry &g = lay[i].hg.g;
-        for (int yi = 0; yi < g.NY; yi++) {
-            // passes of at most 24 layers: the descriptor kernels then keep two
-            // (FP64) or three (32-bit) targets per lane without spilling, which
-            // shortens the stream's largest items (measured: FP64 3.40 -> 2.95 s,
-            // DP32 2.29 -> 2.13 s on the 8,192-pair stream)
-            // (the default rules: tuned choices are made for the all-pairs kernels)
-            const DpTune rule;
-            DpPlan p = dp_shape(g, bg.n, yi, mode, ctx->dp32_tol, 24, &rule, true);
-            int co = 0;
-            if (p.KS >= kCoopMinK) {
-                if (!p.fx && !dp_co_built(false, p.NL, p.YR, p.T) && dp_co_built(false, p.NL, p.YR, 1)) p.T = 1;
-                co = dp_co_built(p.fx, p.NL, p.YR, p.T) ? 1 : 0;
-            }
-            DpKey key{p.fx ? 1 : 0, p.NL, p.YR, p.T, p.fx ? (int)floor(log2(p.scale)) : 0, -1, co};
-            byShape[key].push_back({p, (int)i, yi, bg.n, (size_t)p.KS * p.RS * 4,
-                                    (size_t)p.x * p.KS * (p.fx ? 4 : 8), (double)p.x * p.KS * p.KS});
-        }
-    }
-    // a 32-bit key's classes share one table at the smallest scale among them
-    // (scales within a factor 2): a class whose bound at that scale exceeds
-    // the tolerance moves to the FP64 key of its shape
-    {
-        std::map<DpKey, std::vector<DpClass>> moved;
-        for (auto &kv : byShape) {
-            if (!kv.first.fx) continue;
+    for (int i : order)
+        for (size_t k = ps.off[i]; k < ps.off[i + 1]; k++) add(sh[k].key, k);
+    auto shape = [&](size_t id) -> const ClassShape & { return id < total ? sh[id] : ps.s64[id - total]; };
+    if (fx) {
+        // a 32-bit key's classes share one table at the smallest scale among
+        // them (scales within a factor 2): a class whose bound at that scale
+        // exceeds the tolerance moves to the FP64 key of its shape
+        std::vector<int> touched;
+        const size_t nk = keys.size();
+        for (size_t k = 0; k < nk; k++) {
+            if (!keys[k].fx) continue;
             double smin = 0.0;
-            for (const DpClass &c : kv.second) smin = smin == 0.0 ? c.p.scale : std::min(smin, c.p.scale);
-            std::vector<DpClass> keep;
-            for (const DpClass &c : kv.second) {
-                if (c.p.bound * (c.p.scale / smin) <= ctx->dp32_tol) {
-                    keep.push_back(c);
-                    continue;
-                }
-                const BatchGroup &bg = groups[g0 + c.gi];
-                const DpTune rule;
-                DpPlan p = dp_shape(lay[c.gi].hg.g, bg.n, c.yi, MICX_MODE_FP64, 0.0, 24, &rule, true);
-                int co = 0;
-                if (p.KS >= kCoopMinK) {
-                    if (!dp_co_built(false, p.NL, p.YR, p.T) && dp_co_built(false, p.NL, p.YR, 1)) p.T = 1;
-                    co = dp_co_built(false, p.NL, p.YR, p.T) ? 1 : 0;
-                }
-                DpKey key{0, p.NL, p.YR, p.T, 0, -1, co};
-                moved[key].push_back({p, c.gi, c.yi, c.n, (size_t)p.KS * p.RS * 4, (size_t)p.x * p.KS * 8, c.cost});
+            for (size_t id : members[k]) smin = smin == 0.0 ? sh[id].scale : std::min(smin, sh[id].scale);
+            std::vector<size_t> keep, moved;
+            keep.reserve(members[k].size());
+            for (size_t id : members[k])
+                (sh[id].bound * (sh[id].scale / smin) <= ctx->dp32_tol ? keep : moved).push_back(id);
+            members[k].swap(keep);
+            for (size_t id : moved) {   // (add may grow `members`)
+                add(ps.s64[id].key, id + total);
+                touched.push_back(kid[key_code(ps.s64[id].key)]);
             }
-            kv.second.swap(keep);
         }
-        for (auto &kv : moved)
-            for (DpClass &c : kv.second) byShape[kv.first].push_back(c);
-        for (auto it = byShape.begin(); it != byShape.end();)
-            it = it->second.empty() ? byShape.erase(it) : std::next(it);
+        std::sort(touched.begin(), touched.end());
+        touched.erase(std::unique(touched.begin(), touched.end()), touched.end());
+        for (int k : touched)
+            std::stable_sort(members[k].begin(), members[k].end(),
+                             [&](size_t u, size_t v) { return shape(u).n > shape(v).n; });
     }
-    for (auto &kv : byShape) {
-        std::vector<DpClass> &cl = kv.second;
-        std::sort(cl.begin(), cl.end(), [](const DpClass &u, const DpClass &v) { return u.n > v.n; });
-        const int vb = kv.first.fx ? 4 : 8;
-        const int NLP = (kv.first.NL + 16 / vb - 1) / (16 / vb) * (16 / vb);
+    for (size_t k = 0; k < keys.size(); k++) {
+        if (members[k].empty()) continue;
+        const DpKey &key0 = keys[k];
+        const int vb = key0.fx ? 4 : 8;
+        const int NLP = (key0.NL + 16 / vb - 1) / (16 / vb) * (16 / vb);
         auto need = [&](int nmax, size_t rec) {
-            if (kv.first.co)   // shared records and flags, four waves of eight staged sources
+            if (key0.co)   // shared records and flags, four waves of eight staged sources
                 return (size_t)align16b((size_t)(nmax + 1) * vb) + align16b(rec) + kCoMeta + align16b(nmax) +
                        4 * align16b((size_t)8 * NLP * vb);
             return (size_t)align16b((size_t)(nmax + 1) * vb) + align16b(std::max((size_t)8 * NLP * vb, (size_t)nmax)) +
@@ -1023,29 +1123,39 @@ void make_buckets(micx_ctx *ctx, const std::vector<BatchGroup> &groups, size_t g
         };
         int part = -1, nmax = 0;
         size_t rec = 0;
-        for (const DpClass &c : cl) {
+        for (size_t id : members[k]) {
+            const ClassShape &c = shape(id);
+            const int gi = cgroup[id < total ? id : id - total];
+            const int yi = (int)((id < total ? id : id - total) - ps.off[gi]);
             if (part < 0 || need(nmax, std::max(rec, c.rec)) > 160 * 1024) {
                 part++;
                 nmax = c.n;
                 rec = 0;
             }
             rec = std::max(rec, c.rec);
-            DpKey key = kv.first;
+            DpKey key = key0;
             key.grp = part;
             DpBucket &b = buckets[key];
-            if (b.classes.empty()) b.plan = c.p;
+            if (b.classes.empty())
+                b.plan = class_plan(lay[gi].hg.g, c.n, yi, key0.fx ? MICX_MODE_DP32 : MICX_MODE_FP64,
+                                    ctx->dp32_tol);
             b.nmax = std::max(b.nmax, c.n);
             b.rec = std::max(b.rec, c.rec);
             b.slot = std::max(b.slot, c.slot);
-            if (c.p.fx) b.scale = b.scale == 0.0 ? c.p.scale : std::min(b.scale, c.p.scale);
-            b.classes.push_back({c.cost, {c.gi, c.yi}});
+            if (key0.fx) b.scale = b.scale == 0.0 ? c.scale : std::min(b.scale, c.scale);
+            b.classes.push_back({c.cost, {gi, yi}});
         }
     }
-    for (auto &kv : buckets) {
-        DpBucket &b = kv.second;
+    std::vector<DpBucket *> bl;
+    for (auto &kv : buckets) bl.push_back(&kv.second);
+    parallel_for(bl.size(), 1, [&](size_t i) {
+        DpBucket &b = *bl[i];
         std::sort(b.classes.begin(), b.classes.end(),
                   [](const std::pair<double, std::pair<int, int>> &u,
                      const std::pair<double, std::pair<int, int>> &v) { return u.first > v.first; });
+    });
+    for (auto &kv : buckets) {
+        DpBucket &b = kv.second;
         DpPlan &p = b.plan;
         p.scale = b.scale;
         p.slot_bytes = b.slot;
@@ -1091,7 +1201,7 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
     size_t hc = 0, dc = 0;
     int nmax = 0;
     for (size_t i = 0; i < ng; i++) {
-        layout_group(groups[g0 + i], esize, hc, dc, lay[i], ctx->compat);
+        layout_group(groups[g0 + i], esize, hc, dc, lay[i]);
         nmax = std::max(nmax, groups[g0 + i].n);
     }
     // block maps of the fused per-group stages (group, block inside the group)
@@ -1265,8 +1375,10 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
         }
     }
     // DP keys: every (group, row count) class goes to the launch of its shape
+    PassShapes shapes;
+    plan_pass_shapes(ctx, groups, g0, lay, mode, shapes);
     std::map<DpKey, DpBucket> buckets;
-    make_buckets(ctx, groups, g0, lay, mode, buckets);
+    make_buckets(ctx, groups, g0, lay, shapes, mode, buckets);
     // keys run largest first (their longest items start at once), round-robin
     // over the DP streams
     std::vector<std::pair<const DpKey, DpBucket> *> keys;
@@ -1301,15 +1413,16 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
     // of the pass, each with a device list of the items queued for it
     // (capacity: all items of its classes), per-item flag bits and the
     // flagged pairs (StreamRecheck)
+    // (a class's bound at its bucket's shared scale: the bound scales as 1/S)
+    auto shared_bound = [&](const DpBucket &b, const std::pair<int, int> &c) {
+        const ClassShape &cs = shapes.s32[shapes.off[c.first] + c.second];
+        return cs.bound * (cs.scale / b.plan.scale);
+    };
     double bound = 0.0;
     for (auto &kv : buckets) {
         const DpBucket &b = kv.second;
         if (!b.plan.fx) continue;
-        for (auto &c : b.classes) {
-            const GroupLayout &L = lay[c.second.first];
-            const int y = c.second.second + 2, x = L.hg.xcnt[c.second.second];
-            bound = std::max(bound, dp32_bound(groups[g0 + c.second.first].n, x, y, b.plan.scale));
-        }
+        for (auto &c : b.classes) bound = std::max(bound, shared_bound(b, c.second));
     }
     const bool recheck = bound > 0.0;
     std::map<DpKey, DpBucket> rbuckets;
@@ -1319,7 +1432,7 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
     size_t rc_words = 0;
     int ptotal = 0;
     if (recheck) {
-        make_buckets(ctx, groups, g0, lay, MICX_MODE_FP64, rbuckets);
+        make_buckets(ctx, groups, g0, lay, shapes, MICX_MODE_FP64, rbuckets);
         for (auto &kv : rbuckets) rkeys.push_back(&kv);
         std::vector<size_t> kbase(ng, 0);
         size_t nk = 0;
@@ -1473,12 +1586,8 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
         const DpBucket &b = kv.second;
         for (auto &c : b.classes) {
             if (b.plan.fx) {
-                // the class's bound at the bucket's shared scale
-                const GroupLayout &L = lay[c.second.first];
-                const int y = c.second.second + 2, x = L.hg.xcnt[c.second.second];
-                const double bnd = dp32_bound(groups[g0 + c.second.first].n, x, y, b.plan.scale);
                 pp.dp32_classes++;
-                pp.dp32_bound = std::max(pp.dp32_bound, bnd);
+                pp.dp32_bound = std::max(pp.dp32_bound, shared_bound(b, c.second));
             } else {
                 pp.fp64_classes++;
             }
@@ -1501,26 +1610,36 @@ extern "C" int micx_batch(micx_ctx *ctx, const void *data_dev, int dtype,
         RETCHK(check_common(ctx, d.n, d.alpha, d.c, mode));
         if (d.off_x < 0 || d.off_y < 0) return MICX_EINVAL;
     }
-    // pairs that share (n, alpha, c) share the grid geometry; a group whose
-    // buffers would fill a large part of the arena is split
+    // pairs that share (n, alpha, c) share the grid geometry (made once per
+    // key, on the host's threads); a group whose buffers would fill a large
+    // part of the arena is split
     std::map<std::tuple<int, double, double>, std::vector<int64_t>> byKey;
     for (int64_t k = 0; k < npairs; k++)
         byKey[std::make_tuple(pairs_host[k].n, pairs_host[k].alpha, pairs_host[k].c)].push_back(k);
-    for (auto &kv : byKey) {
-        HostGeometry hg;
-        const int n = std::get<0>(kv.first);
-        make_geometry(n, micx_grid_bound(n, std::get<1>(kv.first)), std::get<2>(kv.first), hg, ctx->compat);
-        if (!dp_fits(hg.g, n)) return MICX_ETOOBIG;
-    }
+    std::vector<const std::pair<const std::tuple<int, double, double>, std::vector<int64_t>> *> kl;
+    for (auto &kv : byKey) kl.push_back(&kv);
+    std::vector<HostGeometry> kgeo(kl.size());
+    std::vector<char> kfits(kl.size(), 0);
+    parallel_for(kl.size(), 32, [&](size_t i) {
+        const int n = std::get<0>(kl[i]->first);
+        make_geometry(n, micx_grid_bound(n, std::get<1>(kl[i]->first)), std::get<2>(kl[i]->first), kgeo[i],
+                      ctx->compat);
+        const DpTune rule;   // the batch stream plans by the default rules
+        kfits[i] = dp_fits(kgeo[i].g, n, &rule) ? 1 : 0;
+    });
+    for (char f : kfits)
+        if (!f) return MICX_ETOOBIG;
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     const int esize = dtype == MICX_F64 ? 8 : 4;
     std::vector<BatchGroup> groups;
-    for (auto &kv : byKey) {
+    for (size_t ki = 0; ki < kl.size(); ki++) {
+        const auto &kv = *kl[ki];
         BatchGroup g;
         g.n = std::get<0>(kv.first);
         g.alpha = std::get<1>(kv.first);
         g.c = std::get<2>(kv.first);
+        g.hg = &kgeo[ki];
         g.idx = {kv.second.front()};
         const size_t per_pair = group_bytes(g, esize);   // upper bound per pair
         const size_t maxp = std::max<size_t>(1, kArenaBytes / 4 / std::max<size_t>(per_pair, 1));

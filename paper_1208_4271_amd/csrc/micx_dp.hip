@@ -215,9 +215,9 @@ DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol, int nl_m
 // Whether every row count's DP item fits the LDS of one compute unit with
 // the smallest split (one wavefront, 8 staged sources), priced in FP64 (the
 // 32-bit form falls back to FP64 per row count).
-bool dp_fits(const Geometry &g, int n) {
+bool dp_fits(const Geometry &g, int n, const DpTune *force) {
     for (int yi = 0; yi < g.NY; yi++) {
-        const DpPlan p = dp_shape(g, n, yi, MICX_MODE_FP64, 0.0);
+        const DpPlan p = dp_shape(g, n, yi, MICX_MODE_FP64, 0.0, 36, force);
         const int NLP = (p.NL + 1) / 2 * 2;
         const size_t need = (size_t)align16((size_t)(n + 1) * 8) +
                             align16(std::max((size_t)8 * NLP * 8, (size_t)n)) +

@@ -209,7 +209,9 @@ DpPlan dp_shape(const Geometry &g, int n, int yi, int mode, double tol, int nl_m
 // The 32-bit form's a-priori bound on |dM| for the entries M[l][y], l <= x,
 // at fixed-point scale S (rows yhat <= y, at least two; see micx_dp.hip).
 double dp32_bound(int n, int x, int y, double scale);
-bool dp_fits(const Geometry &g, int n);   // every row count's DP item fits one CU's LDS
+// Every row count's DP item fits one CU's LDS (shapes by the tuned choices,
+// or by `force` when given).
+bool dp_fits(const Geometry &g, int n, const DpTune *force = nullptr);
 void dp_fit_lds(DpPlan &p, int nmax, size_t rec_bytes, int cus);
 // DP over items of several groups (see DpGroup): gitems holds 3 ints per item
 // (group, y-2, pair*2+orientation); the plan's shape, scale and LDS split
