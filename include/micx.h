@@ -314,6 +314,13 @@ int micx_get_profile(micx_ctx *ctx, micx_profile *out);
  * tol > 0. */
 int micx_set_dp32_tolerance(micx_ctx *ctx, double tol);
 
+/* The a-priori bound on |dM| that MICX_MODE_DP32 guarantees for the entries
+ * M[l][y], 2 <= l <= x, of one row count at sample count n, at that row
+ * count's own scale S = floor(2^32 / (1.02 n ln y)): the largest
+ * l (yhat+1) / (2 S n ln min(l, yhat)) over 2 <= l <= x and 2 <= yhat <= y.
+ * Host arithmetic only (no device); 0 for x < 2, y < 2 or n < 1. */
+double micx_dp32_bound(int n, int x, int y);
+
 /* Compatibility flags (MICX_COMPAT_*, OR-ed) for every later call on ctx.
  * Returns MICX_EINVAL for unknown bits. */
 int micx_set_compat(micx_ctx *ctx, int flags);

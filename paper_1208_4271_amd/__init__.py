@@ -45,7 +45,7 @@ EXPORTS = (
     "micx_allpairs", "micx_pairs", "micx_batch", "micx_debug_item", "micx_strerror",
     "micx_set_profiling", "micx_get_profile", "micx_set_dp32_tolerance", "micx_set_compat",
     "micx_pearson", "micx_score_noalloc", "micx_status", "micx_set_graphs", "micx_debug_tables",
-    "micx_autotune", "micx_tune_save", "micx_tune_load", "micx_tune_clear",
+    "micx_autotune", "micx_tune_save", "micx_tune_load", "micx_tune_clear", "micx_dp32_bound",
 )
 
 # Size of the device array behind micx_score_noalloc (include/micx.h).
@@ -160,6 +160,8 @@ def load_library():
     lib.micx_get_profile.restype = ctypes.c_int
     lib.micx_set_dp32_tolerance.argtypes = [vp, ctypes.c_double]
     lib.micx_set_dp32_tolerance.restype = ctypes.c_int
+    lib.micx_dp32_bound.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.micx_dp32_bound.restype = ctypes.c_double
     lib.micx_set_compat.argtypes = [vp, ctypes.c_int]
     lib.micx_set_compat.restype = ctypes.c_int
     lib.micx_strerror.argtypes = [ctypes.c_int]
@@ -493,6 +495,12 @@ def get_profile(device: int = 0) -> dict:
     p = _Profile()
     _check(load_library().micx_get_profile(context(device), ctypes.byref(p)), "micx_get_profile")
     return {k: getattr(p, k) for k, _ in _Profile._fields_}
+
+
+def dp32_bound(n: int, x: int, y: int) -> float:
+    """A-priori |dM| bound of the 32-bit DP form for the entries M[l][y],
+    l <= x, at sample count n (host arithmetic; no device needed)."""
+    return float(load_library().micx_dp32_bound(int(n), int(x), int(y)))
 
 
 def set_dp32_tolerance(tol: float, device: int = 0):

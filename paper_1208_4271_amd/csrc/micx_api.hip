@@ -1754,6 +1754,12 @@ extern "C" int micx_set_dp32_tolerance(micx_ctx *ctx, double tol) {
     return MICX_OK;
 }
 
+extern "C" double micx_dp32_bound(int n, int x, int y) {
+    if (n < 1 || x < 2 || y < 2) return 0.0;
+    const double S = floor(4294967296.0 / (1.02 * (double)n * log((double)y)));
+    return dp32_bound(n, x, y, S);
+}
+
 extern "C" int micx_get_profile(micx_ctx *ctx, micx_profile *out) {
     if (!ctx || !out) return MICX_EINVAL;
     *out = ctx->prof;

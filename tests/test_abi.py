@@ -156,3 +156,21 @@ def test_tune_table_round_trip(tmp_path):
             micx.tune_load(str(bad))
     finally:
         micx.tune_clear()
+
+
+def test_dp32_bound_is_the_largest_entry_bound():
+    # the 32-bit DP's per-entry error l (yhat+1) / (2 S n ln min(l, yhat)),
+    # maximised by brute force over 2 <= l <= x, 2 <= yhat <= y, against the
+    # library's closed form (host arithmetic, no device)
+    import math
+    for n in (200, 1340, 8000):
+        for y in range(2, 60):
+            S = math.floor(2.0 ** 32 / (1.02 * n * math.log(y)))
+            for x in range(2, 60):
+                want = max(l * (yh + 1) / math.log(min(l, yh))
+                           for l in range(2, x + 1) for yh in range(2, y + 1)) / (2.0 * S * n)
+                got = micx.dp32_bound(n, x, y)
+                assert abs(got - want) <= 1e-12 * want, (n, x, y, got, want)
+                # never looser than the product of the worst l and the worst normaliser
+                assert got <= (y + 1) * x / (2.0 * S * n * math.log(2.0)) * (1 + 1e-12)
+    assert micx.dp32_bound(1340, 1, 5) == 0.0 and micx.dp32_bound(1340, 5, 1) == 0.0
