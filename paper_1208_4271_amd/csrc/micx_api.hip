@@ -88,6 +88,7 @@ struct micx_ctx {
     DevBuf dbg;                        // micx_debug_tables: the DP's count table
     DevBuf grp;                        // the batch of a pair call as one group of the descriptor kernels
     DevBuf litems;                     // descriptors of the x = 2 row counts of a batch (one launch)
+    DevBuf citems;                     // descriptors of one cooperative row count of a batch
     std::vector<hipStream_t> dstreams; // micx_batch: DP launches of different shapes run side by side
     // pinned host memory: the device status word of the last call, and a
     // staging ring for host-to-device copies of asynchronous calls
@@ -108,7 +109,7 @@ struct micx_ctx {
         return {&perm, &gsize, &grank, &rowof, &yhat, &rowstart, &xlogx, &status, &geo, &cbuf, &sbuf,
                 &Kb, &kb, &srcb, &yhb, &A, &scratch, &pairs, &input, &out, &dense, &counters, &fxtab, &lab,
                 &moments, &bdata, &boffs, &bout, &bidx, &rcwords, &rclist, &rcpairs, &rcmeta, &arena,
-                &gitems, &dbg, &grp, &litems};
+                &gitems, &dbg, &grp, &litems, &citems};
     }
 };
 
@@ -425,6 +426,7 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
     size_t scratch = 0;
     auto grid_bytes = [&](const DpPlan &p, int64_t items) {
         const size_t waves = (size_t)std::min<int64_t>(p.max_waves, items);
+        if (p.co) return waves * p.slot_bytes;   // one G table per workgroup
         return ((waves + p.WPB - 1) / p.WPB) * p.WPB * p.slot_bytes;
     };
     // the row counts with x = 2 (one layer at the last target only, the lean
@@ -433,6 +435,39 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
     int ylean = g.NY;
     while (ylean > 0 && g.B / (ylean + 1) == 2) ylean--;
     for (int yi = 0; yi < g.NY; yi++) plans[yi] = dp_plan(g, n, yi, ctx->cus, mode, ctx->dp32_tol);
+    // row counts whose items hold thousands of superclumps (large n and
+    // alpha) may run cooperatively, one item per workgroup, through the
+    // descriptor instances.  One wave per item leaves a CU's LDS to a few
+    // waves (each holds its own count records) and runs each item's passes
+    // serially; a workgroup shares the records and runs the chunks of a pass
+    // side by side, but only the staged part of a chunk overlaps (its own
+    // triangle waits for the chunk before it), so a workgroup finishes an item
+    // about min(waves, chunks/6) times sooner (fitted to the grid-bound
+    // sweep: n = 8000 at alpha 0.7, 21 chunks per pass, gains 1.5x; at
+    // alpha 0.6, 9 chunks, and at n = 2000-4000, alpha 0.7, 8-13 chunks, it
+    // loses 1.3-1.5x).  The cooperative form is taken where that makes the
+    // batch's rounds of items shorter.
+    std::vector<char> coop(g.NY, 0);
+    for (int yi = 0; yi < ylean; yi++) {
+        if (plans[yi].KS < kCoopMinK) continue;
+        const DpTune rule;
+        DpPlan pc = dp_shape(g, n, yi, mode, ctx->dp32_tol, 24, &rule, true);
+        if (!pc.fx && !dp_co_built(false, pc.NL, pc.YR, pc.T) && dp_co_built(false, pc.NL, pc.YR, 1)) pc.T = 1;
+        if (!dp_co_built(pc.fx, pc.NL, pc.YR, pc.T)) continue;
+        pc.groups = true;
+        if (!dp_fit_lds_co(pc, n, (size_t)pc.KS * pc.RS * 4, ctx->cus)) continue;
+        const double items = 2.0 * std::min<int64_t>(pb, npairs);
+        const double chunks = ceil((double)(pc.KS - 1) / (64.0 * pc.T));
+        const double speed = std::min((double)pc.WPB, chunks / 6.0);
+        const double t_one = ceil(items / std::max(plans[yi].max_waves, 1));
+        const double t_co = ceil(items / std::max(pc.max_waves, 1)) / std::max(speed, 1e-9);
+        if (!(t_co < 0.9 * t_one)) continue;
+        plans[yi] = pc;
+        coop[yi] = 1;
+    }
+    bool any_coop = false;
+    for (char c : coop) any_coop |= c != 0;
+    if (any_coop) RETCHK(ctx->citems.ensure((size_t)2 * pb * 3 * sizeof(int)));
     DpPlan lean;
     std::vector<double> bnd(g.NY, 0.0);
     bool lean_fx = false;
@@ -580,8 +615,16 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
         HIPCHK(launch_part(rt, et, g, ps, np, ib, s));
         if (counters) HIPCHK(launch_work(et, g, ps, np, ib, counters, s));
         for (int yi = 0; yi < ylean; yi++) {
-            RETCHK(mark(ev));
             const uint32_t *tab = plans[yi].fx ? ctx->fxtab.as<uint32_t>() + yi * tabn : nullptr;
+            if (coop[yi]) {
+                HIPCHK(launch_range_items(yi, 1, 2 * np, ctx->citems.as<int>(), s));
+                RETCHK(mark(ev));
+                HIPCHK(launch_dp_items(grp, ctx->citems.as<int>(), 2 * np, n, ctx->xlogx.as<double>(), tab,
+                                       ctx->scratch.p, plans[yi], g.compat, s, nullptr, (int *)status));
+                RETCHK(mark(ev));
+                continue;
+            }
+            RETCHK(mark(ev));
             HIPCHK(launch_dp(rt, et, g, ps, np, ib, ctx->xlogx.as<double>(), tab,
                              ctx->scratch.p, yi, plans[yi], s));
             RETCHK(mark(ev));
@@ -956,10 +999,6 @@ struct DpKey {
     }
 };
 
-// Row-count classes of a batch stream whose items hold at least this many
-// superclumps (khat + 1) run cooperatively, one item per workgroup: their
-// one-wave time would otherwise bound the whole stream.
-constexpr int kCoopMinK = 1024;
 struct DpBucket {
     DpPlan plan;
     int nmax = 0;

@@ -351,6 +351,8 @@ bool dp_co_built(bool fx, int NL, int YR, int T) { return dp_pick_co(fx, NL, YR,
 // per wave.  Eight waves per workgroup where they fit, else four; the
 // largest staging block that fits.
 bool dp_fit_lds_co(DpPlan &p, int nmax, size_t rec_bytes, int cus) {
+    // one completion flag per chunk of 64T targets: at most kCoChunks chunks
+    if ((p.KS - 1 + 64 * p.T - 1) / (64 * p.T) > kCoChunks) return false;
     p.co = true;
     const int vb = p.fx ? 4 : 8;
     const int PK = 16 / vb;

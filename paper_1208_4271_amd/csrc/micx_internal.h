@@ -247,6 +247,11 @@ hipError_t launch_fxtable(int n, const DpPlan &p, const double *xlogx, uint32_t 
 // targets, K <= MICX_MAX_N) and the bytes of the shared flags, per-wave
 // minima and abort flag.
 constexpr int kCoChunks = 128;
+// Row-count classes whose items hold at least this many superclump slots
+// (khat + 1) may run cooperatively, one item per workgroup: their one-wave
+// time would otherwise bound a whole launch (batch stream) or leave a CU's
+// LDS to a wave or two (all pairs at large n and alpha).
+constexpr int kCoopMinK = 1024;
 constexpr int kCoMeta = 4 * kCoChunks + 8 * 16 + 16;
 // Cooperative DP (one item per workgroup) for the largest stream items:
 // whether the shape has a cooperative instance, and its LDS split (WPB waves
