@@ -67,6 +67,8 @@ def parse():
                     help="launch every all-pairs call's kernels one by one (no captured graph)")
     ap.add_argument("--no-counts", action="store_true",
                     help="skip the RNA-seq-shaped counts workload (2000 x 1340 int32)")
+    ap.add_argument("--stream-only", action="store_true",
+                    help="time the batch stream alone and print its figures (for profiling)")
     ap.add_argument("--no-stream", action="store_true",
                     help="skip the uneven pair-stream leg (micx_batch, 8,192 pairs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -382,6 +384,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.no_graphs:
         micx.set_graphs(False)
+    if args.stream_only:
+        leg = stream_leg(micx, max(args.steps, 1))[0]
+        print(json.dumps({"batch_stream": leg}), flush=True)
+        return
     alpha, c = 0.6, 15.0
     X, planted = workloads.microarray_matrix()
     X = X[: args.m]

@@ -620,7 +620,7 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
                 HIPCHK(launch_range_items(yi, 1, 2 * np, ctx->citems.as<int>(), s));
                 RETCHK(mark(ev));
                 HIPCHK(launch_dp_items(grp, ctx->citems.as<int>(), 2 * np, n, ctx->xlogx.as<double>(), tab,
-                                       ctx->scratch.p, plans[yi], g.compat, s, nullptr, (int *)status));
+                                       ctx->scratch.p, plans[yi], g.compat, s, nullptr, ctx->status.as<int>()));
                 RETCHK(mark(ev));
                 continue;
             }
