@@ -104,6 +104,7 @@ struct micx_ctx {
     bool gseen = false;
     unsigned ggen = 0;
     hipGraphExec_t gexec = nullptr;
+    micx_profile gprof = {};           // the profile of the captured call (restored on replay)
     hipStream_t cstream = nullptr;     // capture stream
     std::vector<DevBuf *> bufs() {
         return {&perm, &gsize, &grank, &rowof, &yhat, &rowstart, &xlogx, &status, &geo, &cbuf, &sbuf,
@@ -766,9 +767,11 @@ extern "C" int micx_allpairs(micx_ctx *ctx, const void *X_dev, int dtype, int m,
     }
     const bool same = ctx->gseen && key == ctx->gkey && ctx->ggen == ctx->gen;
     if (same && ctx->gexec) {
-        // replay: the whole call is one graph launch
+        // replay: the whole call is one graph launch (its profile is the
+        // captured call's: the same launches over the same arguments)
         HIPCHK(hipGraphLaunch(ctx->gexec, s));
         ctx->last = s;
+        ctx->prof = ctx->gprof;
         return MICX_OK;
     }
     drop_graph(ctx);
@@ -804,6 +807,7 @@ extern "C" int micx_allpairs(micx_ctx *ctx, const void *X_dev, int dtype, int m,
     }
     HIPCHK(hipGraphLaunch(ctx->gexec, s));
     ctx->last = s;
+    ctx->gprof = ctx->prof;
     return MICX_OK;
 }
 

@@ -75,6 +75,22 @@ def test_async_allpairs_and_status(micx):
     micx.batch(torch.from_numpy(data).cuda(), offx, offy, ns, alphas, cs, out=out3, wait=False)
     assert micx.status() == micx.MICX_ENONFINITE
     assert (out3 == -7.0).all()
+    # the profile reports the batch call's own host time (it returned before
+    # the device finished); pair calls report none
+    h = micx.get_profile()["host_ms"]
+    assert 0.0 < h < 60e3
+    micx.allpairs(Xd, 0.6, 15.0)
+    assert micx.get_profile()["host_ms"] == 0.0
+    # a replayed graph reports the profile of its captured call, not of the
+    # calls in between
+    o4 = torch.empty((190, 4), dtype=torch.float64, device="cuda")
+    micx.allpairs(Xd, 0.6, 15.0, out=o4)   # first call with these arguments (eager)
+    micx.allpairs(Xd, 0.6, 15.0, out=o4)   # captured
+    p_cap = micx.get_profile()
+    micx.batch(torch.from_numpy(data).cuda(), [offx[0]], [offy[0]], [ns[0]], [0.6], [15.0])
+    assert micx.get_profile()["host_ms"] > 0.0
+    micx.allpairs(Xd, 0.6, 15.0, out=o4)   # replayed
+    assert micx.get_profile() == p_cap
 
 
 @pytest.mark.parametrize("mode_name", ["fp64", "dp32"])
