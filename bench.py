@@ -235,7 +235,8 @@ def stream_leg(micx, steps=3):
         prof = micx.get_profile()
         micx.set_profiling(False)
         leg[form]["dp_launches"] = prof["dp_launches"]
-        leg[form]["classes"] = {"dp32": prof["dp32_classes"], "fp64": prof["fp64_classes"]}
+        leg[form]["classes"] = {"dp32": prof["dp32_classes"], "fp64": prof["fp64_classes"],
+                                "cooperative": prof["coop_classes"]}
         if prof["dp32_classes"] > 0:
             leg[form]["recheck"] = {"pairs": prof["recheck_pairs"], "items": prof["recheck_items"],
                                     "ms": round(prof["recheck_ms"], 2)}
@@ -393,11 +394,14 @@ def main():
     X = X[: args.m]
     m, n = X.shape
     npairs = m * (m - 1) // 2
-    # the input's host-to-device copy, timed on its own (the timed steps start
-    # with the input already resident)
+    Xd = torch.from_numpy(X).cuda()
+    # the input's host-to-device copy, timed on its own into the resident
+    # buffer (the first copy above also pays for the allocation); the timed
+    # steps start with the input already resident
+    Xh = torch.from_numpy(X)
     torch.cuda.synchronize()
     t_up = time.perf_counter()
-    Xd = torch.from_numpy(X).cuda()
+    Xd.copy_(Xh)
     torch.cuda.synchronize()
     upload_ms = (time.perf_counter() - t_up) * 1e3
     out = torch.empty((npairs, 4), dtype=torch.float64, device="cuda")

@@ -300,6 +300,8 @@ typedef struct {
     int64_t recheck_pairs; /* MICX_MODE_DP32: pairs whose MCN the 32-bit entries left open */
     int64_t recheck_items; /* items of those pairs re-run in FP64 */
     double recheck_ms;    /* duration of the FP64 re-runs and the statistics after them */
+    int coop_classes;     /* (pair, row count) classes whose DP ran cooperatively (one
+                           * item per workgroup); per row count for pair calls */
     double host_ms;       /* micx_batch: host time inside the call (grouping, launch
                            * planning, uploads and launches; the device work may
                            * still run when the call returns); 0 for other calls */

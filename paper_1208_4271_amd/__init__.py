@@ -89,7 +89,7 @@ class _Profile(ctypes.Structure):
                 ("dp32_classes", ctypes.c_int), ("fp64_classes", ctypes.c_int),
                 ("dp32_bound", ctypes.c_double), ("recheck_pairs", ctypes.c_int64),
                 ("recheck_items", ctypes.c_int64), ("recheck_ms", ctypes.c_double),
-                ("host_ms", ctypes.c_double)]
+                ("coop_classes", ctypes.c_int), ("host_ms", ctypes.c_double)]
 
 
 _lib = None

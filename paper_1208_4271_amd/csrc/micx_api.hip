@@ -693,6 +693,7 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
         } else {
             ctx->prof.fp64_classes++;
         }
+        ctx->prof.coop_classes += coop[yi] ? 1 : 0;
     }
     return MICX_OK;
 }
@@ -985,6 +986,7 @@ void add_profile(micx_profile &t, const micx_profile &p) {
     t.dp_launches += p.dp_launches;
     t.dp32_classes += p.dp32_classes;
     t.fp64_classes += p.fp64_classes;
+    t.coop_classes += p.coop_classes;
     t.dp32_bound = std::max(t.dp32_bound, p.dp32_bound);
     t.recheck_pairs += p.recheck_pairs;
     t.recheck_items += p.recheck_items;
@@ -1634,6 +1636,7 @@ int run_batch_pass(micx_ctx *ctx, const void *data_dev, int dtype, const micx_pa
             } else {
                 pp.fp64_classes++;
             }
+            pp.coop_classes += b.plan.co ? 1 : 0;
         }
     }
     add_profile(prof, pp);

@@ -54,8 +54,12 @@ def test_sixteen_bit_labels_single_pair(micx):
     _log("case 16-bit labels n=%d alpha=0.75 B=%d" % (len(x), B))
     want = oracle.score(x, y, 0.75, 15.0)
     _cmp_full(micx.compute_score(x, y, 0.75, 15.0, mode=micx.MODE_FP64), want, 1e-10)
+    # the row counts with thousands of superclumps ran cooperatively (one item
+    # per workgroup) in both forms
+    assert micx.get_profile()["coop_classes"] > 0
     got32 = micx.compute_score(x, y, 0.75, 15.0, mode=micx.MODE_DP32)
     p = micx.get_profile()
+    assert p["coop_classes"] > 0
     _log("16-bit labels dp32: bound %.3g, %d fixed-point row counts, %d fp64" %
          (p["dp32_bound"], p["dp32_classes"], p["fp64_classes"]))
     assert p["dp32_classes"] > 0
