@@ -436,6 +436,17 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
     int ylean = g.NY;
     while (ylean > 0 && g.B / (ylean + 1) == 2) ylean--;
     for (int yi = 0; yi < g.NY; yi++) plans[yi] = dp_plan(g, n, yi, ctx->cus, mode, ctx->dp32_tol);
+    // the near-tie recheck re-runs queued items of 32-bit row counts in FP64
+    // with all rows' counts read from LDS (below): a row count whose records
+    // of all rows would not fit one CU's LDS beside the FP64 table runs in
+    // FP64 from the start (only at the largest n and alpha)
+    for (int yi = 0; yi < ylean; yi++) {
+        if (!plans[yi].fx) continue;
+        auto a16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
+        const size_t need = a16((size_t)(n + 1) * 8) + a16(std::max((size_t)8 * 8 * 8, (size_t)n)) +
+                            a16((size_t)(g.khat_host[yi] + 1) * rec_stride(0, yi + 2) * 4);
+        if (need > 160 * 1024) plans[yi] = dp_plan(g, n, yi, ctx->cus, MICX_MODE_FP64, 0.0);
+    }
     // row counts whose items hold thousands of superclumps (large n and
     // alpha) may run cooperatively, one item per workgroup, through the
     // descriptor instances.  One wave per item leaves a CU's LDS to a few
@@ -452,7 +463,7 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
     for (int yi = 0; yi < ylean; yi++) {
         if (plans[yi].KS < kCoopMinK) continue;
         const DpTune rule;
-        DpPlan pc = dp_shape(g, n, yi, mode, ctx->dp32_tol, 24, &rule, true);
+        DpPlan pc = dp_shape(g, n, yi, plans[yi].fx ? mode : MICX_MODE_FP64, ctx->dp32_tol, 24, &rule, true);
         if (!pc.fx && !dp_co_built(false, pc.NL, pc.YR, pc.T) && dp_co_built(false, pc.NL, pc.YR, 1)) pc.T = 1;
         if (!dp_co_built(pc.fx, pc.NL, pc.YR, pc.T)) continue;
         pc.groups = true;
@@ -521,6 +532,7 @@ int run_pairs(micx_ctx *ctx, const RankTables &rt, const EquipTables &et, const 
         gen.groups = true;
         size_t rec = 0, slot = 0;
         for (int yi = 0; yi < g.NY; yi++) {
+            if (!(yi < ylean ? plans[yi].fx : lean_fx)) continue;   // only 32-bit classes queue items
             const size_t kh1 = (size_t)g.khat_host[yi] + 1;
             rec = std::max(rec, kh1 * (size_t)rec_stride(0, yi + 2) * 4);
             slot = std::max(slot, (size_t)(g.B / (yi + 2)) * kh1 * 8);

@@ -388,12 +388,12 @@ __global__ __launch_bounds__((CO && sizeof(V) == 4) ? 512 : 256) void k_dp(DpArg
             continue;
         }
 
-        // column cost h(s,t) with both records read from LDS (any row count).
-        // Records of all y rows (YR = 0) are read as 16-byte vectors, four
+        // column cost h(s,t) with both records read from LDS (any row count):
+        // the records (a multiple of four ints each) as 16-byte vectors, four
         // table reads in flight per vector (entries past yhat are zero in both
-        // records: L[0] = 0); records of YR rows (stride YR+1), entry by entry.
+        // records: L[0] = 0)
         auto hcost = [&](int s, int t) -> V {
-            if constexpr (YR > 0) {
+            if constexpr (YR > 0 && !rec_vector(YR)) {
                 const int *rs = rec + s * RS, *rt = rec + t * RS;
                 V acc = LB(rt[0] - rs[0]);
                 for (int r = 0; r < yh; r++) acc -= LB(rt[1 + r] - rs[1 + r]);
@@ -463,16 +463,37 @@ __global__ __launch_bounds__((CO && sizeof(V) == 4) ? 512 : 256) void k_dp(DpArg
                 }
                 // h(s, t_j) for this lane's targets (count rows from registers or LDS)
                 auto hsrc = [&](int s, V (&out)[T]) {
-                    const int *rs = rec + s * RS;
-                    const int es = rs[0];
+                    if constexpr (YR > 0 && !rec_vector(YR)) {
+                        const int *rs = rec + s * RS;
+                        const int es = rs[0];
 #pragma unroll
-                    for (int j = 0; j < T; j++) out[j] = LA(et[j] - es);
-                    if constexpr (YR > 0) {
+                        for (int j = 0; j < T; j++) out[j] = LA(et[j] - es);
 #pragma unroll
                         for (int r = 0; r < YR; r++) {
                             const int nsr = rs[1 + r];
 #pragma unroll
                             for (int j = 0; j < T; j++) out[j] -= LA(Nt[j][r] - nsr);
+                        }
+                    } else if constexpr (YR > 0) {
+                        // the source's record as 16-byte broadcast reads, each
+                        // consumed before the next (entry 0 is e_s, entry 1+r
+                        // row r's count)
+                        const int4 *rs4 = (const int4 *)(rec + s * RS);
+#pragma unroll
+                        for (int q = 0; q < (YR + 4) / 4; q++) {
+                            const int4 v = rs4[q];
+                            const int w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                            for (int e = 0; e < 4; e++) {
+                                const int i = 4 * q + e;
+                                if (i == 0) {
+#pragma unroll
+                                    for (int j = 0; j < T; j++) out[j] = LA(et[j] - w[e]);
+                                } else if (i <= YR) {
+#pragma unroll
+                                    for (int j = 0; j < T; j++) out[j] -= LA(Nt[j][i - 1] - w[e]);
+                                }
+                            }
                         }
                     } else {
 #pragma unroll

@@ -23,7 +23,7 @@ constexpr bool dp_built() {
     if (T == 1) {
         if (!GR || NL < 10 || NL >= 20) return true;
         if (std::is_same<V, double>::value)
-            return YR <= (NL <= 10 ? 32 : NL <= 12 ? 24 : NL <= 14 ? 20 : 12);
+            return YR <= (NL <= 10 ? 32 : NL <= 12 ? 24 : NL <= 14 ? 16 : 12);
         return !(NL == 16 && YR == 24);
     }
     if (NL < 20) return false;

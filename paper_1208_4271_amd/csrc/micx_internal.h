@@ -124,9 +124,15 @@ struct PairSource {
 
 // Ints per superclump record of the DP's count table: e_t, then the rows'
 // cumulative counts.  YR rows when the kernel keeps them in registers, else
-// all y rows, padded to a multiple of four so that a record reads as 16-byte
-// vectors (the padding holds zeros).
-__host__ __device__ inline int rec_stride(int YR, int y) { return YR > 0 ? YR + 1 : (y + 4) & ~3; }
+// all y rows.  Padded to a multiple of four so that a record reads as 16-byte
+// vectors (the padding holds zeros), except for YR = 2 and 4: records of 3
+// ints gain nothing from vectors, and padding 5 to 8 cost the benchmark's
+// y = 4 class a workgroup per CU (measured +11%).
+__host__ __device__ constexpr bool rec_vector(int YR) { return YR != 2 && YR != 4; }
+__host__ __device__ inline int rec_stride(int YR, int y) {
+    if (YR > 0 && !rec_vector(YR)) return YR + 1;
+    return ((YR > 0 ? YR : y) + 4) & ~3;
+}
 
 // One group of a batch stream on the device (pairs sharing n, alpha and c):
 // its geometry and item buffers, for DP launches that mix groups.  The

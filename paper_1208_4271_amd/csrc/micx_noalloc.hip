@@ -120,6 +120,15 @@ extern "C" int micx_score_noalloc(micx_ctx *ctx, const void *x_dev, const void *
         return (waves + p.WPB - 1) / p.WPB * p.WPB * p.slot_bytes;
     };
     for (int yi = 0; yi < NY; yi++) plans[yi] = dp_plan(g, n, yi, cus, mode, tol);
+    // a 32-bit row count whose records of all rows would not fit beside the
+    // FP64 table in the recheck's kernel runs in FP64 (as in micx_allpairs)
+    for (int yi = 0; yi < NY; yi++) {
+        if (!plans[yi].fx || B / (yi + 2) == 2) continue;
+        auto a16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
+        const size_t need = a16((size_t)(n + 1) * 8) + a16(std::max((size_t)8 * 8 * 8, (size_t)n)) +
+                            a16((size_t)(khat[yi] + 1) * rec_stride(0, yi + 2) * 4);
+        if (need > 160 * 1024) plans[yi] = dp_plan(g, n, yi, cus, MICX_MODE_FP64, 0.0);
+    }
     // the row counts with x = 2 share the fixed-point scale of the largest y,
     // as in the other entry points (so that both give the same entries)
     int ylean = NY;
@@ -155,6 +164,7 @@ extern "C" int micx_score_noalloc(micx_ctx *ctx, const void *x_dev, const void *
         gen.groups = true;
         size_t rec = 0, slot = 0;
         for (int yi = 0; yi < NY; yi++) {
+            if (!plans[yi].fx) continue;   // only 32-bit classes queue items
             const size_t kh1 = (size_t)khat[yi] + 1;
             rec = std::max(rec, kh1 * (size_t)rec_stride(0, yi + 2) * 4);
             slot = std::max(slot, (size_t)(B / (yi + 2)) * kh1 * 8);

@@ -315,6 +315,16 @@ def test_batch_largest_pair(micx):
     assert p["dp32_classes"] > 0
     assert np.abs(got32[0, :3] - want[:3]).max() <= 2 * p["dp32_bound"] + 1e-12, (got32, want)
     assert abs(got32[0, 3] - want[3]) < 1e-9
+    # the single-pair call on the same pair in the 32-bit form: its near-tie
+    # recheck reads every row's counts from LDS, so the row counts whose
+    # records would not fit there beside the FP64 table run in FP64
+    _log("case single-pair largest pair, dp32")
+    x64, y64 = data[:n].astype(np.float64), data[n:].astype(np.float64)
+    s32 = micx.compute_score(x64, y64, 0.75, 15.0, mode=micx.MODE_DP32)
+    p = micx.get_profile()
+    assert p["dp32_classes"] > 0 and p["fp64_classes"] > 0
+    assert np.abs(s32["stats"][:3] - want[:3]).max() <= 2 * p["dp32_bound"] + 1e-12
+    assert abs(s32["stats"][3] - want[3]) < 1e-9
 
 
 def test_batch_errors_leave_output(micx):
