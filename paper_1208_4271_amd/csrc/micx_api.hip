@@ -1019,7 +1019,7 @@ struct DpKey {
 
 struct DpBucket {
     DpPlan plan;
-    int nmax = 0;
+    int nmax = 0, ksmax = 0;
     size_t rec = 0, slot = 0;
     double scale = 0.0, bound = 0.0;
     std::vector<std::pair<double, std::pair<int, int>>> classes;   // (cost, (group, yi))
@@ -1032,7 +1032,7 @@ constexpr size_t kArenaBytes = (size_t)16 << 30;  // per pass over the stream (o
 // numeric form.
 struct ClassShape {
     DpKey key;          // grp: -1 (set when a key is split)
-    int n;
+    int n, ks;          // samples, superclump slots + 1
     size_t rec, slot;   // count-record and G-table bytes per item
     double cost, scale, bound;
 };
@@ -1065,6 +1065,7 @@ ClassShape class_shape(const DpPlan &p, int n) {
     ClassShape c;
     c.key = DpKey{p.fx ? 1 : 0, p.NL, p.YR, p.T, p.fx ? (int)floor(log2(p.scale)) : 0, -1, p.co ? 1 : 0};
     c.n = n;
+    c.ks = p.KS;
     c.rec = (size_t)p.KS * p.RS * 4;
     c.slot = (size_t)p.x * p.KS * (p.fx ? 4 : 8);
     c.cost = (double)p.x * p.KS * p.KS;
@@ -1171,25 +1172,28 @@ void make_buckets(micx_ctx *ctx, const std::vector<BatchGroup> &groups, size_t g
         const DpKey &key0 = keys[k];
         const int vb = key0.fx ? 4 : 8;
         const int NLP = (key0.NL + 16 / vb - 1) / (16 / vb) * (16 / vb);
-        auto need = [&](int nmax, size_t rec) {
+        auto need = [&](int nmax, size_t rec, int ks) {
             if (key0.co)   // shared records and flags, four waves of eight staged sources
                 return (size_t)align16b((size_t)(nmax + 1) * vb) + align16b(rec) + kCoMeta + align16b(nmax) +
                        4 * align16b((size_t)8 * NLP * vb);
-            return (size_t)align16b((size_t)(nmax + 1) * vb) + align16b(std::max((size_t)8 * NLP * vb, (size_t)nmax)) +
-                   align16b(rec);
+            const size_t pairs = key0.NL == 1 ? (size_t)3 * ks * vb : 0;   // one-layer passes
+            return (size_t)align16b((size_t)(nmax + 1) * vb) +
+                   align16b(std::max(std::max((size_t)8 * NLP * vb, (size_t)nmax), pairs)) + align16b(rec);
         };
-        int part = -1, nmax = 0;
+        int part = -1, nmax = 0, ks = 0;
         size_t rec = 0;
         for (size_t id : members[k]) {
             const ClassShape &c = shape(id);
             const int gi = cgroup[id < total ? id : id - total];
             const int yi = (int)((id < total ? id : id - total) - ps.off[gi]);
-            if (part < 0 || need(nmax, std::max(rec, c.rec)) > 160 * 1024) {
+            if (part < 0 || need(nmax, std::max(rec, c.rec), std::max(ks, c.ks)) > 160 * 1024) {
                 part++;
                 nmax = c.n;
                 rec = 0;
+                ks = 0;
             }
             rec = std::max(rec, c.rec);
+            ks = std::max(ks, c.ks);
             DpKey key = key0;
             key.grp = part;
             DpBucket &b = buckets[key];
@@ -1197,6 +1201,7 @@ void make_buckets(micx_ctx *ctx, const std::vector<BatchGroup> &groups, size_t g
                 b.plan = class_plan(lay[gi].hg.g, c.n, yi, key0.fx ? MICX_MODE_DP32 : MICX_MODE_FP64,
                                     ctx->dp32_tol);
             b.nmax = std::max(b.nmax, c.n);
+            b.ksmax = std::max(b.ksmax, c.ks);
             b.rec = std::max(b.rec, c.rec);
             b.slot = std::max(b.slot, c.slot);
             if (key0.fx) b.scale = b.scale == 0.0 ? c.scale : std::min(b.scale, c.scale);
@@ -1217,6 +1222,7 @@ void make_buckets(micx_ctx *ctx, const std::vector<BatchGroup> &groups, size_t g
         p.scale = b.scale;
         p.slot_bytes = b.slot;
         p.groups = true;
+        if (p.NL == 1) p.KS = b.ksmax;   // one-layer passes size their arrays by the largest item
         if (kv.first.co && dp_fit_lds_co(p, b.nmax, b.rec, ctx->cus)) continue;
         p.co = false;
         dp_fit_lds(p, b.nmax, b.rec, ctx->cus);

@@ -219,8 +219,9 @@ bool dp_fits(const Geometry &g, int n, const DpTune *force) {
     for (int yi = 0; yi < g.NY; yi++) {
         const DpPlan p = dp_shape(g, n, yi, MICX_MODE_FP64, 0.0, 36, force);
         const int NLP = (p.NL + 1) / 2 * 2;
+        const size_t pairs = p.NL == 1 ? (size_t)3 * p.KS * 8 : 0;
         const size_t need = (size_t)align16((size_t)(n + 1) * 8) +
-                            align16(std::max((size_t)8 * NLP * 8, (size_t)n)) +
+                            align16(std::max(std::max((size_t)8 * NLP * 8, (size_t)n), pairs)) +
                             align16((size_t)p.KS * p.RS * 4);
         if (need > 160 * 1024) return false;
     }
@@ -322,8 +323,10 @@ void dp_fit_lds(DpPlan &p, int nmax, size_t rec_bytes, int cus) {
     // four for one-target passes of 14 layers or more (their registers allow
     // four waves per SIMD; measured 7% faster than two), else two
     const int wgs = p.wgs > 0 ? p.wgs : ((p.T == 1 && p.NL >= 14) ? 4 : 2);
+    // one-layer passes (x = 3) keep three arrays of KS values there instead
+    const size_t pairs = p.NL == 1 ? (size_t)3 * p.KS * vb : 0;
     for (p.SB = 64;; p.SB >>= 1) {
-        const int lds_stage = align16(std::max((size_t)p.SB * NLP * vb, (size_t)nmax));
+        const int lds_stage = align16(std::max(std::max((size_t)p.SB * NLP * vb, (size_t)nmax), pairs));
         const int wave = align16((size_t)lds_stage + lds_rec);
         p.lds_L = lds_L;
         p.lds_stage = lds_stage;

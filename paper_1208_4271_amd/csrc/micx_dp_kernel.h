@@ -411,218 +411,259 @@ __global__ __launch_bounds__((CO && sizeof(V) == 4) ? 512 : 256) void k_dp(DpArg
             return acc - sub;
         };
 
-        // ---- full layers l = 2..x-1 for every target (item 10b costs, OptimizeXAxis) ----
-        // (NL = 0 is the shape for x = 2, where no layer is needed at every target)
-        // cooperative: the pass number whose chunk flags a wave waits for
-        int pass = 0;
-        // waits until chunk ci has finished pass `pass` (cooperative only)
-        auto wait_chunk = [&](int ci) {
-            int spins = 0;
-            while (__hip_atomic_load(done + ci, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < pass) {
-                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > kCoSpinMax) {
-                    if (lane == 0) {
-                        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        atomicOr(a.status, 2);
-                    }
-                    break;
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        };
-        if constexpr (NL > 0)
-        for (int l0 = 2; l0 <= x - 1; l0 += NL) {
-            const int nl = min(NL, x - l0);
-            const int nlp = (nl + PK - 1) / PK * PK;
-            pass++;
-            for (int c0 = 0; c0 < K; c0 += 64 * T) {
-                if (CO && (c0 / (64 * T)) % wpb != wv) continue;   // another wave's chunk
-                int tt[T], et[T];
-                int Nt[T][YR > 0 ? YR : 1];
-                V g[T][NLP], gprev[T];
-#pragma unroll
-                for (int j = 0; j < T; j++) {
-                    tt[j] = c0 + 64 * j + lane + 1;
-                    const int tc = tt[j] <= K ? tt[j] : K;
-                    const int *rt = rec + tc * RS;
-                    et[j] = rt[0] + lbase;
-                    V h0 = LA(et[j]);
-                    if constexpr (YR > 0) {
-#pragma unroll
-                        for (int r = 0; r < YR; r++) {
-                            Nt[j][r] = rt[1 + r] + lbase;
-                            h0 -= LA(Nt[j][r]);
-                        }
-                    } else {
-                        h0 = hcost(0, tc);   // record 0 is all zeros
-                    }
-                    gprev[j] = l0 == 2 ? h0 : G[(size_t)(l0 - 1) * KS + tc];
-#pragma unroll
-                    for (int q = 0; q < NLP; q++) g[j][q] = h0;
-                }
-                // h(s, t_j) for this lane's targets (count rows from registers or LDS)
-                auto hsrc = [&](int s, V (&out)[T]) {
-                    if constexpr (YR > 0 && !rec_vector(YR)) {
-                        const int *rs = rec + s * RS;
-                        const int es = rs[0];
-#pragma unroll
-                        for (int j = 0; j < T; j++) out[j] = LA(et[j] - es);
-#pragma unroll
-                        for (int r = 0; r < YR; r++) {
-                            const int nsr = rs[1 + r];
-#pragma unroll
-                            for (int j = 0; j < T; j++) out[j] -= LA(Nt[j][r] - nsr);
-                        }
-                    } else if constexpr (YR > 0) {
-                        // the source's record as 16-byte broadcast reads, each
-                        // consumed before the next (entry 0 is e_s, entry 1+r
-                        // row r's count)
-                        const int4 *rs4 = (const int4 *)(rec + s * RS);
-#pragma unroll
-                        for (int q = 0; q < (YR + 4) / 4; q++) {
-                            const int4 v = rs4[q];
-                            const int w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                            for (int e = 0; e < 4; e++) {
-                                const int i = 4 * q + e;
-                                if (i == 0) {
-#pragma unroll
-                                    for (int j = 0; j < T; j++) out[j] = LA(et[j] - w[e]);
-                                } else if (i <= YR) {
-#pragma unroll
-                                    for (int j = 0; j < T; j++) out[j] -= LA(Nt[j][i - 1] - w[e]);
-                                }
-                            }
-                        }
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < T; j++) out[j] = hcost(s, tt[j] <= K ? tt[j] : K);
-                    }
-                };
-                // sources of earlier chunks, SB at a time through LDS.  The
-                // next sources' costs are gathered while this step's cells
-                // update; the fixed-point form merges two sources per min3
-                // (a missing partner carries the largest value and cost 0).
-                constexpr int SP = DV::SP;
-                for (int sb = 1; sb <= c0; sb += SB) {
-                    const int ns = min(SB, c0 - sb + 1);
-                    // cooperative: the block's sources are final once the
-                    // chunk of its last source has finished this pass (a
-                    // chunk finishes only after every earlier one)
-                    if constexpr (CO) wait_chunk((sb + ns - 2) / (64 * T));
-                    for (int k = lane; k < nlp * SB; k += 64) {
-                        const int q = k >> sbs, sl = k & (SB - 1);
-                        stage[sl * NLP + q] = (sl < ns && q < nl)
-                                                  ? G[(size_t)(l0 - 1 + q) * KS + sb + sl]
-                                                  : DV::big();
-                    }
-                    wave_sync();
-                    V hc[SP][T], hn[SP][T];
-#pragma unroll
-                    for (int u = 0; u < SP; u++) {
-                        if (u < ns) hsrc(sb + u, hc[u]);
-                        else {
-#pragma unroll
-                            for (int j = 0; j < T; j++) hc[u][j] = 0;
-                        }
-                    }
-                    for (int sl = 0; sl < ns; sl += SP) {
-#pragma unroll
-                        for (int u = 0; u < SP; u++) {
-                            const int nx = sl + SP + u;
-                            if (nx < ns) hsrc(sb + nx, hn[u]);
-                            else {
-#pragma unroll
-                                for (int j = 0; j < T; j++) hn[u][j] = 0;
-                            }
-                        }
-#pragma unroll
-                        for (int q = 0; q < NLP; q += PK) {
-                            Pack<V> v[SP];
-#pragma unroll
-                            for (int u = 0; u < SP; u++) v[u] = *(const Pack<V> *)(stage + (sl + u) * NLP + q);
-#pragma unroll
-                            for (int j = 0; j < T; j++)
-#pragma unroll
-                                for (int e = 0; e < PK; e++) {
-                                    V m = g[j][q + e];
-#pragma unroll
-                                    for (int u = 0; u < SP; u++) m = DV::mn(m, v[u].v[e] + hc[u][j]);
-                                    g[j][q + e] = m;
-                                }
-                            if ((q / PK + 1) % MICX_DP_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
-                        }
-#pragma unroll
-                        for (int u = 0; u < SP; u++)
-#pragma unroll
-                            for (int j = 0; j < T; j++) hc[u][j] = hn[u][j];
-                    }
-                    wave_sync();
-                }
-                // sources inside the chunk, in order: the lane that owns source s
-                // holds its final layers; they are broadcast to the wave through
-                // scalar registers, and the next source's costs are gathered
-                // while this source's cells update
-#pragma unroll
-                for (int jo = 0; jo < T; jo++) {
-                    const int sbeg = c0 + 64 * jo + 1;
-                    // the chunk's last target is no source for any target of this chunk
-                    const int send = min(c0 + 64 * jo + 64, min(c0 + 64 * T, K) - 1);
-                    V hs[T], hn[T];
-                    if (sbeg <= send) hsrc(sbeg, hs);
-                    for (int s = sbeg; s <= send; s++) {
-                        const int ln = s - sbeg;
-                        if (s < send) hsrc(s + 1, hn);
-#pragma unroll
-                        for (int q0 = 0; q0 < NL; q0 += 8) {
-                            V src[8];
-#pragma unroll
-                            for (int e = 0; e < 8; e++)
-                                if (q0 + e < NL) src[e] = DV::bcast(q0 + e == 0 ? gprev[jo] : g[jo][q0 + e - 1], ln);
-#pragma unroll
-                            for (int j = jo; j < T; j++) {
-                                if (j == jo && lane <= ln) continue;
-#pragma unroll
-                                for (int e = 0; e < 8; e++)
-                                    if (q0 + e < NL) g[j][q0 + e] = DV::mn(g[j][q0 + e], src[e] + hs[j]);
-                            }
-                        }
-#pragma unroll
-                        for (int j = 0; j < T; j++) hs[j] = hn[j];
-                    }
-                }
-                // the chunk's layers become sources for later chunks
-#pragma unroll
-                for (int j = 0; j < T; j++) {
-                    if (tt[j] <= K) {
-                        if (l0 == 2) G[(size_t)KS + tt[j]] = gprev[j];
-#pragma unroll
-                        for (int q = 0; q < NLP; q++)
-                            if (q < nl) G[(size_t)(l0 + q) * KS + tt[j]] = g[j][q];
-                    }
-                }
-                global_sync();
-                if constexpr (CO) {
-                    // release: the chunk's layers of this pass are in G
-                    if (lane == 0)
-                        __hip_atomic_store(done + c0 / (64 * T), pass, __ATOMIC_RELEASE,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
-            }
-        }
-        if constexpr (CO) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        }
-
-        // ---- last layer only at t = K: G_x(K) = min_{0 <= s < K} G_{x-1}(s) + h(s,K) ----
         V best = DV::big();
-        for (int s = lane + (CO ? 64 * wv : 0); s < K; s += (CO ? 64 * wpb : 64)) {
-            V gs = 0;   // G_{x-1}(0) = 0
-            if (s > 0) gs = (x == 2) ? hcost(0, s) : G[(size_t)(x - 1) * KS + s];
-            best = DV::mn(best, gs + hcost(s, K));
+        bool pairs_done = false;
+        if constexpr (NL == 1 && !CO) if (x == 3) {
+            // ---- x = 3: one full layer, whose sources are all final from the
+            // start (G_1(s) = h(0,s)).  The (s,t) pairs are spread over all
+            // lanes, each cost computed once, and layer 2 is an LDS minimum per
+            // target; a target-per-lane pass would compute every cost on a
+            // lane whether or not its target lies after the source, and leave
+            // the lanes past K idle.
+            // (three arrays of K+1 values in the staging buffer, which the
+            // host sizes for them)
+            V *G1 = (V *)stage, *G2 = G1 + (K + 1), *HK = G2 + (K + 1);
+            for (int t = lane; t <= K; t += 64) {
+                const V h = t == 0 ? (V)0 : hcost(0, t);
+                G1[t] = h;   // G_1(t), G_1(0) = 0
+                G2[t] = h;   // source 0's candidate for G_2(t), G_2(0) = 0
+            }
+            wave_sync();
+            if (lane == 0) HK[0] = G1[K];   // h(0,K)
+            // pairs 1 <= s < t <= K, row s holding t = s+1..K
+            const int np = K * (K - 1) / 2;
+            int s0 = 1, r0 = 0;
+            for (int p = lane; p < np; p += 64) {
+                while (p >= r0 + K - s0) {
+                    r0 += K - s0;
+                    s0++;
+                }
+                const int t = s0 + 1 + (p - r0);
+                const V h = hcost(s0, t);
+                if constexpr (FX) atomicMin((unsigned *)(G2 + t), (unsigned)(G1[s0] + h));
+                else atomicMin((double *)(G2 + t), (double)(G1[s0] + h));
+                if (t == K) HK[s0] = h;
+            }
+            wave_sync();
+            if (lane == 0) G[(size_t)2 * KS + K] = G2[K];
+            // last layer at t = K: G_3(K) = min_s G_2(s) + h(s,K), G_2(0) = 0
+            for (int s1 = lane; s1 < K; s1 += 64) best = DV::mn(best, G2[s1] + HK[s1]);
+            global_sync();   // lane 0's G_2(K) store before the epilogue's loads
+            pairs_done = true;
+        }
+        if (!pairs_done) {
+            // ---- full layers l = 2..x-1 for every target (item 10b costs, OptimizeXAxis) ----
+            // (NL = 0 is the shape for x = 2, where no layer is needed at every target)
+            // cooperative: the pass number whose chunk flags a wave waits for
+            int pass = 0;
+            // waits until chunk ci has finished pass `pass` (cooperative only)
+            auto wait_chunk = [&](int ci) {
+                int spins = 0;
+                while (__hip_atomic_load(done + ci, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < pass) {
+                    if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins > kCoSpinMax) {
+                        if (lane == 0) {
+                            __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            atomicOr(a.status, 2);
+                        }
+                        break;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            };
+            if constexpr (NL > 0)
+            for (int l0 = 2; l0 <= x - 1; l0 += NL) {
+                const int nl = min(NL, x - l0);
+                const int nlp = (nl + PK - 1) / PK * PK;
+                pass++;
+                for (int c0 = 0; c0 < K; c0 += 64 * T) {
+                    if (CO && (c0 / (64 * T)) % wpb != wv) continue;   // another wave's chunk
+                    int tt[T], et[T];
+                    int Nt[T][YR > 0 ? YR : 1];
+                    V g[T][NLP], gprev[T];
+    #pragma unroll
+                    for (int j = 0; j < T; j++) {
+                        tt[j] = c0 + 64 * j + lane + 1;
+                        const int tc = tt[j] <= K ? tt[j] : K;
+                        const int *rt = rec + tc * RS;
+                        et[j] = rt[0] + lbase;
+                        V h0 = LA(et[j]);
+                        if constexpr (YR > 0) {
+    #pragma unroll
+                            for (int r = 0; r < YR; r++) {
+                                Nt[j][r] = rt[1 + r] + lbase;
+                                h0 -= LA(Nt[j][r]);
+                            }
+                        } else {
+                            h0 = hcost(0, tc);   // record 0 is all zeros
+                        }
+                        gprev[j] = l0 == 2 ? h0 : G[(size_t)(l0 - 1) * KS + tc];
+    #pragma unroll
+                        for (int q = 0; q < NLP; q++) g[j][q] = h0;
+                    }
+                    // h(s, t_j) for this lane's targets (count rows from registers or LDS)
+                    auto hsrc = [&](int s, V (&out)[T]) {
+                        if constexpr (YR > 0 && !rec_vector(YR)) {
+                            const int *rs = rec + s * RS;
+                            const int es = rs[0];
+    #pragma unroll
+                            for (int j = 0; j < T; j++) out[j] = LA(et[j] - es);
+    #pragma unroll
+                            for (int r = 0; r < YR; r++) {
+                                const int nsr = rs[1 + r];
+    #pragma unroll
+                                for (int j = 0; j < T; j++) out[j] -= LA(Nt[j][r] - nsr);
+                            }
+                        } else if constexpr (YR > 0) {
+                            // the source's record as 16-byte broadcast reads, each
+                            // consumed before the next (entry 0 is e_s, entry 1+r
+                            // row r's count)
+                            const int4 *rs4 = (const int4 *)(rec + s * RS);
+    #pragma unroll
+                            for (int q = 0; q < (YR + 4) / 4; q++) {
+                                const int4 v = rs4[q];
+                                const int w[4] = {v.x, v.y, v.z, v.w};
+    #pragma unroll
+                                for (int e = 0; e < 4; e++) {
+                                    const int i = 4 * q + e;
+                                    if (i == 0) {
+    #pragma unroll
+                                        for (int j = 0; j < T; j++) out[j] = LA(et[j] - w[e]);
+                                    } else if (i <= YR) {
+    #pragma unroll
+                                        for (int j = 0; j < T; j++) out[j] -= LA(Nt[j][i - 1] - w[e]);
+                                    }
+                                }
+                            }
+                        } else {
+    #pragma unroll
+                            for (int j = 0; j < T; j++) out[j] = hcost(s, tt[j] <= K ? tt[j] : K);
+                        }
+                    };
+                    // sources of earlier chunks, SB at a time through LDS.  The
+                    // next sources' costs are gathered while this step's cells
+                    // update; the fixed-point form merges two sources per min3
+                    // (a missing partner carries the largest value and cost 0).
+                    constexpr int SP = DV::SP;
+                    for (int sb = 1; sb <= c0; sb += SB) {
+                        const int ns = min(SB, c0 - sb + 1);
+                        // cooperative: the block's sources are final once the
+                        // chunk of its last source has finished this pass (a
+                        // chunk finishes only after every earlier one)
+                        if constexpr (CO) wait_chunk((sb + ns - 2) / (64 * T));
+                        for (int k = lane; k < nlp * SB; k += 64) {
+                            const int q = k >> sbs, sl = k & (SB - 1);
+                            stage[sl * NLP + q] = (sl < ns && q < nl)
+                                                      ? G[(size_t)(l0 - 1 + q) * KS + sb + sl]
+                                                      : DV::big();
+                        }
+                        wave_sync();
+                        V hc[SP][T], hn[SP][T];
+    #pragma unroll
+                        for (int u = 0; u < SP; u++) {
+                            if (u < ns) hsrc(sb + u, hc[u]);
+                            else {
+    #pragma unroll
+                                for (int j = 0; j < T; j++) hc[u][j] = 0;
+                            }
+                        }
+                        for (int sl = 0; sl < ns; sl += SP) {
+    #pragma unroll
+                            for (int u = 0; u < SP; u++) {
+                                const int nx = sl + SP + u;
+                                if (nx < ns) hsrc(sb + nx, hn[u]);
+                                else {
+    #pragma unroll
+                                    for (int j = 0; j < T; j++) hn[u][j] = 0;
+                                }
+                            }
+    #pragma unroll
+                            for (int q = 0; q < NLP; q += PK) {
+                                Pack<V> v[SP];
+    #pragma unroll
+                                for (int u = 0; u < SP; u++) v[u] = *(const Pack<V> *)(stage + (sl + u) * NLP + q);
+    #pragma unroll
+                                for (int j = 0; j < T; j++)
+    #pragma unroll
+                                    for (int e = 0; e < PK; e++) {
+                                        V m = g[j][q + e];
+    #pragma unroll
+                                        for (int u = 0; u < SP; u++) m = DV::mn(m, v[u].v[e] + hc[u][j]);
+                                        g[j][q + e] = m;
+                                    }
+                                if ((q / PK + 1) % MICX_DP_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
+                            }
+    #pragma unroll
+                            for (int u = 0; u < SP; u++)
+    #pragma unroll
+                                for (int j = 0; j < T; j++) hc[u][j] = hn[u][j];
+                        }
+                        wave_sync();
+                    }
+                    // sources inside the chunk, in order: the lane that owns source s
+                    // holds its final layers; they are broadcast to the wave through
+                    // scalar registers, and the next source's costs are gathered
+                    // while this source's cells update
+    #pragma unroll
+                    for (int jo = 0; jo < T; jo++) {
+                        const int sbeg = c0 + 64 * jo + 1;
+                        // the chunk's last target is no source for any target of this chunk
+                        const int send = min(c0 + 64 * jo + 64, min(c0 + 64 * T, K) - 1);
+                        V hs[T], hn[T];
+                        if (sbeg <= send) hsrc(sbeg, hs);
+                        for (int s = sbeg; s <= send; s++) {
+                            const int ln = s - sbeg;
+                            if (s < send) hsrc(s + 1, hn);
+    #pragma unroll
+                            for (int q0 = 0; q0 < NL; q0 += 8) {
+                                V src[8];
+    #pragma unroll
+                                for (int e = 0; e < 8; e++)
+                                    if (q0 + e < NL) src[e] = DV::bcast(q0 + e == 0 ? gprev[jo] : g[jo][q0 + e - 1], ln);
+    #pragma unroll
+                                for (int j = jo; j < T; j++) {
+                                    if (j == jo && lane <= ln) continue;
+    #pragma unroll
+                                    for (int e = 0; e < 8; e++)
+                                        if (q0 + e < NL) g[j][q0 + e] = DV::mn(g[j][q0 + e], src[e] + hs[j]);
+                                }
+                            }
+    #pragma unroll
+                            for (int j = 0; j < T; j++) hs[j] = hn[j];
+                        }
+                    }
+                    // the chunk's layers become sources for later chunks
+    #pragma unroll
+                    for (int j = 0; j < T; j++) {
+                        if (tt[j] <= K) {
+                            if (l0 == 2) G[(size_t)KS + tt[j]] = gprev[j];
+    #pragma unroll
+                            for (int q = 0; q < NLP; q++)
+                                if (q < nl) G[(size_t)(l0 + q) * KS + tt[j]] = g[j][q];
+                        }
+                    }
+                    global_sync();
+                    if constexpr (CO) {
+                        // release: the chunk's layers of this pass are in G
+                        if (lane == 0)
+                            __hip_atomic_store(done + c0 / (64 * T), pass, __ATOMIC_RELEASE,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                }
+            }
+            if constexpr (CO) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __syncthreads();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            }
+
+            // ---- last layer only at t = K: G_x(K) = min_{0 <= s < K} G_{x-1}(s) + h(s,K) ----
+            for (int s = lane + (CO ? 64 * wv : 0); s < K; s += (CO ? 64 * wpb : 64)) {
+                V gs = 0;   // G_{x-1}(0) = 0
+                if (s > 0) gs = (x == 2) ? hcost(0, s) : G[(size_t)(x - 1) * KS + s];
+                best = DV::mn(best, gs + hcost(s, K));
+            }
         }
 #pragma unroll
         for (int d = 32; d > 0; d >>= 1) best = DV::mn(best, (V)__shfl_xor(best, d, 64));
