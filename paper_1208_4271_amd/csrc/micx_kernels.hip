@@ -236,6 +236,8 @@ struct PartArgs {
     unsigned char *lab;          // row labels in column order, [item][y-2][p]
     size_t lab_row;
     int compat;                  // MICX_COMPAT_* flags
+    int64_t nitems;              // (pair, orientation) items
+    int flat;                    // waves over consecutive (item, row count) slots
 };
 
 // LDS tile of one 64-point block: each point's labels for the wave's row
@@ -368,6 +370,185 @@ __device__ __forceinline__ void part_body(const PartArgs &a, int w, unsigned cha
     }
 }
 
+// The same scan with a wavefront over 64 consecutive (item, row count)
+// slots, so that the lanes beyond an item's row counts serve the next items
+// (22 <= NY <= 64: at most four items per wave).  Each lane follows its own
+// item's tie groups.  A tile row holds, per item of the wave, the 16-byte
+// chunks of that item's row of labels that cover its row counts in the wave
+// (at most 64 + 4 x 7 labels, 184 bytes); a lane reads its label at its own
+// column.  Rows are 13 x 16 bytes apart (the 16-byte writes of neighbouring
+// lanes fall in different banks).
+constexpr int PART_FSTRIDE = 208;
+constexpr int PART_FSLOTS = 4;
+
+template <bool L16, bool DINT, bool STRICT>
+__device__ __forceinline__ void part_body_flat(const PartArgs &a, int w, unsigned char *tile) {
+    const int NY = a.NY, n = a.n, NYP = a.NYP;
+    const int lane = threadIdx.x;
+    const int64_t total = a.nitems * NY;
+    const int64_t f0 = (int64_t)w * 64, f = f0 + lane;
+    const bool act = f < total;
+    const int64_t fc = act ? f : total - 1;
+    const int po = (int)(fc / NY), yi = (int)(fc - (int64_t)po * NY);
+    const int po0 = (int)(f0 / NY);
+    const int jl = po - po0;                                   // this lane's item among the wave's
+    const int nit = (int)((f0 + 63 < total ? f0 + 63 : total - 1) / NY) - po0 + 1;
+    // the wave's items: column variable U, row variable V, the first 16-byte
+    // chunk of its row counts in the wave, the chunk count, and its first
+    // chunk's place in the tile row
+    // (only indexes are kept per item; the addresses are formed where used)
+    int uS[PART_FSLOTS], vS[PART_FSLOTS], chS[PART_FSLOTS], tS[PART_FSLOTS];
+    int tcol = 0;
+#pragma unroll
+    for (int j = 0; j < PART_FSLOTS; j++) {
+        const int poj = po0 + (j < nit ? j : nit - 1);
+        int pi, pj;
+        pair_of(a.ps, poj >> 1, pi, pj);
+        uS[j] = (poj & 1) ? pj : pi;
+        vS[j] = (poj & 1) ? pi : pj;
+        const int lb = j == 0 ? 0 : (int)((int64_t)poj * NY - f0);   // first lane
+        const int c0 = j == 0 ? (int)(f0 - (int64_t)po0 * NY) : 0;   // first row count
+        const int len = min(NY - c0, 64 - lb);
+        chS[j] = j < nit ? ((c0 & 7) + len + 7) >> 3 : 0;
+        tS[j] = tcol;
+        tcol += chS[j];
+    }
+    const int c0q = (int)(f0 - (int64_t)po0 * NY) >> 3;   // first item's first chunk
+    const int myV = jl == 0 ? vS[0] : jl == 1 ? vS[1] : jl == 2 ? vS[2] : vS[3];
+    const int myT = jl == 0 ? tS[0] : jl == 1 ? tS[1] : jl == 2 ? tS[2] : tS[3];
+    // this lane's label: byte offset in a tile row
+    const int col = 16 * myT + 2 * (yi & 7) + 16 * ((yi >> 3) - (jl == 0 ? c0q : 0));
+    const int kh = a.khat[yi];
+    const size_t base = (size_t)po * a.KSUM + a.koff[yi];
+    int *cb = a.cbuf + base;
+    int *sb = a.sbuf + base;
+    uint4 *labo = (uint4 *)(a.lab + ((size_t)po * NY + yi) * a.lab_row);
+
+    int first = 0, mixed = 0, gstart = 0;
+    int last = -2;
+    int cstart = 0, k = 0;
+    int sa = 0, sP0 = 0, sR = n, sL = kh, sr = 0;
+
+    auto emit_clump = [&](bool e, int ce) {
+        const int size = ce - cstart;
+        k += e ? 1 : 0;
+        if (e & act & (k <= kh)) cb[k - 1] = ce;
+        const bool sup = e & (sa != 0) & closes_row_t<DINT>(sa, size, sR, sL, STRICT);
+        if (sup & act) sb[sr] = sP0 + sa;
+        sr += sup ? 1 : 0;
+        sP0 += sup ? sa : 0;
+        sa = sup ? 0 : sa;
+        sR = n - sP0;
+        sL = kh - sr;
+        sa += e ? size : 0;
+        cstart = e ? ce : cstart;
+    };
+    // closes the current group where g (per lane)
+    auto close_group_if = [&](bool g) {
+        const int lg = mixed ? -1 : first;
+        emit_clump(g & (last != -2) & ((lg == -1) | (last == -1) | (lg != last)), gstart);
+        last = g ? lg : last;
+    };
+
+    int gsz_n[PART_FSLOTS], grk_n[PART_FSLOTS];
+#pragma unroll
+    for (int j = 0; j < PART_FSLOTS; j++) {
+        gsz_n[j] = 0;
+        grk_n[j] = 0;
+        if (j < nit && lane < n) {
+            gsz_n[j] = a.gsize[(size_t)uS[j] * n + lane];
+            grk_n[j] = a.grank[(size_t)vS[j] * n + a.perm[(size_t)uS[j] * n + lane]];
+        }
+    }
+    for (int p0 = 0; p0 < n; p0 += 64) {
+        const int q = p0 + lane;
+        const int cnt = min(64, n - p0);
+        uint64_t st[PART_FSLOTS];
+        uint64_t sall = 0;
+#pragma unroll
+        for (int j = 0; j < PART_FSLOTS; j++) {
+            st[j] = 0;
+            if (j < nit) {
+                if (q < n) {
+                    // up to five chunks loaded together (indexes clamped to the
+                    // slice), the rest (row counts above 33) after them
+                    const uint4 *src = (const uint4 *)(a.rowof + ((size_t)vS[j] * n + grk_n[j]) * NYP) +
+                                       (j == 0 ? c0q : 0);
+                    uint4 *dst = (uint4 *)(tile + lane * PART_FSTRIDE) + tS[j];
+                    const int ch = chS[j];
+                    uint4 v[5];
+#pragma unroll
+                    for (int e = 0; e < 5; e++) v[e] = src[min(e, ch - 1)];
+                    if (ch > 5) {
+                        uint4 u[4];
+#pragma unroll
+                        for (int e = 0; e < 4; e++) u[e] = src[min(5 + e, ch - 1)];
+#pragma unroll
+                        for (int e = 0; e < 4; e++)
+                            if (5 + e < ch) dst[5 + e] = u[e];
+                    }
+#pragma unroll
+                    for (int e = 0; e < 5; e++)
+                        if (e < ch) dst[e] = v[e];
+                }
+                st[j] = __ballot(q < n && gsz_n[j] > 0);
+                sall |= st[j];
+                if (q + 64 < n) {
+                    gsz_n[j] = a.gsize[(size_t)uS[j] * n + q + 64];
+                    grk_n[j] = a.grank[(size_t)vS[j] * n + a.perm[(size_t)uS[j] * n + q + 64]];
+                }
+            }
+        }
+        const uint64_t mine = jl == 0 ? st[0] : jl == 1 ? st[1] : jl == 2 ? st[2] : st[3];
+        const uint32_t mlo = (uint32_t)mine, mhi = (uint32_t)(mine >> 32);
+        wave_sync();
+        constexpr int NW = L16 ? 32 : 16;
+        uint32_t pk[NW];
+#pragma unroll
+        for (int v = 0; v < NW; v++) pk[v] = 0;
+#pragma unroll
+        for (int s = 0; s < 64; s++) {
+            if (s < cnt) {
+                const int lab = *(const uint16_t *)(tile + s * PART_FSTRIDE + col);
+                if (L16) pk[s >> 1] |= (uint32_t)lab << (16 * (s & 1));
+                else pk[s >> 2] |= (uint32_t)lab << (8 * (s & 3));
+                if ((sall >> s) & 1) {
+                    // some item's tie group starts at this point: the lanes of
+                    // those items close their previous group
+                    const bool g = (((s < 32 ? mlo : mhi) >> (s & 31)) & 1) != 0;
+                    if (p0 + s > 0) close_group_if(g);
+                    mixed = g ? 0 : (mixed | (lab != first));
+                    first = g ? lab : first;
+                    gstart = g ? p0 + s : gstart;
+                } else {
+                    mixed |= (lab != first);
+                }
+            }
+        }
+        if (act) {
+            uint4 *d = labo + (p0 >> (L16 ? 3 : 4));
+#pragma unroll
+            for (int v = 0; v < NW / 4; v++) d[v] = make_uint4(pk[4 * v], pk[4 * v + 1], pk[4 * v + 2], pk[4 * v + 3]);
+        }
+        wave_sync();   // the tile is rewritten by the next block
+    }
+    close_group_if(true);
+    emit_clump(true, n);
+    if (act) {
+        sb[sr] = n;
+        const size_t it = (size_t)po * NY + yi;
+        a.k[it] = k;
+        a.Yh[it] = a.yhat[(size_t)myV * NY + yi];
+        if (k <= kh) {
+            a.K[it] = k;
+            a.src[it] = 0;
+        } else {
+            a.K[it] = sr + 1;
+            a.src[it] = 1;
+        }
+    }
+}
+
 // the compatibility variants of the row-closing test as compile-time choices
 // (a uniform branch per launch; the default test has no select or division)
 template <bool L16>
@@ -387,6 +568,22 @@ template <bool L16>
 __global__ __launch_bounds__(64) void k_part(PartArgs a) {
     __shared__ __align__(16) unsigned char tile[64 * PART_TILE];
     part_dispatch<L16>(a, blockIdx.x, tile);
+}
+
+// several items per wave (a kernel of its own: its registers do not weigh on
+// the one-item scan)
+template <bool L16>
+__global__ __launch_bounds__(64) void k_part_flat(PartArgs a) {
+    __shared__ __align__(16) unsigned char tile[64 * PART_FSTRIDE];
+    const bool dint = (a.compat & MICX_COMPAT_DESIRED_INT) != 0;
+    const bool strict = (a.compat & MICX_COMPAT_TIE_STRICT) != 0;
+    if (dint) {
+        if (strict) part_body_flat<L16, true, true>(a, blockIdx.x, tile);
+        else part_body_flat<L16, true, false>(a, blockIdx.x, tile);
+    } else {
+        if (strict) part_body_flat<L16, false, true>(a, blockIdx.x, tile);
+        else part_body_flat<L16, false, false>(a, blockIdx.x, tile);
+    }
 }
 
 // ---------------------------------------------------------- k_moments/k_pearson
@@ -695,9 +892,20 @@ hipError_t launch_part(const RankTables &rt, const EquipTables &et, const Geomet
     a.khat = g.khat; a.koff = g.koff; a.yhat = et.yhat;
     a.cbuf = ib.cbuf; a.sbuf = ib.sbuf; a.K = ib.K; a.k = ib.k; a.src = ib.src; a.Yh = ib.Yh;
     a.lab = ib.lab; a.lab_row = ib.lab_row; a.compat = et.compat;
+    a.nitems = 2 * (int64_t)npairs;
+    // row counts of several items per wave where one item leaves lanes idle
+    // and at most four items share a wave
+    a.flat = g.NY >= 22 && g.NY <= 64;
     const int nyb = (g.NY + 63) / 64;
-    if (ib.lab16) hipLaunchKernelGGL(k_part<true>, dim3((unsigned)(2 * npairs * nyb)), dim3(64), 0, s, a);
-    else hipLaunchKernelGGL(k_part<false>, dim3((unsigned)(2 * npairs * nyb)), dim3(64), 0, s, a);
+    const int64_t waves = a.flat ? (a.nitems * g.NY + 63) / 64 : 2 * (int64_t)npairs * nyb;
+    if (a.flat) {
+        if (ib.lab16) hipLaunchKernelGGL(k_part_flat<true>, dim3((unsigned)waves), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL(k_part_flat<false>, dim3((unsigned)waves), dim3(64), 0, s, a);
+    } else if (ib.lab16) {
+        hipLaunchKernelGGL(k_part<true>, dim3((unsigned)waves), dim3(64), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(k_part<false>, dim3((unsigned)waves), dim3(64), 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -876,6 +1084,8 @@ __global__ __launch_bounds__(64) void k_part_g(const GroupDev *G, const int2 *ma
     a.khat = g.khat; a.koff = g.koff; a.yhat = g.yhat;
     a.cbuf = g.cbuf; a.sbuf = g.sbuf; a.K = g.K; a.k = g.k; a.src = g.src; a.Yh = g.Yh;
     a.lab = g.lab; a.lab_row = g.lab_row; a.compat = g.compat;
+    a.nitems = 2 * (int64_t)g.npairs;
+    a.flat = 0;   // one item per wave (the map names it)
     if (g.lab16) part_dispatch<true>(a, m.y, tile);
     else part_dispatch<false>(a, m.y, tile);
 }
