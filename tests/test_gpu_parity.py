@@ -113,6 +113,41 @@ def test_microarray_subset_allpairs(micx):
     assert (np.abs(got[:, 3] - want[:, 3]) < 1e-9).all()
 
 
+@pytest.mark.parametrize("form", ["fp64", "dp32"])
+def test_partition_waves_of_several_items(micx, form):
+    """22 to 64 row counts: a partition wave serves up to four items (26 row
+    counts at n = 800, alpha 0.6), the last wave ragged; ties, monotone and
+    noisy relations among the pairs."""
+    import torch
+    _log("case several items per partition wave (%s)" % form)
+    rng = np.random.default_rng(23)
+    n, m = 800, 9
+    base = rng.uniform(0.0, 1.0, n)
+    X = np.stack([base,
+                  np.sin(6.0 * base) + rng.normal(0.0, 0.1, n),
+                  np.round(rng.uniform(0.0, 1.0, n) * 30.0) / 30.0,
+                  base ** 2,
+                  np.floor(rng.uniform(0.0, 6.0, n)),
+                  rng.normal(0.0, 1.0, n),
+                  np.abs(base - 0.5) + rng.normal(0.0, 0.05, n),
+                  rng.uniform(0.0, 1.0, n),
+                  np.round(base * 10.0)]).astype(np.float64)
+    B = oracle.grid_bound(n, 0.6)
+    assert 22 <= B // 2 - 1 <= 31, B
+    assert (m * (m - 1) * (B // 2 - 1)) % 64 != 0   # the last wave is ragged
+    mode = micx.MODE_DP32 if form == "dp32" else micx.MODE_FP64
+    got = micx.allpairs(torch.from_numpy(X).cuda(), 0.6, 15, mode=mode).cpu().numpy()
+    want = oracle.allpairs(X, 0.6, 15)
+    tol = TOL
+    if form == "dp32":
+        bound, nfx, _ = _bound(micx)
+        assert nfx > 0
+        tol = min(TOL, bound + 1e-12)
+    d = np.abs(got[:, :3] - want[:, :3]).max()
+    assert d <= tol, (d, tol)
+    assert (np.abs(got[:, 3] - want[:, 3]) < 1e-9).all()
+
+
 def test_counts_int32_pairs(micx):
     import torch
     _log("case counts int32 subset")
