@@ -375,9 +375,10 @@ __device__ __forceinline__ void part_body(const PartArgs &a, int w, unsigned cha
 // (22 <= NY <= 64: at most four items per wave).  Each lane follows its own
 // item's tie groups.  A tile row holds, per item of the wave, the 16-byte
 // chunks of that item's row of labels that cover its row counts in the wave
-// (at most 64 + 4 x 7 labels, 184 bytes); a lane reads its label at its own
-// column.  Rows are 13 x 16 bytes apart (the 16-byte writes of neighbouring
-// lanes fall in different banks).
+// (at most 12 chunks, 192 bytes: a chunk per 8 row counts, plus one per item
+// for a slice that starts or ends inside a chunk); a lane reads its label at
+// its own column.  Rows are 13 x 16 bytes apart (the 16-byte writes of
+// neighbouring lanes fall in different banks).
 constexpr int PART_FSTRIDE = 208;
 constexpr int PART_FSLOTS = 4;
 
