@@ -477,7 +477,12 @@ __global__ __launch_bounds__((CO && sizeof(V) == 4) ? 512 : 256) void k_dp(DpArg
                 const int nl = min(NL, x - l0);
                 const int nlp = (nl + PK - 1) / PK * PK;
                 pass++;
-                for (int c0 = 0; c0 < K; c0 += 64 * T) {
+                // chunks of 64 T targets; one wave per item puts the partial
+                // chunk first (targets 1..r), so that its idle lanes meet no
+                // earlier-chunk sources (cooperative passes keep aligned chunks,
+                // which their chunk flags index)
+                const int first = CO ? 64 * T : K - (K - 1) / (64 * T) * (64 * T);
+                for (int c0 = 0, cend = min(first, K); c0 < K; c0 = cend, cend = min(cend + 64 * T, K)) {
                     if (CO && (c0 / (64 * T)) % wpb != wv) continue;   // another wave's chunk
                     int tt[T], et[T];
                     int Nt[T][YR > 0 ? YR : 1];
@@ -485,7 +490,7 @@ __global__ __launch_bounds__((CO && sizeof(V) == 4) ? 512 : 256) void k_dp(DpArg
     #pragma unroll
                     for (int j = 0; j < T; j++) {
                         tt[j] = c0 + 64 * j + lane + 1;
-                        const int tc = tt[j] <= K ? tt[j] : K;
+                        const int tc = tt[j] <= cend ? tt[j] : cend;
                         const int *rt = rec + tc * RS;
                         et[j] = rt[0] + lbase;
                         V h0 = LA(et[j]);
@@ -538,7 +543,7 @@ __global__ __launch_bounds__((CO && sizeof(V) == 4) ? 512 : 256) void k_dp(DpArg
                             }
                         } else {
     #pragma unroll
-                            for (int j = 0; j < T; j++) out[j] = hcost(s, tt[j] <= K ? tt[j] : K);
+                            for (int j = 0; j < T; j++) out[j] = hcost(s, tt[j] <= cend ? tt[j] : cend);
                         }
                     };
                     // sources of earlier chunks, SB at a time through LDS.  The
@@ -609,7 +614,7 @@ __global__ __launch_bounds__((CO && sizeof(V) == 4) ? 512 : 256) void k_dp(DpArg
                     for (int jo = 0; jo < T; jo++) {
                         const int sbeg = c0 + 64 * jo + 1;
                         // the chunk's last target is no source for any target of this chunk
-                        const int send = min(c0 + 64 * jo + 64, min(c0 + 64 * T, K) - 1);
+                        const int send = min(c0 + 64 * jo + 64, cend - 1);
                         V hs[T], hn[T];
                         if (sbeg <= send) hsrc(sbeg, hs);
                         for (int s = sbeg; s <= send; s++) {
@@ -636,7 +641,7 @@ __global__ __launch_bounds__((CO && sizeof(V) == 4) ? 512 : 256) void k_dp(DpArg
                     // the chunk's layers become sources for later chunks
     #pragma unroll
                     for (int j = 0; j < T; j++) {
-                        if (tt[j] <= K) {
+                        if (tt[j] <= cend) {
                             if (l0 == 2) G[(size_t)KS + tt[j]] = gprev[j];
     #pragma unroll
                             for (int q = 0; q < NLP; q++)
