@@ -661,7 +661,8 @@ hipError_t launch_pearson(const void *X, int dtype, int m, int n, PairSource ps,
 }
 
 // ------------------------------------------------------------------ k_stats
-// Characteristic matrix and statistics of one pair per thread.
+// Characteristic matrix and statistics of a pair (one pair per thread in the
+// batch-stream kernels, one per wavefront in k_stats).
 // M_{x,y} (x bins of the first variable, y of the second) is the larger of
 // the orientation scores for that grid shape: first variable optimised into
 // x columns with the second equipartitioned into y rows, or the second
@@ -787,13 +788,103 @@ __device__ __forceinline__ void stats_body(const StatsArgs &a, int pl) {
     }
 }
 
-__global__ void k_stats(StatsArgs a) {
+// The same statistics with one pair per wavefront (the pair calls): the lanes
+// take a row's cells, so that the pair's entries are read in runs rather than
+// 64 pairs' rows at once, and the four statistics and the near-tie products
+// are wave reductions (maxima and minima: exact in any order).
+__device__ __forceinline__ double wave_fmax(double v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_fmin(double v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = fmin(v, __shfl_xor(v, d, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_imin(int v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = min(v, __shfl_xor(v, d, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_imax(int v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+__device__ __forceinline__ void stats_wave(const StatsArgs &a, int pl, int lane) {
+    const double *A0 = a.A + (size_t)(2 * pl) * a.ASUM;
+    const double *A1 = a.A + (size_t)(2 * pl + 1) * a.ASUM;
+    const int Bh = a.B / 2;
+    const bool ci = (a.compat & MICX_COMPAT_COMBINE_INDEX) != 0;
+    auto Mxy = [&](int xx, int yy) -> double {
+        return fmax(A0[a.aoff[yy - 2] + xx - 2], ci ? A1[a.aoff[yy - 2] + xx - 2] : A1[a.aoff[xx - 2] + yy - 2]);
+    };
+    // cells (xx, yy), xx * yy <= B: row yy holds xx = 2..B/yy
+    double mic = 0.0, mas = 0.0, mev = 0.0;
+    for (int yy = 2; yy <= Bh; yy++)
+        for (int xx = 2 + lane; xx <= a.B / yy; xx += 64) {
+            const double v = Mxy(xx, yy);
+            mic = fmax(mic, v);
+            mas = fmax(mas, fabs(v - Mxy(yy, xx)));
+            if (xx == 2 || yy == 2) mev = fmax(mev, v);
+        }
+    mic = wave_fmax(mic);
+    mas = wave_fmax(mas);
+    mev = wave_fmax(mev);
+    // MCN over the cells that reach MIC; the near-tie band of the 32-bit form
+    // (the rule of stats_body)
+    const double band = a.rc.band, lo = mic - band;
+    double mcn = INFINITY;
+    int pmin = 0x7fffffff, pmax = 0;
+    for (int yy = 2; yy <= Bh; yy++)
+        for (int xx = 2 + lane; xx <= a.B / yy; xx += 64) {
+            const double v = Mxy(xx, yy);
+            if (v >= mic - 1e-12) mcn = fmin(mcn, log2((double)(xx * yy)));
+            if (band > 0.0 && v >= lo) {
+                pmin = min(pmin, xx * yy);
+                pmax = max(pmax, xx * yy);
+            }
+        }
+    mcn = wave_fmin(mcn);
+    if (band > 0.0) {
+        pmin = wave_imin(pmin);
+        pmax = wave_imax(pmax);
+        if (pmin != pmax) {
+            if (lane == 0) a.rc.plist[atomicAdd(a.rc.pcount, 1)] = pl;
+            for (int yy = 2; yy <= Bh; yy++)
+                for (int xx = 2 + lane; xx <= a.B / yy; xx += 64)
+                    if (Mxy(xx, yy) >= lo) {
+                        queue_item(a.rc, 2 * pl, yy - 2);
+                        queue_item(a.rc, 2 * pl + 1, (ci ? yy : xx) - 2);
+                    }
+        }
+    }
+    if (lane == 0) {
+        double *o = a.out + (size_t)4 * pl;
+        o[0] = mic; o[1] = mas; o[2] = mev; o[3] = mcn;
+    }
+    if (a.M) {
+        const int W = a.W;
+        for (int q = lane; q < W * W; q += 64) {
+            const int r = q / W + 2, cc = q % W + 2;
+            const bool ok = r * cc <= a.B;
+            a.M[q] = ok ? Mxy(cc, r) : NAN;
+            a.Axy[q] = ok ? A0[a.aoff[r - 2] + cc - 2] : NAN;
+            a.Ayx[q] = ok ? A1[a.aoff[r - 2] + cc - 2] : NAN;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_stats(StatsArgs a) {
     if (a.status && *a.status) return;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (a.plist) {
-        if (k < min(*a.pcount, a.npairs)) stats_body(a, a.plist[k]);
+        if (k < min(*a.pcount, a.npairs)) stats_wave(a, a.plist[k], lane);
     } else if (k < a.npairs) {
-        stats_body(a, k);
+        stats_wave(a, k, lane);
     }
 }
 
@@ -919,7 +1010,7 @@ hipError_t launch_stats(const Geometry &g, int npairs, const ItemBuffers &ib, do
     a.rc = flag ? *flag : Recheck();
     a.plist = plist; a.pcount = pcount; a.status = status;
     a.srq = nullptr; a.grp = nullptr; a.gi = 0;
-    hipLaunchKernelGGL(k_stats, dim3((npairs + 127) / 128), dim3(128), 0, s, a);
+    hipLaunchKernelGGL(k_stats, dim3((npairs + 3) / 4), dim3(256), 0, s, a);   // one pair per wavefront
     return hipGetLastError();
 }
 
