@@ -243,7 +243,7 @@ void make_geometry(int n, int B, double c, HostGeometry &hg, int compat = 0) {
         hg.khat[yi] = kh;
         hg.koff[yi] = ks;
         hg.aoff[yi] = as;
-        ks += kh;
+        ks += end_slots(kh);
         as += x - 1;
         kmax = std::max(kmax, kh);
         kymax = std::max(kymax, (kh + 1) * y);

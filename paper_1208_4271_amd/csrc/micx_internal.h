@@ -122,6 +122,12 @@ struct PairSource {
     int m = 0;
 };
 
+// End slots of one row count inside a (pair, orientation)'s clump and
+// superclump end buffers: khat rounded up to a multiple of four, so that every
+// item's buffer starts on 16 bytes and the partition kernel can store its
+// ends four at a time.
+__host__ __device__ constexpr int end_slots(int khat) { return (khat + 3) & ~3; }
+
 // Ints per superclump record of the DP's count table: e_t, then the rows'
 // cumulative counts.  YR rows when the kernel keeps them in registers, else
 // all y rows.  Padded to a multiple of four so that a record reads as 16-byte

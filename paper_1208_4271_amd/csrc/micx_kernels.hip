@@ -86,7 +86,7 @@ __global__ void k_geometry(int n, int B, double c, int compat, int NY, int *geo)
         geo[NY + yi] = kh;
         geo[2 * NY + yi] = ks;
         geo[3 * NY + yi] = as;
-        ks += kh;
+        ks += end_slots(kh);
         as += x - 1;
     }
 }
@@ -429,13 +429,27 @@ __device__ __forceinline__ void part_body_flat(const PartArgs &a, int w, unsigne
     int last = -2;
     int cstart = 0, k = 0;
     int sa = 0, sP0 = 0, sR = n, sL = kh, sr = 0;
+    // the last four clump and superclump ends, stored four at a time (16-byte
+    // aligned: the buffers hold end_slots(khat) ints per row count); the rest
+    // is stored at the end
+    int cq0 = 0, cq1 = 0, cq2 = 0, cq3 = 0, sq0 = 0, sq1 = 0, sq2 = 0, sq3 = 0;
 
     auto emit_clump = [&](bool e, int ce) {
         const int size = ce - cstart;
         k += e ? 1 : 0;
-        if (e & act & (k <= kh)) cb[k - 1] = ce;
+        const bool cpush = e & (k <= kh);
+        cq0 = cpush ? cq1 : cq0;
+        cq1 = cpush ? cq2 : cq1;
+        cq2 = cpush ? cq3 : cq2;
+        cq3 = cpush ? ce : cq3;
+        if (cpush & act & ((k & 3) == 0)) *(int4 *)(cb + k - 4) = make_int4(cq0, cq1, cq2, cq3);
         const bool sup = e & (sa != 0) & closes_row_t<DINT>(sa, size, sR, sL, STRICT);
-        if (sup & act) sb[sr] = sP0 + sa;
+        const int se = sP0 + sa;
+        sq0 = sup ? sq1 : sq0;
+        sq1 = sup ? sq2 : sq1;
+        sq2 = sup ? sq3 : sq2;
+        sq3 = sup ? se : sq3;
+        if (sup & act & (((sr + 1) & 3) == 0)) *(int4 *)(sb + sr - 3) = make_int4(sq0, sq1, sq2, sq3);
         sr += sup ? 1 : 0;
         sP0 += sup ? sa : 0;
         sa = sup ? 0 : sa;
@@ -536,6 +550,14 @@ __device__ __forceinline__ void part_body_flat(const PartArgs &a, int w, unsigne
     close_group_if(true);
     emit_clump(true, n);
     if (act) {
+        // the ends still queued: the last (count mod 4) of each buffer
+        const int kc = min(k, kh), rc = kc & 3, rs = sr & 3;
+        if (rc >= 1) cb[kc - 1] = cq3;
+        if (rc >= 2) cb[kc - 2] = cq2;
+        if (rc >= 3) cb[kc - 3] = cq1;
+        if (rs >= 1) sb[sr - 1] = sq3;
+        if (rs >= 2) sb[sr - 2] = sq2;
+        if (rs >= 3) sb[sr - 3] = sq1;
         sb[sr] = n;
         const size_t it = (size_t)po * NY + yi;
         a.k[it] = k;

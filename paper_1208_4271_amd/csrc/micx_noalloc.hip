@@ -102,7 +102,7 @@ extern "C" int micx_score_noalloc(micx_ctx *ctx, const void *x_dev, const void *
         int kh = kd >= (double)n ? n : (int)kd;
         if (kh < 1) kh = 1;
         khat[yi] = kh;
-        KSUM += kh;
+        KSUM += end_slots(kh);
         ASUM += x - 1;
     }
     g.KSUM = KSUM;
