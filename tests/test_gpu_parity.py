@@ -71,6 +71,12 @@ def _integer_stage_cases():
     cases.append(("ties_c2", x, y, 0.6, 2.0))
     x = rng.uniform(0, 1, 777)
     cases.append(("sine_c5", x, np.sin(9 * x) + rng.normal(0, 0.2, 777), 0.7, 5.0))
+    # 43 row counts (several items per partition wave) with c = 40: the items'
+    # end counts take every remainder mod 4 for clump ends and for superclump
+    # ends, the partition kernel's tails of four-at-a-time stores
+    r2 = np.random.default_rng(23)
+    x = r2.uniform(0, 1, 600)
+    cases.append(("flat_c40", x, np.sin(6 * x) + r2.normal(0, 0.3, 600), 0.7, 40.0))
     return cases
 
 
@@ -79,6 +85,7 @@ def test_integer_stages_bit_exact(micx, case):
     name, x, y, alpha, c = case
     _log("case integer stages %s" % name)
     B = oracle.grid_bound(len(x), alpha)
+    tails = {0: set(), 1: set()}   # K mod 4 of items ending in clumps (0) / superclumps (1)
     for orient in (0, 1):
         for ry in range(2, B // 2 + 1):
             g = micx.debug_item(x, y, alpha, c, orient, ry)
@@ -87,6 +94,9 @@ def test_integer_stages_bit_exact(micx, case):
             assert np.array_equal(g["row_starts"], w["row_starts"]), (orient, ry)
             assert g["k"] == w["k"] and g["K"] == w["K"], (orient, ry, g["k"], w["k"], g["K"], w["K"])
             assert np.array_equal(g["ends"], w["ends"]), (orient, ry)
+            tails[0 if w["k"] <= int(np.floor(c * (B // ry))) else 1].add(w["K"] % 4)
+    if name == "flat_c40":
+        assert tails[0] == tails[1] == {0, 1, 2, 3}, tails
 
 
 def test_relations_allpairs(micx):
